@@ -1,0 +1,145 @@
+// Full linear convolution y[t] = sum_{j<K} g[j] x[t-j] on the vector ALUs,
+// one stream per blockIdx.y, for int64 words (entangled or widened plain
+// streams, modulo 2^64) and for raw int32 streams (exact int64 results).
+//
+// A block owns kTile consecutive outputs. For each chunk of up to kKC taps
+// it stages the input window the chunk touches, zero-padded outside
+// [0, n), in LDS together with the taps, then every lane accumulates kQ
+// outputs spaced kBlock apart, so that consecutive lanes read consecutive
+// LDS words (no bank conflicts) and the tap is a broadcast.
+//
+// int64 x int32 products modulo 2^64 without a 64x64 multiply: with
+// x = xh 2^32 + xl (xl unsigned) and g = gu - 2^32 [g < 0] (gu = g mod 2^32),
+//     x g = xl gu + 2^32 (xh gu - xl [g < 0])          (mod 2^64),
+// so each tap costs one 32x32->64 multiply-add into a 64-bit accumulator
+// and one 32-bit multiply-add into a second accumulator that only needs to
+// be right modulo 2^32; the two are combined once per output.
+#include "ne_internal.h"
+
+namespace ne {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kQ = 4;
+constexpr int kTile = kBlock * kQ;
+constexpr int kKC = 1024;
+
+struct ConvArgsI64 {
+    PtrsCI64 x;
+    PtrsI64 y;
+    const int32_t *g;
+    int64_t n, K, n_out;
+};
+
+struct ConvArgsI32 {
+    PtrsI32 x;
+    PtrsI64 y;
+    const int32_t *g;
+    int64_t n, K, n_out;
+};
+
+__global__ __launch_bounds__(kBlock) void k_conv_i64(ConvArgsI64 a)
+{
+    __shared__ uint32_t sxl[kTile + kKC];
+    __shared__ uint32_t sxh[kTile + kKC];
+    __shared__ int32_t sg[kKC];
+    const int tid = threadIdx.x;
+    const int64_t *x = a.x.p[blockIdx.y];
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
+    uint64_t lo[kQ];
+    uint32_t hi[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        lo[q] = 0;
+        hi[q] = 0;
+    }
+    for (int64_t j0 = 0; j0 < a.K; j0 += kKC) {
+        const int kc = (int)((a.K - j0) < kKC ? (a.K - j0) : kKC);
+        const int64_t wbase = t0 - j0 - (kc - 1);
+        const int wlen = kTile + kc - 1;
+        __syncthreads();
+        for (int w = tid; w < wlen; w += kBlock) {
+            const int64_t idx = wbase + w;
+            const uint64_t v = (idx >= 0 && idx < a.n) ? (uint64_t)x[idx] : 0;
+            sxl[w] = (uint32_t)v;
+            sxh[w] = (uint32_t)(v >> 32);
+        }
+        for (int j = tid; j < kc; j += kBlock) sg[j] = a.g[j0 + j];
+        __syncthreads();
+        for (int j = 0; j < kc; ++j) {
+            const int32_t gj = sg[j];
+            const uint32_t gu = (uint32_t)gj;
+            const uint32_t gs = (uint32_t)(gj >> 31);
+            const int wb = tid + kc - 1 - j;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const uint32_t xl = sxl[wb + q * kBlock];
+                const uint32_t xh = sxh[wb + q * kBlock];
+                lo[q] += (uint64_t)xl * gu;
+                hi[q] += xh * gu - (xl & gs);
+            }
+        }
+    }
+    int64_t *y = a.y.p[blockIdx.y];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int64_t t = t0 + q * kBlock + tid;
+        if (t < a.n_out) y[t] = (int64_t)(lo[q] + ((uint64_t)hi[q] << 32));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_conv_i32(ConvArgsI32 a)
+{
+    __shared__ int32_t sx[kTile + kKC];
+    __shared__ int32_t sg[kKC];
+    const int tid = threadIdx.x;
+    const int32_t *x = a.x.p[blockIdx.y];
+    const int64_t t0 = (int64_t)blockIdx.x * kTile;
+    int64_t acc[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) acc[q] = 0;
+    for (int64_t j0 = 0; j0 < a.K; j0 += kKC) {
+        const int kc = (int)((a.K - j0) < kKC ? (a.K - j0) : kKC);
+        const int64_t wbase = t0 - j0 - (kc - 1);
+        const int wlen = kTile + kc - 1;
+        __syncthreads();
+        for (int w = tid; w < wlen; w += kBlock) {
+            const int64_t idx = wbase + w;
+            sx[w] = (idx >= 0 && idx < a.n) ? x[idx] : 0;
+        }
+        for (int j = tid; j < kc; j += kBlock) sg[j] = a.g[j0 + j];
+        __syncthreads();
+        for (int j = 0; j < kc; ++j) {
+            const int64_t gj = sg[j];
+            const int wb = tid + kc - 1 - j;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) acc[q] += (int64_t)sx[wb + q * kBlock] * gj;
+        }
+    }
+    int64_t *y = a.y.p[blockIdx.y];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int64_t t = t0 + q * kBlock + tid;
+        if (t < a.n_out) y[t] = acc[q];
+    }
+}
+
+}  // namespace
+
+void launch_conv_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
+                     const PtrsI64 &y, hipStream_t s)
+{
+    ConvArgsI64 a{x, y, g, n, K, n + K - 1};
+    const int64_t tiles = (a.n_out + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_conv_i64, dim3((unsigned)tiles, count), dim3(kBlock), 0, s, a);
+}
+
+void launch_conv_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
+                     const PtrsI64 &y, hipStream_t s)
+{
+    ConvArgsI32 a{x, y, g, n, K, n + K - 1};
+    const int64_t tiles = (a.n_out + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_conv_i32, dim3((unsigned)tiles, count), dim3(kBlock), 0, s, a);
+}
+
+}  // namespace ne

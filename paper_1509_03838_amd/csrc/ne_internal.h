@@ -1,0 +1,78 @@
+// Private declarations shared by the translation units of libne.
+// Kernel argument blocks are passed by value in the kernarg segment; every
+// pointer table is indexed either with compile-time indices (templated
+// kernels) or with wave-uniform indices, so none of them is copied to
+// scratch memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ne.h"
+
+namespace ne {
+
+constexpr int kMaxM = NE_MAX_M;
+
+struct PtrsI32 {
+    const int32_t *p[kMaxM];
+};
+struct PtrsCI64 {
+    const int64_t *p[kMaxM];
+};
+struct PtrsI64 {
+    int64_t *p[kMaxM];
+};
+
+// Records a failed HIP call for ne_last_hip_error() and returns NE_EHIP.
+ne_status hip_fail(hipError_t e);
+// Checks hipGetLastError() after a launch.
+ne_status launch_status();
+
+// ------------------------------------------------------------- launchers
+// All launchers assume validated arguments (the C-ABI layer checks them).
+
+// eps_m = c_m + 2^l c_{m-1}; M in [3, kMaxM].
+void launch_entangle(int M, int l, int64_t n, const PtrsI32 &c, const PtrsI64 &eps,
+                     hipStream_t s);
+void launch_entangle_inplace(int M, int l, int64_t n, const PtrsI64 &x, hipStream_t s);
+void launch_entangle_operand(int l, int64_t n, const int32_t *g, int64_t *g_ent,
+                             hipStream_t s);
+
+// Recovery. `in` holds the M-1 available entangled outputs in the order
+// delta_{r+1}, ..., delta_{r+M-1} (indices mod M); `out` receives
+// d_{r+1}, ..., d_{r+M-1}, d_r in that order.
+void launch_extract(int M, int l, int64_t n, const PtrsCI64 &in, const PtrsI64 &out,
+                    hipStream_t s);
+
+// Element-wise LSB operations on `count` int64 streams (already compacted to
+// the active ones).
+void launch_scale_i64(int count, int64_t n, const PtrsCI64 &x, int64_t s_val, const PtrsI64 &y,
+                      hipStream_t s);
+void launch_add_i64(int count, int64_t n, const PtrsCI64 &x, const int64_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_perm_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *p, const PtrsI64 &y,
+                     hipStream_t s);
+void launch_inner_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,
+                      hipStream_t s);
+void launch_conv_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
+                     const PtrsI64 &y, hipStream_t s);
+
+// The same operations on raw int32 streams with int64 results.
+void launch_scale_i32(int count, int64_t n, const PtrsI32 &x, int64_t s_val, const PtrsI64 &y,
+                      hipStream_t s);
+void launch_add_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_perm_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *p, const PtrsI64 &y,
+                     hipStream_t s);
+void launch_inner_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                      hipStream_t s);
+void launch_conv_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
+                     const PtrsI64 &y, hipStream_t s);
+
+// Checksum method.
+void launch_checksum(int M, int64_t n, const PtrsI32 &c, int64_t *rsum, hipStream_t s);
+void launch_checksum_recover(int count, int64_t n, const PtrsCI64 &d, const int64_t *e,
+                             int64_t *d_r, hipStream_t s);
+
+}  // namespace ne

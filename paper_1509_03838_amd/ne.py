@@ -1,0 +1,205 @@
+"""ctypes binding of libne (include/ne.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library. Tensors must be contiguous device tensors of the stated dtype; the
+binding passes their data pointers and the current HIP stream, and raises
+``NeError`` with the library's status text on any non-zero status. If the
+library has not been built, loading raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libne.so")
+
+CONV, SCALE, ADD, INNER, PERM = 0, 1, 2, 3, 4
+OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM}
+MAX_M = 32
+
+EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_entangle",
+           "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
+           "ne_plain_apply", "ne_checksum", "ne_checksum_recover")
+
+
+class NeError(RuntimeError):
+    def __init__(self, fn: str, status: int, text: str, hip: int = 0):
+        super().__init__(f"{fn}: {text} (status {status}" + (f", hip error {hip})" if hip else ")"))
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_i32, _i64, _u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+
+
+def load() -> ctypes.CDLL:
+    """Load libne.so (built by paper_1509_03838_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing; build it with python -m paper_1509_03838_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "ne_strerror": (ctypes.c_char_p, [_i32]),
+        "ne_last_hip_error": (_i32, []),
+        "ne_version": (_i32, []),
+        "ne_params": (_i32, [_i32, _i32, _P, _P, _P]),
+        "ne_entangle": (_i32, [_i32, _i32, _i64, _P, _P, _P]),
+        "ne_entangle_inplace": (_i32, [_i32, _i32, _i64, _P, _P]),
+        "ne_entangle_operand": (_i32, [_i32, _i64, _P, _P, _P]),
+        "ne_lsb_apply": (_i32, [_i32, _i32, _i64, _P, _P, _i64, _i64, _P, _i64, _u32, _P]),
+        "ne_extract_recover": (_i32, [_i32, _i32, _i64, _P, _i32, _P, _P]),
+        "ne_plain_apply": (_i32, [_i32, _i32, _i64, _P, _P, _i64, _i64, _P, _i64, _P]),
+        "ne_checksum": (_i32, [_i32, _i64, _P, _P, _P]),
+        "ne_checksum_recover": (_i32, [_i32, _i64, _P, _P, _i32, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        L = load()
+        raise NeError(fn, status, L.ne_strerror(status).decode(), L.ne_last_hip_error())
+
+
+def _ptr(t) -> int:
+    """Device address of a tensor, or a raw integer address, or 0 for None."""
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _ptr_array(ts: Sequence) -> ctypes.Array:
+    arr = (ctypes.c_void_p * max(1, len(ts)))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+def _stream(stream) -> int:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dtype(ts, dt, what):
+    for t in ts:
+        if t is not None and not isinstance(t, int) and t.dtype != dt:
+            raise TypeError(f"{what} must be {dt}, got {t.dtype}")
+
+
+def params(M: int, w: int = 64) -> tuple[int, int, int]:
+    """(l, k, D) per Table I and eq. (11)/(13)."""
+    l, k, D = _i32(), _i32(), _i64()
+    _check("ne_params", load().ne_params(M, w, ctypes.byref(l), ctypes.byref(k), ctypes.byref(D)))
+    return l.value, k.value, D.value
+
+
+def entangle(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=None):
+    """eps[m] = c[m] + 2^l c[m-1] (int32 -> int64), eq. (14)-(15)."""
+    import torch
+    _dtype(c, torch.int32, "c")
+    _dtype(eps, torch.int64, "eps")
+    if len(c) != len(eps):
+        raise ValueError("c and eps differ in length")
+    n = c[0].numel() if n is None else n
+    _check("ne_entangle", load().ne_entangle(len(c), l, n, _ptr_array(c), _ptr_array(eps),
+                                             _stream(stream)))
+
+
+def entangle_inplace(x: Sequence, l: int, n: int | None = None, stream=None):
+    import torch
+    _dtype(x, torch.int64, "x")
+    n = x[0].numel() if n is None else n
+    _check("ne_entangle_inplace", load().ne_entangle_inplace(len(x), l, n, _ptr_array(x),
+                                                             _stream(stream)))
+
+
+def entangle_operand(g, g_ent, l: int, stream=None):
+    import torch
+    _dtype([g], torch.int32, "g")
+    _dtype([g_ent], torch.int64, "g_ent")
+    _check("ne_entangle_operand", load().ne_entangle_operand(l, g.numel(), _ptr(g), _ptr(g_ent),
+                                                             _stream(stream)))
+
+
+def n_out(op: str, n_in: int, n_operand: int) -> int:
+    if op == "conv":
+        return 0 if n_in == 0 else n_in + n_operand - 1
+    if op == "inner":
+        return 1
+    return n_in
+
+
+def lsb_apply(op: str, eps: Sequence, operand, delta: Sequence, scalar: int = 0,
+              mask: int | None = None, n_in: int | None = None, n_operand: int | None = None,
+              stream=None):
+    """delta[m] = eps[m] op operand for every stream whose mask bit is set."""
+    import torch
+    _dtype(eps, torch.int64, "eps")
+    _dtype(delta, torch.int64, "delta")
+    M = len(eps)
+    if mask is None:
+        mask = (1 << M) - 1
+    if n_in is None:
+        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    if n_operand is None:
+        n_operand = 0 if operand is None or isinstance(operand, int) else operand.numel()
+    no = n_out(op, n_in, n_operand)
+    _check("ne_lsb_apply", load().ne_lsb_apply(OPS[op], M, n_in, _ptr_array(eps), _ptr(operand),
+                                               n_operand, int(scalar), _ptr_array(delta), no,
+                                               mask & 0xFFFFFFFF, _stream(stream)))
+
+
+def extract_recover(delta: Sequence, r: int, dhat: Sequence, l: int, n: int | None = None,
+                    stream=None):
+    """Recover all M outputs without reading delta[r] (eq. (16)-(19))."""
+    import torch
+    _dtype(delta, torch.int64, "delta")
+    _dtype(dhat, torch.int64, "dhat")
+    M = len(dhat)
+    if n is None:
+        n = dhat[0].numel()
+    _check("ne_extract_recover", load().ne_extract_recover(M, l, n, _ptr_array(delta), r,
+                                                           _ptr_array(dhat), _stream(stream)))
+
+
+def plain_apply(op: str, c: Sequence, operand, d: Sequence, scalar: int = 0, stream=None):
+    import torch
+    _dtype(c, torch.int32, "c")
+    _dtype(d, torch.int64, "d")
+    n_in = c[0].numel()
+    n_operand = 0 if operand is None else operand.numel()
+    no = n_out(op, n_in, n_operand)
+    _check("ne_plain_apply", load().ne_plain_apply(OPS[op], len(c), n_in, _ptr_array(c),
+                                                   _ptr(operand), n_operand, int(scalar),
+                                                   _ptr_array(d), no, _stream(stream)))
+
+
+def checksum(c: Sequence, rsum, stream=None):
+    import torch
+    _dtype(c, torch.int32, "c")
+    _dtype([rsum], torch.int64, "rsum")
+    _check("ne_checksum", load().ne_checksum(len(c), c[0].numel(), _ptr_array(c), _ptr(rsum),
+                                             _stream(stream)))
+
+
+def checksum_recover(d: Sequence, e, r: int, d_r, stream=None):
+    import torch
+    _dtype(d, torch.int64, "d")
+    n = e.numel()
+    _check("ne_checksum_recover", load().ne_checksum_recover(len(d), n, _ptr_array(d), _ptr(e), r,
+                                                             _ptr(d_r), _stream(stream)))

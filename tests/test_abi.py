@@ -1,0 +1,111 @@
+"""The C-ABI library loads, exports every symbol include/ne.h declares, and
+its host-only logic (parameters, argument validation) is right. No kernel is
+launched here: every call below returns before enqueueing work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1509_03838_amd import ne
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(ne_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ne.load()
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_symbols()) == set(ne.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strerror(lib):
+    assert lib.ne_version() >= 100
+    assert lib.ne_strerror(0) == b"ok"
+    assert b"index" in lib.ne_strerror(-3)
+
+
+@pytest.mark.parametrize("w", [8, 10, 12, 16, 24, 32, 48, 63, 64])
+def test_params_match_oracle(w):
+    for M in range(3, 33):
+        try:
+            l, k, D = oracle.params(M, w)
+        except oracle.OracleError:  # no (l, k) at all: M - 1 > w
+            l, k, D = 0, 0, 0
+        if D < 1:
+            with pytest.raises(ne.NeError):
+                ne.params(M, w)
+            continue
+        assert ne.params(M, w) == (l, k, D), (M, w)
+
+
+def test_params_rejects(lib):
+    out = ctypes.c_int32()
+    assert lib.ne_params(2, 64, ctypes.byref(out), None, None) == -1
+    assert lib.ne_params(33, 64, ctypes.byref(out), None, None) == -1
+    assert lib.ne_params(3, 65, ctypes.byref(out), None, None) == -1
+    assert lib.ne_params(3, 64, None, None, None) == -1
+
+
+def _ptrs(vals):
+    a = (ctypes.c_void_p * len(vals))()
+    for i, v in enumerate(vals):
+        a[i] = v
+    return a
+
+
+FAKE = 0x100000  # never dereferenced: every call below fails validation first
+
+
+def test_validation_before_launch(lib):
+    p3 = _ptrs([FAKE, FAKE + 64, FAKE + 128])
+    # M < 3 for entanglement
+    assert lib.ne_entangle(2, 22, 10, p3, p3, None) == -1
+    # l out of range
+    assert lib.ne_entangle(3, 0, 10, p3, p3, None) == -1
+    # NULL stream entry
+    assert lib.ne_entangle(3, 22, 10, _ptrs([FAKE, 0, FAKE]), p3, None) == -1
+    # failed index out of range
+    assert lib.ne_extract_recover(3, 22, 10, p3, 3, p3, None) == -3
+    assert lib.ne_extract_recover(3, 22, 10, p3, -2, p3, None) == -3
+    # (M-1) l > 64
+    assert lib.ne_extract_recover(3, 33, 10, p3, 0, p3, None) == -1
+    # NULL among the M-1 streams that recovery reads
+    assert lib.ne_extract_recover(3, 22, 10, _ptrs([FAKE, 0, FAKE]), 0, p3, None) == -1
+    # conv: n_out must be n + K - 1
+    assert lib.ne_lsb_apply(0, 3, 10, p3, FAKE, 4, 0, p3, 12, 7, None) == -1
+    # inner: n_out must be 1
+    assert lib.ne_lsb_apply(3, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -1
+    # unknown op
+    assert lib.ne_lsb_apply(9, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -4
+    # a NULL output for a stream that is computed
+    assert lib.ne_lsb_apply(1, 3, 10, p3, 0, 0, 2, _ptrs([FAKE, 0, FAKE]), 10, 7, None) == -1
+    # checksum recovery: bad index
+    assert lib.ne_checksum_recover(3, 10, p3, FAKE, 3, FAKE, None) == -3
+
+
+def test_empty_inputs_enqueue_nothing(lib):
+    p3 = _ptrs([FAKE, FAKE + 64, FAKE + 128])
+    assert lib.ne_entangle(3, 22, 0, p3, p3, None) == 0
+    assert lib.ne_extract_recover(3, 22, 0, p3, 1, p3, None) == 0
+    assert lib.ne_lsb_apply(0, 3, 0, p3, FAKE, 16, 0, p3, 0, 7, None) == 0
+    # every stream masked off (all lost): nothing to compute
+    assert lib.ne_lsb_apply(1, 3, 10, p3, 0, 0, 2, p3, 10, 0, None) == 0
