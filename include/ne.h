@@ -192,6 +192,103 @@ ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rs
 ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
                               const int64_t *e, int32_t r, int64_t *d_r, ne_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Batched executor: many groups (uneven M, length, operation and operand
+ * size) in a fixed set of fused launches, optionally as one hipGraph.
+ *
+ * In NE_MODE_ENTANGLED each group goes through the whole method in one pass
+ * over HBM: its int32 inputs are read once, entangled on load (eq. (14)-
+ * (15)), the operation runs on every entangled stream (eq. (9); convolution
+ * on the i8 matrix cores with exact digit splitting, the others on the
+ * vector ALUs), and the outputs are recovered from the M-1 streams other
+ * than the lost one (eq. (16)-(19)) before anything is written; only the
+ * recovered int64 outputs reach memory. The lost stream's operation is not
+ * run. When no stream is lost, the redundant stream is checked against the
+ * recovered outputs and a disagreement sets NE_FLAG_MISMATCH.
+ *
+ * The other modes run the baselines on the same machinery: NE_MODE_PLAIN is
+ * the failure-intolerant operation with the fewest digits the declared
+ * input range needs; NE_MODE_PLAIN_SAME the same operation on the datapath
+ * (digit counts) the entangled words need; NE_MODE_CHECKSUM the checksum
+ * method of eq. (3)-(5) (M data streams plus their sum, with recovery of a
+ * lost stream as d_r = e - sum of the others).
+ * ------------------------------------------------------------------------ */
+
+#define NE_FUSED_MAX_M 8
+
+typedef enum ne_mode {
+    NE_MODE_ENTANGLED = 0,
+    NE_MODE_PLAIN = 1,
+    NE_MODE_PLAIN_SAME = 2,
+    NE_MODE_CHECKSUM = 3
+} ne_mode;
+
+/* Device-side error bits (ne_plan_flags). */
+#define NE_FLAG_INPUT_RANGE 1u /* an input or operand value outside in_bits */
+#define NE_FLAG_LIMBS 2u       /* a word needed more digits than planned */
+#define NE_FLAG_MISMATCH 4u    /* redundant stream disagrees with the outputs */
+
+/* One group: M streams of n int32 samples sharing one operand. */
+typedef struct ne_group {
+    int32_t op;          /* ne_op */
+    int32_t M;           /* streams: 3..8 (entangled), 2..8 (checksum), 1..8 */
+    int64_t n;           /* samples per stream (>= 0) */
+    int64_t n_operand;   /* K taps (conv), n (add, inner, perm), 0 (scale) */
+    int64_t scalar;      /* scale factor (NE_OP_SCALE) */
+    int32_t lost;        /* -1, or the stream whose operation is dropped */
+    int32_t in_bits;     /* 1..31 (conv) or 1..32: every sample and operand
+                            value v satisfies -2^(in_bits-1) <= v < 2^(in_bits-1);
+                            violations are flagged (NE_FLAG_INPUT_RANGE) */
+    const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
+    const int32_t *operand;           /* device int32 taps / vector /
+                                         permutation indices; NULL for scale.
+                                         For add, the plain vector g (the
+                                         entangled mode entangles it itself,
+                                         footnote 3). */
+    int64_t *out[NE_FUSED_MAX_M];     /* device outputs, n_out int64 each,
+                                         8-byte aligned, disjoint */
+} ne_group;
+
+typedef struct ne_tuning {
+    int32_t conv_steps;   /* 1024-output steps per convolution block; 0: 4 */
+    int32_t stream_steps; /* positions per lane per element-wise block; 0: 16 */
+} ne_tuning;
+
+typedef struct ne_plan_stats {
+    int64_t groups, items, launches;
+    int64_t in_bytes;     /* int32 input and operand bytes one run must read */
+    int64_t out_bytes;    /* int64 output bytes one run must write */
+    int64_t out_samples;  /* recovered output samples of one run */
+    int64_t macs;         /* useful multiply-adds of one run (conv and inner) */
+    int64_t mfma_macs;    /* i8 multiply-adds issued on the matrix cores */
+    int64_t lds_bytes;    /* largest dynamic LDS of a launch */
+} ne_plan_stats;
+
+typedef struct ne_plan ne_plan;
+
+/*
+ * Validate the groups (host array of n_groups), choose digit counts from
+ * in_bits, check that every group's worst-case output is admissible
+ * (|d| <= D of eq. (11)/(13) in NE_MODE_ENTANGLED, |d| < 2^63 otherwise;
+ * NE_ERANGE if not), build the work items and upload them. Allocates device
+ * memory for the plan only (freed by ne_plan_destroy). The caller keeps
+ * owning every buffer the groups point to; they must stay valid while the
+ * plan is used. tuning may be NULL.
+ */
+ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
+                         const ne_tuning *tuning, ne_plan **plan);
+/* Enqueue one run of the whole batch on `stream`. Allocates nothing. */
+ne_status ne_plan_run(ne_plan *plan, ne_stream stream);
+/* Record one run into a hipGraph (by stream capture on `stream`); later
+ * ne_plan_launch calls replay it as one graph launch. */
+ne_status ne_plan_capture(ne_plan *plan, ne_stream stream);
+/* Launch the captured graph (or enqueue a run if none was captured). */
+ne_status ne_plan_launch(ne_plan *plan, ne_stream stream);
+/* Synchronously read (and optionally clear) the device error bits. */
+ne_status ne_plan_flags(ne_plan *plan, uint32_t *flags, int32_t clear);
+ne_status ne_plan_stats_get(const ne_plan *plan, ne_plan_stats *stats);
+ne_status ne_plan_destroy(ne_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libne.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip"]
+SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "plan.hip"]
 
 # Packed-FP32 instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",

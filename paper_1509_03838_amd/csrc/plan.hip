@@ -1,0 +1,391 @@
+// Batched executor (ne_plan_*): validation, digit-count choice, work-item
+// construction and launch of the fused kernels.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "fused.h"
+#include "ne_internal.h"
+
+namespace ne {
+hipError_t fused_conv_prepare(int cls, int la, int lb, size_t lds);
+void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *items,
+                       uint32_t nitems, uint32_t *flags, size_t lds, hipStream_t s);
+void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
+                         uint32_t *flags, hipStream_t s);
+void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,
+                          uint32_t *flags, hipStream_t s);
+}  // namespace ne
+
+using namespace ne;
+
+struct Bucket {
+    int conv;             // 1: convolution kernel, 0: element-wise kernel
+    int cls, la, lb;
+    size_t lds;
+    uint32_t first, count;  // range in the item array
+};
+
+struct ne_plan {
+    int mode = 0;
+    std::vector<GroupDev> host_groups;
+    std::vector<Bucket> buckets;
+    unsigned char *arena = nullptr;  // device: groups | items | inner idx | acc | flags
+    GroupDev *d_groups = nullptr;
+    Item *d_items = nullptr;
+    uint32_t *d_inner = nullptr;
+    uint32_t n_inner = 0;
+    uint32_t *d_flags = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ne_plan_stats stats{};
+};
+
+namespace {
+
+constexpr int kConvStepsDefault = 4;
+constexpr int kStreamStepsDefault = 16;
+constexpr size_t kMaxLds = 160 * 1024;
+
+// Fewest balanced base-256 digits (each in [-128, 127]) that represent every
+// integer in [-neg, pos]: L digits reach -128 R and 127 R, R = (256^L - 1)/255.
+int digits_for(unsigned __int128 neg, unsigned __int128 pos)
+{
+    unsigned __int128 R = 0, p = 1;
+    for (int L = 1; L <= 16; ++L) {
+        R += p;
+        p *= 256;
+        if (128 * R >= neg && 127 * R >= pos) return L;
+    }
+    return 17;
+}
+
+inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
+                         const ne_tuning *tuning, ne_plan **out_plan)
+{
+    if (!out_plan || n_groups < 0 || (n_groups > 0 && !groups)) return NE_EINVAL;
+    if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
+    *out_plan = nullptr;
+    const int conv_steps = (tuning && tuning->conv_steps > 0) ? tuning->conv_steps : kConvStepsDefault;
+    const int stream_steps =
+        (tuning && tuning->stream_steps > 0) ? tuning->stream_steps : kStreamStepsDefault;
+    if (conv_steps > 4096 || stream_steps > 4096) return NE_EINVAL;
+
+    ne_plan *plan = new (std::nothrow) ne_plan;
+    if (!plan) return NE_ENOMEM;
+    plan->mode = mode;
+    plan->host_groups.resize(n_groups);
+    std::vector<std::vector<Item>> per_group(n_groups);
+    // bucket key -> items
+    std::map<std::tuple<int, int, int, int>, std::vector<Item>> bucket_items;
+    std::map<std::tuple<int, int, int, int>, size_t> bucket_lds;
+    std::vector<uint32_t> inner_groups;
+    ne_plan_stats st{};
+    st.groups = n_groups;
+
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const ne_group &u = groups[gi];
+        GroupDev &G = plan->host_groups[gi];
+        memset(&G, 0, sizeof(G));
+        auto fail = [&](ne_status s) {
+            delete plan;
+            return s;
+        };
+        const int minM = mode == kEntangled ? 3 : (mode == kChecksum ? 2 : 1);
+        if (u.M < minM || u.M > kFusedMaxM || u.n < 0 || u.in_bits < 1 || u.in_bits > 32)
+            return fail(NE_EINVAL);
+        if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
+        if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
+        for (int m = 0; m < u.M; ++m) {
+            if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 8))
+                return fail(NE_EINVAL);
+        }
+        int64_t n_out;
+        switch (u.op) {
+        case NE_OP_CONV:
+            if (u.n_operand < 1 || !u.operand || u.in_bits > 31) return fail(NE_EINVAL);
+            n_out = u.n == 0 ? 0 : u.n + u.n_operand - 1;
+            break;
+        case NE_OP_SCALE: n_out = u.n; break;
+        case NE_OP_INNER: n_out = 1; break;
+        default: n_out = u.n; break;
+        }
+        if (u.op == NE_OP_ADD || u.op == NE_OP_INNER || u.op == NE_OP_PERM) {
+            if (u.n_operand != u.n || (u.n > 0 && !u.operand)) return fail(NE_EINVAL);
+        }
+        if (u.op == NE_OP_PERM && u.n > INT32_MAX) return fail(NE_EUNSUP);
+
+        // Worst-case output magnitude from the declared input range.
+        const unsigned __int128 B = (unsigned __int128)1 << (u.in_bits - 1);
+        unsigned __int128 bound = 0;
+        const unsigned __int128 s_abs =
+            (unsigned __int128)(u.scalar < 0 ? -(__int128)u.scalar : (__int128)u.scalar);
+        switch (u.op) {
+        case NE_OP_CONV: bound = B * B * (unsigned __int128)u.n_operand; break;
+        case NE_OP_SCALE: bound = B * s_abs; break;
+        case NE_OP_ADD: bound = 2 * B; break;
+        case NE_OP_INNER: bound = B * B * (unsigned __int128)(u.n > 0 ? u.n : 1); break;
+        case NE_OP_PERM: bound = B; break;
+        }
+        int l = 0;
+        int64_t D = 0;
+        if (mode == kEntangled) {
+            int32_t ll, kk;
+            if (ne_params(u.M, 64, &ll, &kk, &D) != NE_OK) return fail(NE_ERANGE);
+            l = ll;
+            if (bound > (unsigned __int128)D) return fail(NE_ERANGE);
+        } else {
+            const unsigned __int128 lim = ((unsigned __int128)1 << 63) - 1;
+            const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)u.M : bound;
+            if (chk > lim) return fail(NE_ERANGE);
+        }
+
+        G.op = u.op;
+        G.M = u.M;
+        G.mode = mode;
+        G.lost = u.lost >= 0 ? 1 : 0;
+        G.r = u.lost >= 0 ? u.lost : 0;
+        G.l = l;
+        G.nslots = mode == kChecksum ? u.M + 1 : u.M;
+        G.in_lo = u.in_bits == 32 ? INT32_MIN : -(int32_t)((int64_t)1 << (u.in_bits - 1));
+        G.in_hi = u.in_bits == 32 ? INT32_MAX : (int32_t)(((int64_t)1 << (u.in_bits - 1)) - 1);
+        G.n = u.n;
+        G.K = u.op == NE_OP_CONV ? u.n_operand : 0;
+        G.n_out = n_out;
+        G.scalar = u.scalar;
+        for (int m = 0; m < u.M; ++m) {
+            G.c[m] = u.c[m];
+            G.out[m] = u.out[m];
+        }
+        G.operand = u.operand;
+        const int cls = G.nslots <= 4 ? 0 : 1;
+
+        // Algorithmic traffic and work of one run.
+        st.in_bytes += (int64_t)u.M * u.n * 4 + (u.op == NE_OP_SCALE ? 0 : u.n_operand * 4);
+        st.out_bytes += (int64_t)u.M * n_out * 8;
+        st.out_samples += (int64_t)u.M * n_out;
+        if (u.op == NE_OP_CONV) st.macs += (int64_t)u.M * u.n * u.n_operand;
+        if (u.op == NE_OP_INNER) st.macs += (int64_t)u.M * u.n;
+
+        if (n_out == 0) continue;
+        if (u.op == NE_OP_CONV) {
+            // Digits of the data words: inputs lie in [-B, B-1]; entangled
+            // words c + 2^l c' in (2^l + 1) times that; the checksum stream in
+            // M times that (the same digit count serves every slot).
+            unsigned __int128 neg = B, pos = B - 1;
+            if (mode == kEntangled || mode == kPlainSame) {
+                int32_t ll = 0, kk;
+                int64_t dd;
+                if (ne_params(u.M < 3 ? 3 : u.M, 64, &ll, &kk, &dd) != NE_OK) return fail(NE_ERANGE);
+                const unsigned __int128 f = ((unsigned __int128)1 << ll) + 1;
+                neg *= f;
+                pos *= f;
+            } else if (mode == kChecksum) {
+                neg *= (unsigned)u.M;
+                pos *= (unsigned)u.M;
+            }
+            const int la = digits_for(neg, pos), lb = digits_for(B, B - 1);
+            if (la > kLimbsA || lb > kLimbsB) return fail(NE_EUNSUP);
+            G.la = la;
+            G.lb = lb;
+            G.nch = (int)((u.n_operand + 15 + 63) / 64);
+            G.kp = 64 * G.nch - 16;
+            G.wlen = kConvTile + G.kp;
+            G.steps = conv_steps;
+            // int32 accumulation: a digit product is at most 2^14, summed over
+            // 64 nch inputs and at most min(la, lb) digit pairs per shift.
+            if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
+                return fail(NE_EUNSUP);
+            const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
+            const size_t lds = (size_t)G.nch * lb * 1024 + (size_t)nplanes * la * G.wlen;
+            if (lds > kMaxLds) return fail(NE_EUNSUP);
+            const int64_t strip = (int64_t)conv_steps * kConvTile;
+            const int64_t nstrips = (n_out + strip - 1) / strip;
+            auto key = std::make_tuple(1, cls, la, lb);
+            auto &v = bucket_items[key];
+            for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
+            bucket_lds[key] = std::max(bucket_lds[key], lds);
+            const int64_t slots_run = G.nslots - G.lost;
+            st.mfma_macs += slots_run * nstrips * conv_steps * (int64_t)kConvTile * 64 * G.nch *
+                            la * lb;
+        } else {
+            G.steps = stream_steps;
+            const int64_t strip = (int64_t)stream_steps * 256;
+            const int64_t nstrips = (u.n + strip - 1) / strip;
+            auto key = std::make_tuple(0, cls, 0, 0);
+            auto &v = bucket_items[key];
+            for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
+            if (u.op == NE_OP_INNER) inner_groups.push_back((uint32_t)gi);
+        }
+    }
+
+    // Flatten buckets; items of a bucket keep group order, strips ascending.
+    std::vector<Item> all_items;
+    for (auto &kv : bucket_items) {
+        Bucket b{};
+        b.conv = std::get<0>(kv.first);
+        b.cls = std::get<1>(kv.first);
+        b.la = std::get<2>(kv.first);
+        b.lb = std::get<3>(kv.first);
+        b.lds = b.conv ? bucket_lds[kv.first] : 0;
+        b.first = (uint32_t)all_items.size();
+        b.count = (uint32_t)kv.second.size();
+        all_items.insert(all_items.end(), kv.second.begin(), kv.second.end());
+        plan->buckets.push_back(b);
+        if (b.conv && b.lds > 64 * 1024) {
+            hipError_t e = fused_conv_prepare(b.cls, b.la, b.lb, b.lds);
+            if (e != hipSuccess) {
+                delete plan;
+                return hip_fail(e);
+            }
+        }
+        st.lds_bytes = std::max<int64_t>(st.lds_bytes, (int64_t)b.lds);
+    }
+    plan->n_inner = (uint32_t)inner_groups.size();
+    st.items = (int64_t)all_items.size();
+    st.launches = (int64_t)plan->buckets.size() + (plan->n_inner ? 1 : 0);
+
+    // One device arena: groups | items | inner index | accumulators | flags.
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t sz_groups = up(sizeof(GroupDev) * std::max(1, n_groups));
+    const size_t sz_items = up(sizeof(Item) * std::max<size_t>(1, all_items.size()));
+    const size_t sz_inner = up(sizeof(uint32_t) * std::max<size_t>(1, inner_groups.size()));
+    const size_t sz_acc = up(sizeof(uint64_t) * kMaxSlots * std::max<size_t>(1, inner_groups.size()));
+    const size_t sz_flags = 256;
+    const size_t total = sz_groups + sz_items + sz_inner + sz_acc + sz_flags;
+    hipError_t e = hipMalloc((void **)&plan->arena, total);
+    if (e != hipSuccess) {
+        delete plan;
+        (void)hipGetLastError();
+        return NE_ENOMEM;
+    }
+    unsigned char *p = plan->arena;
+    plan->d_groups = (GroupDev *)p;
+    p += sz_groups;
+    plan->d_items = (Item *)p;
+    p += sz_items;
+    plan->d_inner = (uint32_t *)p;
+    p += sz_inner;
+    uint64_t *d_acc = (uint64_t *)p;
+    p += sz_acc;
+    plan->d_flags = (uint32_t *)p;
+    for (size_t i = 0; i < inner_groups.size(); ++i)
+        plan->host_groups[inner_groups[i]].acc = d_acc + kMaxSlots * i;
+
+    std::vector<unsigned char> zeros(sz_acc + sz_flags, 0);
+    e = hipMemcpy(plan->d_groups, plan->host_groups.data(), sizeof(GroupDev) * n_groups,
+                  hipMemcpyHostToDevice);
+    if (e == hipSuccess && !all_items.empty())
+        e = hipMemcpy(plan->d_items, all_items.data(), sizeof(Item) * all_items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !inner_groups.empty())
+        e = hipMemcpy(plan->d_inner, inner_groups.data(), sizeof(uint32_t) * inner_groups.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_acc, zeros.data(), sz_acc + sz_flags, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ne_plan_destroy(plan);
+        return hip_fail(e);
+    }
+    plan->stats = st;
+    *out_plan = plan;
+    return NE_OK;
+}
+
+ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
+{
+    if (!plan) return NE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    for (const Bucket &b : plan->buckets) {
+        if (b.count == 0) continue;
+        if (b.conv)
+            fused_conv_launch(b.cls, b.la, b.lb, plan->d_groups, plan->d_items + b.first, b.count,
+                              plan->d_flags, b.lds, s);
+        else
+            fused_stream_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count,
+                                plan->d_flags, s);
+    }
+    if (plan->n_inner)
+        fused_inner_finalize(plan->d_groups, plan->d_inner, plan->n_inner, plan->d_flags, s);
+    return launch_status();
+}
+
+ne_status ne_plan_capture(ne_plan *plan, ne_stream stream)
+{
+    if (!plan || !stream) return NE_EINVAL;  // the null stream cannot be captured
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->exec) {
+        (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e);
+    ne_status st = ne_plan_run(plan, stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st != NE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e);
+    }
+    plan->graph = g;
+    return NE_OK;
+}
+
+ne_status ne_plan_launch(ne_plan *plan, ne_stream stream)
+{
+    if (!plan) return NE_EINVAL;
+    if (!plan->exec) return ne_plan_run(plan, stream);
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? NE_OK : hip_fail(e);
+}
+
+ne_status ne_plan_flags(ne_plan *plan, uint32_t *flags, int32_t clear)
+{
+    if (!plan || !flags) return NE_EINVAL;
+    hipError_t e = hipMemcpy(flags, plan->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    if (clear) {
+        const uint32_t z = 0;
+        e = hipMemcpy(plan->d_flags, &z, sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return NE_OK;
+}
+
+ne_status ne_plan_stats_get(const ne_plan *plan, ne_plan_stats *stats)
+{
+    if (!plan || !stats) return NE_EINVAL;
+    *stats = plan->stats;
+    return NE_OK;
+}
+
+ne_status ne_plan_destroy(ne_plan *plan)
+{
+    if (!plan) return NE_OK;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->arena) (void)hipFree(plan->arena);
+    delete plan;
+    return NE_OK;
+}
+
+}  // extern "C"

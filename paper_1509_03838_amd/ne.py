@@ -21,7 +21,32 @@ MAX_M = 32
 
 EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_entangle",
            "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
-           "ne_plain_apply", "ne_checksum", "ne_checksum_recover")
+           "ne_plain_apply", "ne_checksum", "ne_checksum_recover", "ne_plan_create",
+           "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
+           "ne_plan_stats_get", "ne_plan_destroy")
+
+FUSED_MAX_M = 8
+MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
+FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH = 1, 2, 4
+
+
+class GroupC(ctypes.Structure):
+    """struct ne_group"""
+    _fields_ = [("op", ctypes.c_int32), ("M", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("n_operand", ctypes.c_int64), ("scalar", ctypes.c_int64),
+                ("lost", ctypes.c_int32), ("in_bits", ctypes.c_int32),
+                ("c", ctypes.c_void_p * FUSED_MAX_M), ("operand", ctypes.c_void_p),
+                ("out", ctypes.c_void_p * FUSED_MAX_M)]
+
+
+class TuningC(ctypes.Structure):
+    _fields_ = [("conv_steps", ctypes.c_int32), ("stream_steps", ctypes.c_int32)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("groups", "items", "launches", "in_bytes",
+                                               "out_bytes", "out_samples", "macs", "mfma_macs",
+                                               "lds_bytes")]
 
 
 class NeError(RuntimeError):
@@ -56,6 +81,14 @@ def load() -> ctypes.CDLL:
         "ne_plain_apply": (_i32, [_i32, _i32, _i64, _P, _P, _i64, _i64, _P, _i64, _P]),
         "ne_checksum": (_i32, [_i32, _i64, _P, _P, _P]),
         "ne_checksum_recover": (_i32, [_i32, _i64, _P, _P, _i32, _P, _P]),
+        "ne_plan_create": (_i32, [ctypes.POINTER(GroupC), _i32, _i32, ctypes.POINTER(TuningC),
+                                  ctypes.POINTER(ctypes.c_void_p)]),
+        "ne_plan_run": (_i32, [_P, _P]),
+        "ne_plan_capture": (_i32, [_P, _P]),
+        "ne_plan_launch": (_i32, [_P, _P]),
+        "ne_plan_flags": (_i32, [_P, ctypes.POINTER(ctypes.c_uint32), _i32]),
+        "ne_plan_stats_get": (_i32, [_P, ctypes.POINTER(StatsC)]),
+        "ne_plan_destroy": (_i32, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -203,3 +236,81 @@ def checksum_recover(d: Sequence, e, r: int, d_r, stream=None):
     n = e.numel()
     _check("ne_checksum_recover", load().ne_checksum_recover(len(d), n, _ptr_array(d), _ptr(e), r,
                                                              _ptr(d_r), _stream(stream)))
+
+
+class GroupSpec:
+    """One group for a Plan: M int32 input tensors, an int32 operand (or None
+    for scale), M int64 output tensors of n_out elements."""
+
+    def __init__(self, op: str, c: Sequence, operand, out: Sequence, scalar: int = 0,
+                 lost: int = -1, in_bits: int = 32):
+        self.op, self.c, self.operand, self.out = op, list(c), operand, list(out)
+        self.scalar, self.lost, self.in_bits = int(scalar), int(lost), int(in_bits)
+
+    def to_c(self) -> GroupC:
+        import torch
+        _dtype(self.c, torch.int32, "c")
+        _dtype(self.out, torch.int64, "out")
+        if self.operand is not None:
+            _dtype([self.operand], torch.int32, "operand")
+        g = GroupC()
+        g.op = OPS[self.op]
+        g.M = len(self.c)
+        g.n = self.c[0].numel() if self.c else 0
+        g.n_operand = 0 if self.operand is None else self.operand.numel()
+        g.scalar = self.scalar
+        g.lost = self.lost
+        g.in_bits = self.in_bits
+        for m, t in enumerate(self.c):
+            g.c[m] = _ptr(t)
+        for m, t in enumerate(self.out):
+            g.out[m] = _ptr(t)
+        g.operand = _ptr(self.operand) if self.operand is not None else None
+        return g
+
+
+class Plan:
+    """A batched run of many groups (ne_plan_*)."""
+
+    def __init__(self, groups: Sequence[GroupSpec], mode: str = "entangled", conv_steps: int = 0,
+                 stream_steps: int = 0):
+        L = load()
+        self._groups = list(groups)  # keeps the tensors alive
+        arr = (GroupC * max(1, len(self._groups)))()
+        for i, g in enumerate(self._groups):
+            arr[i] = g.to_c()
+        tun = TuningC(conv_steps, stream_steps)
+        h = ctypes.c_void_p()
+        _check("ne_plan_create", L.ne_plan_create(arr, len(self._groups), MODES[mode],
+                                                  ctypes.byref(tun), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check("ne_plan_run", load().ne_plan_run(self._h, _stream(stream)))
+
+    def capture(self, stream):
+        _check("ne_plan_capture", load().ne_plan_capture(self._h, _stream(stream)))
+
+    def launch(self, stream=None):
+        _check("ne_plan_launch", load().ne_plan_launch(self._h, _stream(stream)))
+
+    def flags(self, clear: bool = False) -> int:
+        f = ctypes.c_uint32()
+        _check("ne_plan_flags", load().ne_plan_flags(self._h, ctypes.byref(f), int(clear)))
+        return f.value
+
+    def stats(self) -> dict:
+        st = StatsC()
+        _check("ne_plan_stats_get", load().ne_plan_stats_get(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in StatsC._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().ne_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -109,3 +109,38 @@ def test_empty_inputs_enqueue_nothing(lib):
     assert lib.ne_lsb_apply(0, 3, 0, p3, FAKE, 16, 0, p3, 0, 7, None) == 0
     # every stream masked off (all lost): nothing to compute
     assert lib.ne_lsb_apply(1, 3, 10, p3, 0, 0, 2, p3, 10, 0, None) == 0
+
+
+def _group(**kw):
+    g = ne.GroupC()
+    g.op, g.M, g.n, g.n_operand, g.scalar, g.lost, g.in_bits = 0, 3, 100, 16, 0, -1, 12
+    for m in range(3):
+        g.c[m] = FAKE + 256 * m
+        g.out[m] = FAKE + 4096 + 1024 * m
+    g.operand = FAKE + 8192
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("kw,status", [
+    ({"M": 2}, -1),                      # entangled needs M >= 3
+    ({"M": 9}, -1),                      # above the fused limit
+    ({"lost": 3}, -3),                   # failed index out of range
+    ({"op": 7}, -4),                     # unknown operation
+    ({"n_operand": 0}, -1),              # convolution without taps
+    ({"in_bits": 32}, -1),               # 32-bit convolution operands
+    ({"in_bits": 31, "n_operand": 1 << 20}, -2),  # worst case above D
+])
+def test_plan_validation_before_allocation(lib, kw, status):
+    arr = (ne.GroupC * 1)(_group(**kw))
+    h = ctypes.c_void_p()
+    assert lib.ne_plan_create(arr, 1, 0, None, ctypes.byref(h)) == status
+    assert not h.value
+
+
+def test_plan_rejects_misaligned_inputs(lib):
+    g = _group()
+    g.c[1] = FAKE + 4  # int32 streams must be 16-byte aligned
+    h = ctypes.c_void_p()
+    assert lib.ne_plan_create((ne.GroupC * 1)(g), 1, 0, None, ctypes.byref(h)) == -1

@@ -1,0 +1,200 @@
+"""GPU parity of the batched, fused executor (ne_plan_*): every mode, every
+operation, uneven batches, every single-stream loss, graph replay -- all
+against the CPU oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_03838_amd import ne
+from paper_1509_03838_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+POISON = 0x3C3C3C3C3C3C3C3C
+
+
+def dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+
+
+def host(ts):
+    torch.cuda.synchronize()
+    return np.stack([t.cpu().numpy() for t in ts]) if ts else np.zeros((0, 0), np.int64)
+
+
+class DevGroup:
+    """A workloads.Group on the device with output buffers."""
+
+    def __init__(self, grp: wl.Group, in_bits: int, lost: int = -1, mode: str = "entangled"):
+        self.grp = grp
+        self.c = [dev32(row) for row in grp.c]
+        self.operand = None if grp.op == "scale" else dev32(grp.operand)
+        self.n_out = ne.n_out(grp.op, grp.n, 0 if grp.operand is None else grp.operand.size)
+        self.out = [torch.full((max(self.n_out, 1),), POISON, dtype=torch.int64, device=DEV)[:self.n_out]
+                    for _ in range(grp.M)]
+        self.spec = ne.GroupSpec(grp.op, self.c, self.operand, self.out, grp.scalar, lost, in_bits)
+
+    def result(self):
+        return host(self.out)
+
+    def reference(self):
+        g = self.grp
+        return oracle.apply(g.op, g.c, g.operand if g.op != "scale" else None, g.scalar)
+
+
+def run(groups, mode="entangled", **kw):
+    plan = ne.Plan([g.spec for g in groups], mode, **kw)
+    plan.run()
+    torch.cuda.synchronize()
+    flags = plan.flags()
+    return plan, flags
+
+
+def make(op, M, n, K, bits, seed):
+    g = wl.rng(seed)
+    lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+    c = wl.uniform_i32(g, lo, hi, (M, n))
+    s = 0
+    if op == "conv":
+        operand = wl.uniform_i32(g, lo, hi, K)
+    elif op in ("add", "inner"):
+        operand = wl.uniform_i32(g, lo, hi, n)
+    elif op == "perm":
+        operand = wl.permutation(g, n)
+    else:
+        operand, s = np.zeros(0, np.int32), int(g.integers(lo, hi))
+    return wl.Group(op, c, operand, s)
+
+
+# ------------------------------------------------------------ small config
+
+def test_small_config_every_loss_fused():
+    grp = wl.config_small()
+    ref = oracle.apply("conv", grp.c, grp.operand)
+    for lost in (-1, 0, 1, 2):
+        dg = DevGroup(grp, 8, lost)
+        _, flags = run([dg])
+        assert flags == 0
+        assert np.array_equal(dg.result(), ref), lost
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("M", [3, 4, 5, 8])
+@pytest.mark.parametrize("n,K,bits", [(1, 1, 8), (5, 3, 12), (3001, 37, 12), (4096, 64, 12),
+                                      (5000, 300, 10), (2049, 1024, 16), (1, 1024, 11)])
+def test_conv_modes(mode, M, n, K, bits):
+    grp = make("conv", M, n, K, bits, seed=M * 1000 + n + K)
+    ref = oracle.apply("conv", grp.c, grp.operand)
+    losses = [-1] + list(range(M)) if mode in ("entangled", "checksum") else [-1]
+    for lost in losses:
+        dg = DevGroup(grp, bits, lost, mode)
+        _, flags = run([dg], mode)
+        assert flags == 0, (mode, lost, flags)
+        assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost)
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("op", ["scale", "add", "inner", "perm"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_streaming_ops_modes(mode, op, M):
+    for n in (1, 255, 4097, 70001):
+        grp = make(op, M, n, 0, 10, seed=n * 13 + M + len(op))
+        ref = oracle.apply(op, grp.c, grp.operand if op != "scale" else None, grp.scalar)
+        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+        for lost in losses:
+            dg = DevGroup(grp, 10, lost, mode)
+            _, flags = run([dg], mode)
+            assert flags == 0
+            assert np.array_equal(dg.result(), ref), (mode, op, M, n, lost)
+
+
+def test_uneven_batch_matches_standalone_and_oracle():
+    """Uneven groups (M 3..8, lengths 2^12..2^15, taps 8..512, all five ops)
+    in one plan: each result equals the oracle and its standalone run."""
+    groups = wl.config_uneven(seed=5, groups=40, n_hi=1 << 15)
+    rng = wl.rng(99)
+    devs = [DevGroup(g, 10, int(rng.integers(-1, g.M))) for g in groups]
+    plan, flags = run(devs)
+    assert flags == 0
+    assert plan.stats()["groups"] == 40
+    for dg in devs:
+        ref = dg.reference()
+        assert np.array_equal(dg.result(), ref), (dg.grp.op, dg.grp.M, dg.grp.n)
+    for dg in devs[:6]:
+        alone = DevGroup(dg.grp, 10, dg.spec.lost)
+        run([alone])
+        assert np.array_equal(alone.result(), dg.result())
+
+
+def test_graph_replay_matches_eager():
+    groups = [make("conv", 3, 20000, 64, 12, 1), make("scale", 4, 9000, 0, 12, 2),
+              make("inner", 5, 7777, 0, 12, 3), make("perm", 3, 5000, 0, 12, 4)]
+    devs = [DevGroup(g, 12) for g in groups]
+    plan = ne.Plan([d.spec for d in devs])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(s)
+        for rep in range(4):
+            for d in devs:
+                for t in d.out:
+                    t.fill_(POISON)
+            x = torch.arange(1000, device=DEV).sum()  # unrelated eager work
+            plan.launch(s)
+            s.synchronize()
+            assert int(x) == 499500
+            for d in devs:
+                assert np.array_equal(d.result(), d.reference()), (rep, d.grp.op)
+    assert plan.flags() == 0
+
+
+def test_declared_range_violation_is_flagged():
+    grp = make("conv", 3, 5000, 16, 12, 7)
+    grp.c[1, 100] = 1 << 12   # outside the declared 12 bits
+    dg = DevGroup(grp, 12)
+    _, flags = run([dg])
+    assert flags & ne.FLAG_INPUT_RANGE
+
+
+def test_batched_config_full_length_sampled():
+    """Two stream-triples at the batched size (2^20 samples, 64 taps): every
+    loss gives the same outputs, equal to the oracle at sampled positions and
+    to the plain mode everywhere."""
+    groups = wl.config_batched(groups=2)
+    pos = np.unique(np.concatenate([np.arange(0, 300), np.arange((1 << 20) - 300, (1 << 20) + 63),
+                                    wl.rng(1).integers(0, (1 << 20) + 63, 4000)]))
+    for grp in groups:
+        outs = []
+        for lost in (-1, 0, 1, 2):
+            dg = DevGroup(grp, 12, lost)
+            _, flags = run([dg])
+            assert flags == 0
+            outs.append(dg.result())
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+        plain = DevGroup(grp, 12, -1, "plain")
+        run([plain], "plain")
+        assert np.array_equal(plain.result(), outs[0])
+        for m in range(3):
+            assert np.array_equal(outs[0][m][pos], oracle.conv_at(grp.c[m], grp.operand, pos))
+
+
+def test_long_kernel_config_shape():
+    """The long-kernel shape: 16-bit samples, 1024 taps (more digits)."""
+    grp = wl.config_long_kernel(groups=1, n=9000)[0]
+    ref = oracle.apply("conv", grp.c, grp.operand)
+    for lost in (-1, 2):
+        dg = DevGroup(grp, 16, lost)
+        _, flags = run([dg])
+        assert flags == 0
+        assert np.array_equal(dg.result(), ref)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 7])
+def test_tuning_steps(steps):
+    grp = make("conv", 4, 30001, 129, 12, 8)
+    ref = oracle.apply("conv", grp.c, grp.operand)
+    dg = DevGroup(grp, 12, 1)
+    run([dg], conv_steps=steps, stream_steps=steps)
+    assert np.array_equal(dg.result(), ref)
