@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark: numerical entanglement of batched integer convolution on one
+MI355X.
+
+Workload (the batched configuration): 64 groups of M = 3 streams, each
+stream 1,048,576 int32 samples uniform in [-2^11, 2^11), each group with its
+own 64-tap int32 kernel in the same range; full linear convolution. One step
+is one pass of the whole method over the batch -- entangle (eq. (14)-(15)),
+convolve every entangled stream (eq. (9)), recover every output (eq. (16)-
+(19)) -- as one graph launch of the fused executor, inputs already resident
+in HBM. The same batch is also run through the failure-intolerant plain
+convolution (narrow and same-datapath) and the checksum method, and with one
+stream lost per group.
+
+Prints one JSON line. `value` is recovered output samples per second (Gout-
+samples/s, whole job); `roofline` relates the dominant kernel's algorithmic
+HBM bytes per launch to its average duration (HIP events on its stream);
+`cpu_baseline` times the CPU oracle on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "entangled vs plain int conv Gout-samples/s; overhead %; % roofline; p99"
+HBM_PEAK_GBS = 8000.0
+INT8_PEAK_TOPS = 5000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1509_03838_amd", "csrc", "fused.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_fused_batched_traffic.txt")
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--groups", type=int, default=64, help="stream-triples in the batch")
+    p.add_argument("--no-baselines", action="store_true")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    p.add_argument("--conv-steps", type=int, default=0)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only copy a buffer of this many MiB a few times (a kernel of known "
+                        "traffic, to calibrate the HBM byte counters) and exit")
+    return p.parse_args()
+
+
+def source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(bytes_per_launch_hint: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each GPU would run its own share of groups; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
+
+    from paper_1509_03838_amd import ne
+    from paper_1509_03838_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    ne.load()
+    t_gen = time.perf_counter()
+    groups = wl.config_batched(groups=args.groups)
+    print(f"# generated {len(groups)} groups in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    M, n, K = groups[0].M, groups[0].n, groups[0].operand.size
+    n_out = n + K - 1
+    c_dev = [[torch.from_numpy(row).to(dev) for row in g.c] for g in groups]
+    k_dev = [torch.from_numpy(g.operand).to(dev) for g in groups]
+    out = [[torch.empty(n_out, dtype=torch.int64, device=dev) for _ in range(M)] for _ in groups]
+    out_ref = None
+    stream = torch.cuda.Stream()
+
+    def make_plan(mode, lost=-1):
+        specs = [ne.GroupSpec("conv", c_dev[i], k_dev[i], out[i], 0, lost, 12)
+                 for i in range(len(groups))]
+        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps)
+        plan.capture(stream)
+        return plan
+
+    def time_plan(plan):
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                plan.launch(stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for _ in range(args.steps):
+                plan.launch(stream)
+            e1.record(stream)
+            e1.synchronize()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        return e0.elapsed_time(e1) / args.steps, wall
+
+    results = {}
+    ent = make_plan("entangled")
+    stats = ent.stats()
+    ms_ev, ms_wall = time_plan(ent)
+    flags = ent.flags()
+    if flags:
+        raise SystemExit(f"device flags {flags:#x} after the entangled run")
+    results["entangled"] = ms_ev
+    out_ref = [[t[::997].cpu() for t in row] for row in out[:4]]
+    print(f"# entangled: {ms_ev:.3f} ms/step (events), {ms_wall:.3f} ms (wall)", file=sys.stderr,
+          flush=True)
+
+    if not args.no_baselines:
+        for mode in ("plain", "plain_same", "checksum"):
+            p = make_plan(mode)
+            results[mode], _ = time_plan(p)
+            same = all(torch.equal(out[i][m][::997].cpu(), out_ref[i][m])
+                       for i in range(len(out_ref)) for m in range(M))
+            if not same or p.flags():
+                raise SystemExit(f"{mode} results differ from the entangled run")
+            print(f"# {mode}: {results[mode]:.3f} ms/step", file=sys.stderr, flush=True)
+            p.close()
+        lost = make_plan("entangled", lost=1)
+        results["entangled_one_lost"], _ = time_plan(lost)
+        lost.close()
+        lost = make_plan("checksum", lost=1)
+        results["checksum_one_lost"], _ = time_plan(lost)
+        lost.close()
+
+    samples = stats["out_samples"]
+    value = samples / (ms_ev * 1e-3) / 1e9
+    alg_bytes = stats["in_bytes"] + stats["out_bytes"]
+    achieved = alg_bytes / (ms_ev * 1e-3) / 1e9
+    traffic = read_traffic(alg_bytes)
+
+    def thr(ms):
+        return samples / (ms * 1e-3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gout-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_ev, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batched M={M}: {len(groups)} stream-triples x {n:,} int32 samples "
+                         f"uniform in [-2^11,2^11), {K}-tap int32 kernels, full linear "
+                         "convolution, entangle+conv+recover fused, one graph launch"),
+            "groups": len(groups), "M": M, "n": n, "K": K, "w": 64,
+            "l": ne.params(M)[0],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_conv_fused<5,2,4>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "mfma_i8_tops": round(2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12, 1),
+            "mfma_frac": round(2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+        },
+        "wall_ms_per_step": round(ms_wall, 4),
+    }
+    if "plain" in results:
+        line["baselines"] = {
+            "gout_per_s": {k: round(thr(v), 3) for k, v in results.items()},
+            "ms_per_step": {k: round(v, 4) for k, v in results.items()},
+            "overhead_pct_vs_plain_same": round(100 * (1 - results["plain_same"] / ms_ev), 2),
+            "overhead_pct_vs_plain": round(100 * (1 - results["plain"] / ms_ev), 2),
+            "checksum_overhead_pct_vs_plain_same":
+                round(100 * (1 - results["plain_same"] / results["checksum"]), 2),
+            "checksum_overhead_pct_vs_plain":
+                round(100 * (1 - results["plain"] / results["checksum"]), 2),
+        }
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(groups, np)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(groups, np):
+    """The CPU oracle (entangle, convolve, recover; 128-bit C) on the whole
+    batch, one group per host thread."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    oracle.lib()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        outs = list(ex.map(lambda g: oracle.pipeline(g.c, "conv", g.operand, r=1)[0].size, groups))
+    dt = time.perf_counter() - t0
+    samples = int(sum(outs))
+    return {"value": round(samples / dt / 1e9, 5), "unit": "Gout-samples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"all {len(groups)} groups of the batch, one lost stream each, "
+                      f"{threads} threads, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -12,11 +12,15 @@ LIB = os.path.join(HERE, "libne.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "plan.hip"]
+SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "fused_conv4.hip",
+           "fused_conv9.hip", "plan.hip"]
 
-# Packed-FP32 instructions are disabled for all device code.
+# Packed-FP32 instructions are disabled for all device code. Matrix-core
+# results stay in ordinary VGPRs (no accumulation-register copies in the
+# convolution loops).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

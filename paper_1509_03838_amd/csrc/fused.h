@@ -1,6 +1,7 @@
 // Device-side descriptors of the batched executor (private to libne).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace ne {
@@ -40,7 +41,9 @@ struct GroupDev {
     int32_t wlen;     // staged window length: kConvTile + kp (conv)
     int32_t in_lo, in_hi;  // declared input range [in_lo, in_hi]
     int32_t steps;    // conv tile steps (or streaming positions / 256) per block
-    int32_t pad_;
+    int32_t ring;     // bytes per LDS digit-plane ring (= wlen) (conv)
+    int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv)
+    int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
     int64_t n, K, n_out;
     int64_t scalar;
     const int32_t *c[kFusedMaxM];
@@ -53,5 +56,19 @@ struct Item {
     uint32_t g;       // group index
     uint32_t strip;   // strip index within the group
 };
+
+// Launchers of the fused kernels (fused_conv*.hip, fused.hip).
+template <int NS>
+hipError_t conv_prepare_ns(int la, int lb, size_t lds);
+template <int NS>
+void conv_launch_ns(int la, int lb, const GroupDev *g, const Item *items, uint32_t nitems,
+                    uint32_t *flags, size_t lds, hipStream_t s);
+hipError_t fused_conv_prepare(int cls, int la, int lb, size_t lds);
+void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *items,
+                       uint32_t nitems, uint32_t *flags, size_t lds, hipStream_t s);
+void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
+                         uint32_t *flags, hipStream_t s);
+void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,
+                          uint32_t *flags, hipStream_t s);
 
 }  // namespace ne

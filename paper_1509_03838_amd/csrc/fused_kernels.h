@@ -1,0 +1,636 @@
+// Fused batched kernels (private to libne): for every group of M streams,
+// entangle on load (eq. (14)-(15)), run the LSB operation on each entangled
+// stream (eq. (9)), and recover every output from M-1 of them
+// (eq. (16)-(19)) -- in one pass over HBM: the inputs are read once as int32
+// and only the recovered int64 outputs are written. The entangled words and
+// the entangled outputs live in LDS and registers only.
+//
+// Convolution runs on the i8 matrix cores as a Toeplitz product. A block
+// step covers 1024 consecutive outputs; wave w owns the 16x16 tile of
+// outputs y[T + 256w + 16i + j] (row i, column j), and
+//     y[P + 16i + j] = sum_s A[i][s] B[s][j],
+//     A[i][s] = x[P + 16i - kp + s],  B[s][j] = g[j + kp - s]  (0 outside [0, K)),
+// with s over 64*nch >= K + 15 values and kp = 64*nch - 16, so every row of
+// A is a contiguous window of the stream: the staged window of the block is
+// the whole A operand. Words are split into balanced base-256 digits in
+// [-128, 127] (LA digits for data words, LB for taps); every digit pair is
+// one v_mfma_i32_16x16x64_i8 with exact int32 accumulation, and
+// y = sum 256^(a+b) acc_ab is recombined in 64-bit wrap-around arithmetic,
+// which is exact modulo 2^64 whatever the digit count (a word that needs more
+// digits than chosen is flagged, never silently truncated).
+//
+// Every stream's entangled output depends only on its own entangled input;
+// the stream the plan marks as lost is simply not computed, and recovery
+// never reads its slot.
+#pragma once
+
+#include "fused.h"
+#include "ne_internal.h"
+
+namespace ne {
+namespace fk {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+
+// Maps blockIdx to a work item so that each XCD (blocks are dealt to the 8
+// XCDs round-robin) receives a contiguous run of items: neighbouring strips
+// of a stream share their halo through that XCD's L2.
+__device__ __forceinline__ uint32_t item_index(uint32_t nitems)
+{
+    const uint32_t per = (nitems + 7u) >> 3;
+    return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+}
+
+__device__ __forceinline__ int64_t ent(int64_t cur, int64_t prev, int l)
+{
+    return (int64_t)((uint64_t)cur + ((uint64_t)prev << l));
+}
+
+__device__ __forceinline__ int64_t *out_ptr(const GroupDev *G, int m) { return G->out[m]; }
+
+// Running bounds of every input value a thread reads; checked once against
+// the declared range at the end of the kernel.
+struct Bounds {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    __device__ __forceinline__ void add(int32_t v)
+    {
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+};
+
+// Results of one lane: V positions base + loc[v], one entangled (or plain)
+// output per slot. Slot t of an entangled group is stream (r + 1 + t) mod M,
+// so that slots 0 .. M-2 are exactly the M-1 streams recovery reads and slot
+// M-1 is stream r. Slot t of the other modes is stream t (slot M: the
+// checksum).
+//
+// Entangled recovery (64-bit form of eq. (16)-(19), as in the streaming
+// extraction kernel): d_temp's low (M-1)l bits give d_{r-1}; then
+// d_{j-1} = (delta_j - d_j) >> l walking back to d_r. When stream r was not
+// lost its slot is redundant and is checked against the recovered outputs.
+template <int NS, int V>
+__device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int r, int lost,
+                                         int l, int64_t base, int64_t lim, const int (&loc)[V],
+                                         const int64_t (&dl)[NS][V], uint32_t &flag)
+{
+    if (mode == kEntangled) {
+        const int s = 64 - (M - 1) * l;
+        int64_t *o_last = out_ptr(G, (r + M - 1) % M) + base;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool ok = loc[v] < lim;
+            uint64_t acc = 0;
+#pragma unroll
+            for (int t = 0; t < NS - 1; ++t) {
+                if (t < M - 1) {
+                    const uint64_t x = (uint64_t)dl[t][v];
+                    acc = (acc << l) + (((M + t) & 1) ? (uint64_t)0 - x : x);
+                }
+            }
+            int64_t cur = ((int64_t)(acc << s)) >> s;  // d_{r-1}
+            const int64_t d_prev = cur;
+            if (ok) o_last[loc[v]] = cur;
+#pragma unroll
+            for (int t = NS - 2; t >= 0; --t) {
+                if (t <= M - 2) {
+                    cur = (int64_t)((uint64_t)dl[t][v] - (uint64_t)cur) >> l;
+                    const int m = (t == 0) ? r : (r + t) % M;
+                    if (ok) (out_ptr(G, m) + base)[loc[v]] = cur;
+                }
+            }
+            // cur is d_r; with stream r computed, delta_r = d_r + 2^l d_{r-1}
+            if (!lost && ok) {
+                int64_t dr_slot = 0;
+#pragma unroll
+                for (int t = 0; t < NS; ++t)
+                    if (t == M - 1) dr_slot = dl[t][v];
+                if ((uint64_t)dr_slot != (uint64_t)cur + ((uint64_t)d_prev << l))
+                    flag |= kFlagMismatch;
+            }
+        }
+    } else if (mode == kChecksum) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (loc[v] >= lim) continue;
+            uint64_t e = 0, sum = 0;
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (t == M) e = (uint64_t)dl[t][v];
+#pragma unroll
+            for (int t = 0; t < NS - 1; ++t)
+                if (t < M && !(lost && t == r)) {
+                    sum += (uint64_t)dl[t][v];
+                    (out_ptr(G, t) + base)[loc[v]] = dl[t][v];
+                }
+            if (lost)
+                (out_ptr(G, r) + base)[loc[v]] = (int64_t)(e - sum);
+            else if (e != sum)
+                flag |= kFlagMismatch;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            if (t >= M || (lost && t == r)) continue;
+            int64_t *o = out_ptr(G, t) + base;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (loc[v] < lim) o[loc[v]] = dl[t][v];
+        }
+    }
+}
+
+// Stream (plane) that slot t holds.
+__device__ __forceinline__ int slot_stream(int mode, int M, int r, int t)
+{
+    return mode == kEntangled ? (r + 1 + t) % M : t;
+}
+
+__device__ __forceinline__ bool slot_live(int mode, int M, int r, int lost, int t, int nslots)
+{
+    if (t >= nslots) return false;
+    if (!lost) return true;
+    return mode == kEntangled ? t != M - 1 : t != r;
+}
+
+// Byte transpose: w[a] = byte a of v[0], v[1], v[2], v[3] (in that order).
+__device__ __forceinline__ void transpose4(const uint32_t *v, uint32_t *w)
+{
+    const uint32_t t0 = __builtin_amdgcn_perm(v[1], v[0], 0x05010400u);
+    const uint32_t t1 = __builtin_amdgcn_perm(v[1], v[0], 0x07030602u);
+    const uint32_t t2 = __builtin_amdgcn_perm(v[3], v[2], 0x05010400u);
+    const uint32_t t3 = __builtin_amdgcn_perm(v[3], v[2], 0x07030602u);
+    w[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    w[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    w[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    w[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+// Balanced digits by one add: with C = 128 (256^L - 1) / 255, u = x + C has
+// ordinary base-256 digits u_a in [0, 255] exactly when x has L balanced
+// digits d_a in [-128, 127], and d_a = u_a - 128, whose two's-complement
+// byte is u_a ^ 0x80.
+template <int L>
+__device__ __forceinline__ constexpr uint64_t digit_offset()
+{
+    return L >= 8 ? 0x8080808080808080ull : (0x8080808080808080ull >> (64 - 8 * L));
+}
+
+// Stage 4 consecutive positions p..p+3 of every data word into the LA digit
+// planes at ring offset `off`. Entanglement happens here, on load.
+// Digit planes in LDS: plane (stream) pl occupies LAP * ring bytes; the 16
+// positions starting at ring offset 16k keep their LA digit vectors (16 bytes
+// each) together at pl * LAP * ring + k * 16 * LAP. LAP is LA rounded up to an
+// odd count, so that the 16 lanes of an A-fragment read (16 consecutive k)
+// hit 16 disjoint groups of 4 LDS banks, and each digit is an immediate
+// offset 16a from one address.
+template <int LA>
+__device__ __forceinline__ constexpr int lap() { return LA | 1; }
+
+__device__ __forceinline__ int plane_off(int o, int lapv) { return (o >> 4) * 16 * lapv + (o & 15); }
+
+// Raw int32 inputs of 4 consecutive positions of every stream, in flight
+// between their (prefetched) global loads and their conversion into digit
+// planes. cl: the stream that entangles into stream 0 (c_{M-1}).
+template <int NS>
+struct Raw4 {
+    static constexpr int DM = NS < kFusedMaxM ? NS : kFusedMaxM;
+    int32_t cv[DM][4];
+    int32_t cl[4];
+};
+
+template <int NS>
+__device__ __forceinline__ void load4(const GroupDev *G, int mode, int M, int64_t p, int64_t n,
+                                      Raw4<NS> &raw)
+{
+    constexpr int DM = Raw4<NS>::DM;
+    const bool full = p >= 0 && p + 4 <= n;
+#pragma unroll
+    for (int m = 0; m < DM; ++m) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) raw.cv[m][q] = 0;
+        if (m < M) {
+            if (full) {
+                const int4 v = *reinterpret_cast<const int4 *>(G->c[m] + p);
+                raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (p + q >= 0 && p + q < n) raw.cv[m][q] = G->c[m][p + q];
+            }
+        }
+    }
+    if (mode == kEntangled) {
+        // c_{M-1}, the partner of stream 0, loaded again by pointer (an L1
+        // hit) instead of selected out of the registers with a runtime M.
+        const int32_t *cl = G->c[M - 1];
+        if (full) {
+            const int4 v = *reinterpret_cast<const int4 *>(cl + p);
+            raw.cl[0] = v.x; raw.cl[1] = v.y; raw.cl[2] = v.z; raw.cl[3] = v.w;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) raw.cl[q] = (p + q >= 0 && p + q < n) ? cl[p + q] : 0;
+        }
+    }
+}
+
+// Converts raw inputs of 4 positions into the LA digit planes at ring offset
+// `off`: entanglement (or the checksum sum) happens here.
+template <int LA, int NS>
+__device__ __forceinline__ void store4(const Raw4<NS> &raw, int mode, int M, int l, int nplanes,
+                                       unsigned char *planes, int ring, int off, Bounds &bd)
+{
+    constexpr int DM = Raw4<NS>::DM;
+    constexpr uint64_t C = digit_offset<LA>();
+    constexpr int LAP = lap<LA>();
+    int32_t csum[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        csum[q] = 0;
+#pragma unroll
+        for (int m = 0; m < DM; ++m)
+            if (m < M) {
+                bd.add(raw.cv[m][q]);
+                csum[q] += raw.cv[m][q];
+            }
+    }
+#pragma unroll
+    for (int pl = 0; pl < NS; ++pl) {
+        if (pl >= nplanes) continue;
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int64_t x;
+            const int32_t own = pl < DM ? raw.cv[pl < DM ? pl : 0][q] : 0;
+            if (mode == kEntangled) {
+                const int32_t prev = pl == 0 ? raw.cl[q] : raw.cv[pl == 0 ? 0 : (pl - 1) % DM][q];
+                x = ent(own, prev, l);
+            } else if (mode == kChecksum && pl == M) {
+                x = csum[q];
+            } else {
+                x = own;
+            }
+            // (x has LA digits whenever the inputs lie in the declared range,
+            // which the plan sized LA for and the kernel verifies.)
+            const uint64_t u = (uint64_t)x + C;
+            lo[q] = (uint32_t)u;
+            hi[q] = (uint32_t)(u >> 32);
+        }
+        uint32_t w[8];
+        transpose4(lo, w);
+        if (LA > 4) transpose4(hi, w + 4);
+        unsigned char *dst = planes + (size_t)pl * LAP * ring + plane_off(off, LAP);
+#pragma unroll
+        for (int a = 0; a < LA; ++a) *reinterpret_cast<uint32_t *>(dst + 16 * a) = w[a] ^ 0x80808080u;
+    }
+}
+
+// ----------------------------------------------------- convolution kernel
+
+template <int LA, int LB, int NS>
+__global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
+                                                       const Item *__restrict__ items,
+                                                       uint32_t nitems, uint32_t *flags)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t ii = item_index(nitems);
+    if (ii >= nitems) return;
+    const Item it = items[ii];
+    const GroupDev *G = groups + it.g;
+    const int mode = G->mode, M = G->M, r = G->r, lost = G->lost, l = G->l;
+    const int nslots = G->nslots, nch = G->nch, kp = G->kp, wlen = G->wlen, ring = G->ring;
+    const int steps = G->steps, acc16 = G->acc16, use_dma = G->dma;
+    const int64_t n = G->n, K = G->K, n_out = G->n_out;
+    const int32_t *__restrict__ g = G->operand;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nplanes = (mode == kChecksum) ? M + 1 : M;
+    uint32_t flag = 0;
+    Bounds bd;
+
+    v4i *bfrag = reinterpret_cast<v4i *>(smem);
+    unsigned char *planes = smem + (size_t)nch * LB * 1024;
+
+    // Toeplitz operand B, in the lane layout of the MFMA: lane (j, h) holds
+    // B[64c + 16h + q][j] for q = 0..15, split into LB digit planes.
+    {
+        constexpr uint64_t CB = digit_offset<LB>();
+        for (int e = tid; e < nch * 64; e += kBlock) {
+            const int c = e >> 6, ln = e & 63, j = ln & 15, h = ln >> 4;
+            uint32_t words[LB][4];
+#pragma unroll
+            for (int qg = 0; qg < 4; ++qg) {
+                uint32_t u4[4];
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int q = 4 * qg + q4;
+                    const int64_t idx = (int64_t)j + kp - (64 * c + 16 * h + q);
+                    const int32_t gv = (idx >= 0 && idx < K) ? g[idx] : 0;
+                    bd.add(gv);
+                    u4[q4] = (uint32_t)((uint64_t)(int64_t)gv + CB);
+                }
+                uint32_t w[4];
+                transpose4(u4, w);
+#pragma unroll
+                for (int b = 0; b < LB; ++b) words[b][qg] = w[b] ^ 0x80808080u;
+            }
+#pragma unroll
+            for (int b = 0; b < LB; ++b) {
+                v4i v = {(int)words[b][0], (int)words[b][1], (int)words[b][2], (int)words[b][3]};
+                bfrag[(c * LB + b) * 64 + ln] = v;
+            }
+        }
+    }
+
+    // The digit planes are rings of `ring` bytes (the window 1024 + kp, a
+    // multiple of 16, so no 16-byte access wraps): ring offset 0 is position
+    // T0 - kp. The first step stages the whole window, every later step only
+    // its 1024 new positions.
+    const int64_t T0 = (int64_t)it.strip * steps * kConvTile;
+    const int64_t base = T0 - kp;
+    {
+        Raw4<NS> raw;
+        for (int gi = tid; gi < (wlen >> 2); gi += kBlock) {
+            load4<NS>(G, mode, M, base + 4 * gi, n, raw);
+            store4<LA, NS>(raw, mode, M, l, nplanes, planes, ring, 4 * gi, bd);
+        }
+    }
+    // The raw int32 inputs of the next step travel HBM -> LDS by direct
+    // loads (global_load_lds_dwordx4, no registers held) while this step
+    // computes; wave w lane j fetches positions 256w + 4j .. +3 of every
+    // stream, exactly the positions thread 64w + j converts at the step
+    // boundary, so only the wave's own wait is needed before converting.
+    // Lanes whose 4 positions are not all inside [0, n) load nothing; their
+    // positions are read with bounds checks at conversion.
+    unsigned char *rawb = planes + (size_t)nplanes * lap<LA>() * ring;
+    auto dma = [&](int64_t Tq) {
+        const int64_t p = Tq + 4 * tid;
+        if (use_dma && p + 4 <= n) {
+#pragma unroll
+            for (int m = 0; m < Raw4<NS>::DM; ++m)
+                if (m < M)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)(G->c[m] + p),
+                        (__attribute__((address_space(3))) void *)(rawb + m * 4096 + wave * 1024),
+                        16, 0, 0);
+        }
+    };
+    if (steps > 1 && T0 + kConvTile < n_out) dma(T0 + kConvTile);
+
+    int loc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) loc[v] = 16 * (4 * (lane >> 4) + v) + (lane & 15);
+
+    for (int step = 0; step < steps; ++step) {
+        const int64_t T = T0 + (int64_t)step * kConvTile;
+        if (T >= n_out) break;
+        __syncthreads();  // digit planes of this step complete
+
+        // Each wave: its 16x16 output tile, for every live slot.
+        const int64_t P0 = T + 256 * wave;
+        const int aoff =
+            (int)(((T - T0) + 256 * wave + 16 * (lane & 15) + 16 * (lane >> 4)) % ring);
+        int64_t dl[NS][4];
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dl[t][v] = 0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            if (!slot_live(mode, M, r, lost, t, nslots)) continue;
+            const int pl = slot_stream(mode, M, r, t);
+            const unsigned char *pbase = planes + (size_t)pl * lap<LA>() * ring;
+            // One accumulator per digit pair (a, b), each MFMA reading and
+            // writing its own; a pair with a + b >= 8 is a multiple of 2^64
+            // and is skipped. Chunk 0 starts from zero.
+            v4i acc[LA][LB];
+            for (int c = 0; c < nch; ++c) {
+                int o = aoff + 64 * c;  // < 2 ring
+                o = o >= ring ? o - ring : o;
+                const unsigned char *pa = pbase + plane_off(o, lap<LA>());
+                v4i bf[LB], af[LA];
+#pragma unroll
+                for (int b = 0; b < LB; ++b) bf[b] = bfrag[(c * LB + b) * 64 + lane];
+#pragma unroll
+                for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
+                if (c == 0) {
+#pragma unroll
+                    for (int b = 0; b < LB; ++b)
+#pragma unroll
+                        for (int a = 0; a < LA; ++a)
+                            if (a + b < 8)
+                                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                    af[a], bf[b], v4i{0, 0, 0, 0}, 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int b = 0; b < LB; ++b)
+#pragma unroll
+                        for (int a = 0; a < LA; ++a)
+                            if (a + b < 8)
+                                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
+                                                                                  acc[a][b], 0, 0, 0);
+                }
+            }
+            // y = sum_s 256^s acc_s (mod 2^64). When the plan has shown every
+            // acc_s + 256 acc_{s+1} fits in int32 (acc16), neighbouring digit
+            // sums are merged in 32 bits first and the 64-bit Horner steps
+            // over 16-bit shifts.
+            constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+            constexpr int H = (S + 1) / 2;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // digit sums of equal weight 256^s (exact in int32, plan-checked)
+                int32_t sh[S];
+#pragma unroll
+                for (int k = 0; k < S; ++k) sh[k] = 0;
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8) sh[a + b] += acc[a][b][v];
+                uint64_t y;
+                if (acc16) {
+                    int32_t z[H];
+#pragma unroll
+                    for (int k = 0; k < H; ++k)
+                        z[k] = (int32_t)((uint32_t)sh[2 * k] +
+                                         (2 * k + 1 < S ? (uint32_t)sh[(2 * k + 1) % S] << 8 : 0u));
+                    y = (uint64_t)(int64_t)z[H - 1];
+#pragma unroll
+                    for (int k = H - 2; k >= 0; --k) y = (y << 16) + (uint64_t)(int64_t)z[k];
+                } else {
+                    y = (uint64_t)(int64_t)sh[S - 1];
+#pragma unroll
+                    for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)sh[s];
+                }
+                dl[t][v] = (int64_t)y;
+            }
+        }
+        epilogue<NS, 4>(G, mode, M, r, lost, l, P0, n_out - P0, loc, dl, flag);
+
+        const int64_t Tn = T + kConvTile;
+        if (step + 1 < steps && Tn < n_out) {
+            Raw4<NS> raw;
+            const int64_t p = Tn + 4 * tid;
+            if (use_dma && p + 4 <= n) {
+                __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
+#pragma unroll
+                for (int m = 0; m < Raw4<NS>::DM; ++m) {
+                    if (m < M) {
+                        const int4 v = *reinterpret_cast<const int4 *>(rawb + m * 4096 + 16 * tid);
+                        raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) raw.cv[m][q] = 0;
+                    }
+                }
+                if (mode == kEntangled) {
+                    const int4 v = *reinterpret_cast<const int4 *>(rawb + (M - 1) * 4096 + 16 * tid);
+                    raw.cl[0] = v.x; raw.cl[1] = v.y; raw.cl[2] = v.z; raw.cl[3] = v.w;
+                }
+            } else {
+                load4<NS>(G, mode, M, p, n, raw);
+            }
+            __syncthreads();  // every wave is done with the ring slots reused here
+            store4<LA, NS>(raw, mode, M, l, nplanes, planes, ring, (int)((p - base) % ring), bd);
+            if (step + 2 < steps && Tn + kConvTile < n_out) dma(Tn + kConvTile);
+        }
+    }
+    if (bd.lo < G->in_lo || bd.hi > G->in_hi) flag |= kFlagInputRange;
+    if (flag) atomicOr(flags, flag);
+}
+
+// ------------------------------------------------ element-wise operations
+
+// Scale, add, permutation and inner product: one position per lane per
+// step, all M streams of the group at once (entangle -> op -> recover in
+// registers). Inputs are loaded directly in slot order (slot t of an
+// entangled group is stream (r + 1 + t) mod M), so the previous stream of
+// slot t >= 1 is slot t - 1 and no register is selected at run time.
+// Inner products accumulate per slot into the group's accumulators;
+// k_inner_finalize recovers them.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
+                                                         const Item *__restrict__ items,
+                                                         uint32_t nitems, uint32_t *flags)
+{
+    const uint32_t ii = item_index(nitems);
+    if (ii >= nitems) return;
+    const Item it = items[ii];
+    const GroupDev *G = groups + it.g;
+    const int op = G->op, mode = G->mode, M = G->M, r = G->r, lost = G->lost, l = G->l;
+    const int nslots = G->nslots, steps = G->steps;
+    const int64_t n = G->n, sv = G->scalar;
+    const int32_t *__restrict__ opd = G->operand;
+    uint32_t flag = 0;
+    Bounds bd;
+    uint64_t iacc[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) iacc[t] = 0;
+
+    const int64_t strip0 = (int64_t)it.strip * steps * kBlock;
+    const int loc[1] = {(int)threadIdx.x};
+    for (int q = 0; q < steps; ++q) {
+        const int64_t pb = strip0 + (int64_t)q * kBlock;
+        if (pb >= n) break;
+        const int64_t p = pb + threadIdx.x;
+        const bool in = p < n;
+        int64_t src = in ? p : 0;
+        if (op == NE_OP_PERM && in) {
+            src = opd[p];
+            src = src < 0 ? 0 : (src >= n ? n - 1 : src);
+        }
+        // Inputs in slot order; `prev0` is the partner of slot 0.
+        int32_t cv[NS], prev0 = 0, csum = 0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            cv[t] = 0;
+            if (t < M && in) {
+                cv[t] = G->c[slot_stream(mode, M, r, t)][src];
+                bd.add(cv[t]);
+                csum += cv[t];
+            }
+        }
+        if (mode == kEntangled && in) prev0 = G->c[r][src];
+        int32_t gv = 0;
+        if ((op == NE_OP_ADD || op == NE_OP_INNER) && in) {
+            gv = opd[p];
+            bd.add(gv);
+        }
+        int64_t dl[NS][1];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            dl[t][0] = 0;
+            if (!slot_live(mode, M, r, lost, t, nslots)) continue;
+            int64_t x, gs = gv;
+            if (mode == kEntangled) {
+                x = ent(cv[t], t == 0 ? prev0 : cv[t == 0 ? 0 : t - 1], l);
+                gs = ent(gv, gv, l);  // footnote 3: the added vector is entangled too
+            } else if (mode == kChecksum && t == M) {
+                x = csum;
+                gs = (int64_t)M * gv;  // checksum of the M added operands
+            } else {
+                x = cv[t];
+            }
+            uint64_t y;
+            switch (op) {
+            case NE_OP_SCALE: y = (uint64_t)x * (uint64_t)sv; break;
+            case NE_OP_ADD: y = (uint64_t)x + (uint64_t)gs; break;
+            case NE_OP_INNER: y = (uint64_t)x * (uint64_t)(int64_t)gv; break;
+            default: y = (uint64_t)x; break;  // permutation: the gather above
+            }
+            if (op == NE_OP_INNER)
+                iacc[t] += in ? y : 0;
+            else
+                dl[t][0] = (int64_t)y;
+        }
+        if (op != NE_OP_INNER) epilogue<NS, 1>(G, mode, M, r, lost, l, pb, n - pb, loc, dl, flag);
+    }
+    if (op == NE_OP_INNER) {
+        __shared__ uint64_t part[kBlock / 64][NS];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            uint64_t v = iacc[t];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                v += (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][t] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NS && (int)threadIdx.x < nslots) {
+            uint64_t s = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s += part[w][threadIdx.x];
+            atomicAdd(reinterpret_cast<unsigned long long *>(G->acc + threadIdx.x),
+                      (unsigned long long)s);
+        }
+    }
+    if (bd.lo < G->in_lo || bd.hi > G->in_hi) flag |= kFlagInputRange;
+    if (flag) atomicOr(flags, flag);
+}
+
+// Recovery of inner products (one output per stream) after all partial
+// sums have landed; also clears the accumulators for the next run.
+template <int NS>
+__global__ __launch_bounds__(64) void k_inner_finalize(const GroupDev *__restrict__ groups,
+                                                       const uint32_t *__restrict__ gidx,
+                                                       uint32_t count, uint32_t *flags)
+{
+    const uint32_t i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= count) return;
+    const GroupDev *G = groups + gidx[i];
+    uint32_t flag = 0;
+    int64_t dl[NS][1];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        dl[t][0] = (int64_t)G->acc[t];
+        G->acc[t] = 0;
+    }
+    const int loc[1] = {0};
+    epilogue<NS, 1>(G, G->mode, G->M, G->r, G->lost, G->l, 0, 1, loc, dl, flag);
+    if (flag) atomicOr(flags, flag);
+}
+
+}  // namespace fk
+}  // namespace ne

@@ -11,16 +11,6 @@
 #include "fused.h"
 #include "ne_internal.h"
 
-namespace ne {
-hipError_t fused_conv_prepare(int cls, int la, int lb, size_t lds);
-void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *items,
-                       uint32_t nitems, uint32_t *flags, size_t lds, hipStream_t s);
-void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
-                         uint32_t *flags, hipStream_t s);
-void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,
-                          uint32_t *flags, hipStream_t s);
-}  // namespace ne
-
 using namespace ne;
 
 struct Bucket {
@@ -201,14 +191,22 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
             G.nch = (int)((u.n_operand + 15 + 63) / 64);
             G.kp = 64 * G.nch - 16;
             G.wlen = kConvTile + G.kp;
+            G.ring = G.wlen;
+            // Neighbouring digit sums merge in int32 when
+            // |acc_s| + 256 |acc_{s+1}| < 2^31, |acc_s| <= min(la, lb) 64 nch 2^14.
+            G.acc16 = (int64_t)257 * std::min(la, lb) * 64 * G.nch * 16384 < ((int64_t)1 << 31);
             G.steps = conv_steps;
             // int32 accumulation: a digit product is at most 2^14, summed over
             // 64 nch inputs and at most min(la, lb) digit pairs per shift.
             if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
                 return fail(NE_EUNSUP);
             const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
-            const size_t lds = (size_t)G.nch * lb * 1024 + (size_t)nplanes * la * G.wlen;
+            // B fragments | digit planes | raw int32 staging of one step
+            // (M x 4 KiB, only when it fits: the prefetch is an optimisation)
+            size_t lds = (size_t)G.nch * lb * 1024 + (size_t)nplanes * (la | 1) * G.ring;
             if (lds > kMaxLds) return fail(NE_EUNSUP);
+            G.dma = lds + (size_t)u.M * 4096 <= kMaxLds && conv_steps > 1;
+            if (G.dma) lds += (size_t)u.M * 4096;
             const int64_t strip = (int64_t)conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
             auto key = std::make_tuple(1, cls, la, lb);
