@@ -32,7 +32,10 @@ sys.path.insert(0, ROOT)
 METRIC = "entangled vs plain int conv Gout-samples/s; overhead %; % roofline; p99"
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1509_03838_amd", "csrc", "fused.hip")
+CSRC = os.path.join(ROOT, "paper_1509_03838_amd", "csrc")
+# Sources that define the fused convolution kernel and its launch.
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("fused_kernels.h", "fused.h", "fused_conv_impl.h",
+                                               "plan.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_fused_batched_traffic.txt")
 
 
@@ -52,8 +55,11 @@ def parse():
 
 
 def source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(bytes_per_launch_hint: float):
