@@ -48,6 +48,11 @@ def parse():
     p.add_argument("--no-baselines", action="store_true")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--conv-steps", type=int, default=0)
+    p.add_argument("--stream-steps", type=int, default=0)
+    p.add_argument("--config", default="batched", choices=("batched", "small", "uneven", "long"),
+                   help="workload; the benchmark line is the batched one")
+    p.add_argument("--only", default=None, choices=("entangled", "plain", "plain_same", "checksum"),
+                   help="time one mode only (profiling)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only copy a buffer of this many MiB a few times (a kernel of known "
                         "traffic, to calibrate the HBM byte counters) and exit")
@@ -108,21 +113,21 @@ def main():
     dev = torch.device("cuda:0")
     ne.load()
     t_gen = time.perf_counter()
-    groups = wl.config_batched(groups=args.groups)
+    cfg = CONFIGS[args.config]
+    groups, in_bits, describe = cfg(wl, args)
     print(f"# generated {len(groups)} groups in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
-    M, n, K = groups[0].M, groups[0].n, groups[0].operand.size
-    n_out = n + K - 1
     c_dev = [[torch.from_numpy(row).to(dev) for row in g.c] for g in groups]
-    k_dev = [torch.from_numpy(g.operand).to(dev) for g in groups]
-    out = [[torch.empty(n_out, dtype=torch.int64, device=dev) for _ in range(M)] for _ in groups]
-    out_ref = None
+    k_dev = [None if g.op == "scale" else torch.from_numpy(g.operand).to(dev) for g in groups]
+    n_outs = [ne.n_out(g.op, g.n, 0 if g.operand is None else g.operand.size) for g in groups]
+    out = [[torch.empty(max(no, 1), dtype=torch.int64, device=dev)[:no] for _ in range(g.M)]
+           for g, no in zip(groups, n_outs)]
     stream = torch.cuda.Stream()
 
     def make_plan(mode, lost=-1):
-        specs = [ne.GroupSpec("conv", c_dev[i], k_dev[i], out[i], 0, lost, 12)
-                 for i in range(len(groups))]
-        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps)
+        specs = [ne.GroupSpec(g.op, c_dev[i], k_dev[i], out[i], g.scalar, lost, in_bits)
+                 for i, g in enumerate(groups)]
+        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps)
         plan.capture(stream)
         return plan
 
@@ -143,44 +148,64 @@ def main():
             wall = (time.perf_counter() - t0) * 1e3 / args.steps
         return e0.elapsed_time(e1) / args.steps, wall
 
+    def snapshot():
+        return [[t[::997].cpu() for t in row] for row in out[:8]]
+
     results = {}
-    ent = make_plan("entangled")
+    main_mode = args.only or "entangled"
+    ent = make_plan(main_mode)
     stats = ent.stats()
     ms_ev, ms_wall = time_plan(ent)
     flags = ent.flags()
     if flags:
-        raise SystemExit(f"device flags {flags:#x} after the entangled run")
-    results["entangled"] = ms_ev
-    out_ref = [[t[::997].cpu() for t in row] for row in out[:4]]
-    print(f"# entangled: {ms_ev:.3f} ms/step (events), {ms_wall:.3f} ms (wall)", file=sys.stderr,
-          flush=True)
+        raise SystemExit(f"device flags {flags:#x} after the {main_mode} run")
+    results[main_mode] = ms_ev
+    out_ref = snapshot()
+    print(f"# {main_mode}: {ms_ev:.3f} ms/step (events), {ms_wall:.3f} ms (wall), "
+          f"{stats['launches']} launches", file=sys.stderr, flush=True)
 
-    if not args.no_baselines:
+    if not args.no_baselines and not args.only:
         for mode in ("plain", "plain_same", "checksum"):
             p = make_plan(mode)
             results[mode], _ = time_plan(p)
-            same = all(torch.equal(out[i][m][::997].cpu(), out_ref[i][m])
-                       for i in range(len(out_ref)) for m in range(M))
+            same = all(torch.equal(a, b) for ra, rb in zip(snapshot(), out_ref)
+                       for a, b in zip(ra, rb))
             if not same or p.flags():
                 raise SystemExit(f"{mode} results differ from the entangled run")
             print(f"# {mode}: {results[mode]:.3f} ms/step", file=sys.stderr, flush=True)
             p.close()
-        lost = make_plan("entangled", lost=1)
-        results["entangled_one_lost"], _ = time_plan(lost)
-        lost.close()
-        lost = make_plan("checksum", lost=1)
-        results["checksum_one_lost"], _ = time_plan(lost)
-        lost.close()
+        for mode in ("entangled", "checksum"):
+            lost = make_plan(mode, lost=1)
+            results[f"{mode}_one_lost"], _ = time_plan(lost)
+            lost.close()
 
     samples = stats["out_samples"]
     value = samples / (ms_ev * 1e-3) / 1e9
     alg_bytes = stats["in_bytes"] + stats["out_bytes"]
     achieved = alg_bytes / (ms_ev * 1e-3) / 1e9
-    traffic = read_traffic(alg_bytes)
+    mfma_tops = 2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12
+    hbm_frac, mfma_frac = achieved / HBM_PEAK_GBS, mfma_tops / INT8_PEAK_TOPS
+    traffic = read_traffic(alg_bytes) if args.config == "batched" and main_mode == "entangled" \
+        else None
 
     def thr(ms):
         return samples / (ms * 1e-3) / 1e9
 
+    single = len({(g.op, g.M) for g in groups}) == 1 and stats["launches"] == 1
+    if hbm_frac >= mfma_frac:
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "achieved": round(mfma_tops, 1), "peak": INT8_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": round(mfma_frac, 4), "traffic": traffic}
+    roof.update({
+        "kernel": stats_kernel_name(stats, groups, main_mode) if single else
+        f"all {stats['launches']} launches of the plan",
+        "alg_bytes_per_launch": alg_bytes,
+        "hbm_GBps": round(achieved, 1), "hbm_frac": round(hbm_frac, 4),
+        "mfma_i8_tops": round(mfma_tops, 1), "mfma_frac": round(mfma_frac, 4),
+    })
+    M0 = groups[0].M
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -194,25 +219,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {
-            "workload": (f"batched M={M}: {len(groups)} stream-triples x {n:,} int32 samples "
-                         f"uniform in [-2^11,2^11), {K}-tap int32 kernels, full linear "
-                         "convolution, entangle+conv+recover fused, one graph launch"),
-            "groups": len(groups), "M": M, "n": n, "K": K, "w": 64,
-            "l": ne.params(M)[0],
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_conv_fused<5,2,4>",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "alg_bytes_per_launch": alg_bytes,
-            "mfma_i8_tops": round(2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12, 1),
-            "mfma_frac": round(2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
-        },
+        "config": dict(workload=describe, groups=len(groups), mode=main_mode, w=64,
+                       out_samples=samples, **({"l": ne.params(M0)[0]} if M0 >= 3 else {})),
+        "roofline": roof,
         "wall_ms_per_step": round(ms_wall, 4),
     }
     if "plain" in results:
@@ -227,9 +236,43 @@ def main():
                 round(100 * (1 - results["plain"] / results["checksum"]), 2),
         }
 
-    if not args.no_cpu:
+    if not args.no_cpu and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(groups, np)
     print(json.dumps(line), flush=True)
+
+
+def stats_kernel_name(stats, groups, mode):
+    g = groups[0]
+    return "k_conv_fused" if g.op == "conv" else "k_stream_fused"
+
+
+def _batched(wl, args):
+    groups = wl.config_batched(groups=args.groups)
+    g = groups[0]
+    return groups, 12, (f"batched M={g.M}: {len(groups)} stream-triples x {g.n:,} int32 samples "
+                        f"uniform in [-2^11,2^11), {g.operand.size}-tap int32 kernels, full linear "
+                        "convolution, entangle+conv+recover fused, one graph launch")
+
+
+def _small(wl, args):
+    return [wl.config_small()], 8, ("small: M=3 x 65,536 int32 samples uniform in [-128,127], "
+                                    "16-tap kernel, full linear convolution")
+
+
+def _uneven(wl, args):
+    groups = wl.config_uneven(groups=args.groups if args.groups != 64 else 512)
+    return groups, 10, (f"uneven: {len(groups)} groups, M in 3..8, n log-uniform [2^12,2^22], "
+                        "int32 samples in [-2^9,2^9), conv taps log-uniform [8,512], ops mixed "
+                        "(conv/scale/add/inner/perm), one graph launch")
+
+
+def _long(wl, args):
+    groups = wl.config_long_kernel(groups=args.groups if args.groups != 64 else 256)
+    return groups, 16, (f"long kernel: {len(groups)} stream-triples x 262,144 int16-range samples "
+                        "held as int32, 1024-tap kernels, i8-MFMA Toeplitz convolution")
+
+
+CONFIGS = {"batched": _batched, "small": _small, "uneven": _uneven, "long": _long}
 
 
 def cpu_baseline(groups, np):

@@ -241,17 +241,19 @@ typedef struct ne_group {
                             violations are flagged (NE_FLAG_INPUT_RANGE) */
     const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
     const int32_t *operand;           /* device int32 taps / vector /
-                                         permutation indices; NULL for scale.
+                                         permutation indices, 16-byte aligned;
+                                         NULL for scale.
                                          For add, the plain vector g (the
                                          entangled mode entangles it itself,
                                          footnote 3). */
     int64_t *out[NE_FUSED_MAX_M];     /* device outputs, n_out int64 each,
-                                         8-byte aligned, disjoint */
+                                         16-byte aligned, disjoint */
 } ne_group;
 
 typedef struct ne_tuning {
     int32_t conv_steps;   /* 1024-output steps per convolution block; 0: 4 */
-    int32_t stream_steps; /* positions per lane per element-wise block; 0: 16 */
+    int32_t stream_steps; /* steps of 256 lanes x 4 (M <= 4) or x 2 positions
+                             per element-wise block; 0: 4 */
 } ne_tuning;
 
 typedef struct ne_plan_stats {

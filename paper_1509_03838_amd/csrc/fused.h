@@ -11,6 +11,8 @@ constexpr int kMaxSlots = kFusedMaxM + 1;  // + the checksum stream
 constexpr int kConvTile = 1024;     // output positions per block step (4 waves x 256)
 constexpr int kLimbsA = 8;          // largest limb count of a data word
 constexpr int kLimbsB = 4;          // largest limb count of an operand value
+constexpr int kStreamV0 = 4;        // element-wise kernel: positions per lane, <= 4 slots
+constexpr int kStreamV1 = 2;        // element-wise kernel: positions per lane, <= 9 slots
 
 // Execution modes of a plan.
 enum Mode : int32_t {

@@ -21,13 +21,12 @@ void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *i
 void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
                          uint32_t *flags, hipStream_t s)
 {
-    const uint32_t grid = ((nitems + 7u) >> 3) << 3;
     if (cls == 0)
-        hipLaunchKernelGGL(fk::k_stream_fused<4>, dim3(grid), dim3(fk::kBlock), 0, s, g, items,
-                           nitems, flags);
+        hipLaunchKernelGGL((fk::k_stream_fused<4, kStreamV0>), dim3(nitems), dim3(fk::kBlock), 0, s,
+                           g, items, nitems, flags);
     else
-        hipLaunchKernelGGL(fk::k_stream_fused<kMaxSlots>, dim3(grid), dim3(fk::kBlock), 0, s, g,
-                           items, nitems, flags);
+        hipLaunchKernelGGL((fk::k_stream_fused<kMaxSlots, kStreamV1>), dim3(nitems),
+                           dim3(fk::kBlock), 0, s, g, items, nitems, flags);
 }
 
 void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,

@@ -34,6 +34,10 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 
+struct alignas(16) I64x2 {
+    int64_t a, b;
+};
+
 // Maps blockIdx to a work item so that each XCD (blocks are dealt to the 8
 // XCDs round-robin) receives a contiguous run of items: neighbouring strips
 // of a stream share their halo through that XCD's L2.
@@ -503,19 +507,95 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
 
 // ------------------------------------------------ element-wise operations
 
-// Scale, add, permutation and inner product: one position per lane per
-// step, all M streams of the group at once (entangle -> op -> recover in
-// registers). Inputs are loaded directly in slot order (slot t of an
-// entangled group is stream (r + 1 + t) mod M), so the previous stream of
-// slot t >= 1 is slot t - 1 and no register is selected at run time.
-// Inner products accumulate per slot into the group's accumulators;
-// k_inner_finalize recovers them.
-template <int NS>
+// V consecutive int32 values (V = 2: one 8-byte load, V = 4: one 16-byte load).
+template <int V, typename T>
+__device__ __forceinline__ void load_vec(const int32_t *src, T (&x)[V])
+{
+    if constexpr (V == 4) {
+        const int4 w = *reinterpret_cast<const int4 *>(src);
+        x[0] = w.x; x[1] = w.y; x[2] = w.z; x[3] = w.w;
+    } else {
+        const int2 w = *reinterpret_cast<const int2 *>(src);
+        x[0] = w.x; x[1] = w.y;
+    }
+}
+
+// Recovery of V consecutive positions per lane with the results left in
+// place: on return dl[t][v] holds the recovered output of slot t (entangled:
+// stream (r + 1 + t) mod M; otherwise stream t), for t < M. Same arithmetic
+// as epilogue(); with stream r computed, the redundant slot is checked.
+template <int NS, int V>
+__device__ __forceinline__ void recover_inplace(int mode, int M, int r, int lost, int l,
+                                                int64_t (&dl)[NS][V], uint32_t &flag)
+{
+    if (mode == kEntangled) {
+        const int s = 64 - (M - 1) * l;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            uint64_t acc = 0;
+#pragma unroll
+            for (int t = 0; t < NS - 1; ++t)
+                if (t < M - 1) {
+                    const uint64_t x = (uint64_t)dl[t][v];
+                    acc = (acc << l) + (((M + t) & 1) ? (uint64_t)0 - x : x);
+                }
+            int64_t cur = ((int64_t)(acc << s)) >> s;  // d of slot M-2
+            const int64_t d_prev = cur;
+#pragma unroll
+            for (int t = NS - 2; t >= 0; --t)
+                if (t <= M - 2) {
+                    const int64_t delta = dl[t][v];
+                    dl[t][v] = cur;                                              // d of slot t
+                    cur = (int64_t)((uint64_t)delta - (uint64_t)cur) >> l;      // d of slot t-1
+                }
+            // cur is d_r (slot M-1)
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (t == M - 1) {
+                    if (!lost && (uint64_t)dl[t][v] != (uint64_t)cur + ((uint64_t)d_prev << l))
+                        flag |= kFlagMismatch;
+                    dl[t][v] = cur;
+                }
+        }
+    } else if (mode == kChecksum) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            uint64_t e = 0, sum = 0;
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (t == M) e = (uint64_t)dl[t][v];
+#pragma unroll
+            for (int t = 0; t < NS - 1; ++t)
+                if (t < M && !(lost && t == r)) sum += (uint64_t)dl[t][v];
+            if (lost) {
+#pragma unroll
+                for (int t = 0; t < NS - 1; ++t)
+                    if (t == r) dl[t][v] = (int64_t)(e - sum);
+            } else if (e != sum) {
+                flag |= kFlagMismatch;
+            }
+        }
+    }
+}
+
+// Scale, add, permutation and inner product: V consecutive positions per
+// lane per step (8- or 16-byte loads, 16-byte stores), all M streams of the group at
+// once (entangle -> op -> recover in registers). Inputs are loaded directly
+// in slot order (slot t of an entangled group is stream (r + 1 + t) mod M),
+// so the previous stream of slot t >= 1 is slot t - 1 and no register is
+// selected at run time. Inner products accumulate per slot into the group's
+// accumulators; k_inner_finalize recovers them.
+//
+// Items are taken in plain block order (no per-XCD runs): neighbouring
+// blocks then work on the same group at the same time, so a permutation's
+// random gathers fall into a working set the memory-side cache holds.
+template <int NS, int V>
 __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
                                                          const Item *__restrict__ items,
                                                          uint32_t nitems, uint32_t *flags)
 {
-    const uint32_t ii = item_index(nitems);
+    static_assert(V == 2 || V == 4, "2 or 4 positions per lane");
+    const uint32_t ii = blockIdx.x;
     if (ii >= nitems) return;
     const Item it = items[ii];
     const GroupDev *G = groups + it.g;
@@ -528,64 +608,115 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     uint64_t iacc[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) iacc[t] = 0;
+    int sst[NS];  // stream of each slot (wave-uniform)
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        int st = mode == kEntangled ? r + 1 + t : t;
+        st = st >= M ? st - M : st;
+        st = st >= M ? st - M : st;
+        sst[t] = st < M ? st : 0;
+    }
 
-    const int64_t strip0 = (int64_t)it.strip * steps * kBlock;
-    const int loc[1] = {(int)threadIdx.x};
+    const int64_t strip0 = (int64_t)it.strip * steps * kBlock * V;
     for (int q = 0; q < steps; ++q) {
-        const int64_t pb = strip0 + (int64_t)q * kBlock;
+        const int64_t pb = strip0 + (int64_t)q * kBlock * V;
         if (pb >= n) break;
-        const int64_t p = pb + threadIdx.x;
-        const bool in = p < n;
-        int64_t src = in ? p : 0;
-        if (op == NE_OP_PERM && in) {
-            src = opd[p];
-            src = src < 0 ? 0 : (src >= n ? n - 1 : src);
-        }
-        // Inputs in slot order; `prev0` is the partner of slot 0.
-        int32_t cv[NS], prev0 = 0, csum = 0;
+        const int64_t p = pb + V * threadIdx.x;
+        const bool full = p + V <= n;
+        int64_t src[V];
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            cv[t] = 0;
-            if (t < M && in) {
-                cv[t] = G->c[slot_stream(mode, M, r, t)][src];
-                bd.add(cv[t]);
-                csum += cv[t];
-            }
-        }
-        if (mode == kEntangled && in) prev0 = G->c[r][src];
-        int32_t gv = 0;
-        if ((op == NE_OP_ADD || op == NE_OP_INNER) && in) {
-            gv = opd[p];
-            bd.add(gv);
-        }
-        int64_t dl[NS][1];
-#pragma unroll
-        for (int t = 0; t < NS; ++t) {
-            dl[t][0] = 0;
-            if (!slot_live(mode, M, r, lost, t, nslots)) continue;
-            int64_t x, gs = gv;
-            if (mode == kEntangled) {
-                x = ent(cv[t], t == 0 ? prev0 : cv[t == 0 ? 0 : t - 1], l);
-                gs = ent(gv, gv, l);  // footnote 3: the added vector is entangled too
-            } else if (mode == kChecksum && t == M) {
-                x = csum;
-                gs = (int64_t)M * gv;  // checksum of the M added operands
+        for (int v = 0; v < V; ++v) src[v] = p + v < n ? p + v : 0;
+        if (op == NE_OP_PERM) {
+            if (full) {
+                load_vec<V>(opd + p, src);
             } else {
-                x = cv[t];
+#pragma unroll
+                for (int v = 0; v < V; ++v) src[v] = p + v < n ? opd[p + v] : 0;
             }
-            uint64_t y;
-            switch (op) {
-            case NE_OP_SCALE: y = (uint64_t)x * (uint64_t)sv; break;
-            case NE_OP_ADD: y = (uint64_t)x + (uint64_t)gs; break;
-            case NE_OP_INNER: y = (uint64_t)x * (uint64_t)(int64_t)gv; break;
-            default: y = (uint64_t)x; break;  // permutation: the gather above
-            }
-            if (op == NE_OP_INNER)
-                iacc[t] += in ? y : 0;
-            else
-                dl[t][0] = (int64_t)y;
+#pragma unroll
+            for (int v = 0; v < V; ++v) src[v] = src[v] < 0 ? 0 : (src[v] >= n ? n - 1 : src[v]);
         }
-        if (op != NE_OP_INNER) epilogue<NS, 1>(G, mode, M, r, lost, l, pb, n - pb, loc, dl, flag);
+        auto load = [&](const int32_t *base, int32_t (&x)[V]) {
+            if (op != NE_OP_PERM && full) {
+                load_vec<V>(base + p, x);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) x[v] = p + v < n ? base[src[v]] : 0;
+            }
+        };
+        // Inputs in slot order; prev0: the partner of slot 0 (stream r).
+        int32_t cv[NS][V], prev0[V], csum[V], gv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) csum[v] = prev0[v] = gv[v] = 0;
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) cv[t][v] = 0;
+            if (t < M) {
+                load(G->c[sst[t]], cv[t]);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    bd.add(cv[t][v]);
+                    csum[v] += cv[t][v];
+                }
+            }
+        }
+        if (mode == kEntangled) load(G->c[r], prev0);
+        if (op == NE_OP_ADD || op == NE_OP_INNER) {
+            if (full) {
+                load_vec<V>(opd + p, gv);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) gv[v] = p + v < n ? opd[p + v] : 0;
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) bd.add(gv[v]);
+        }
+        int64_t dl[NS][V];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                dl[t][v] = 0;
+                if (!slot_live(mode, M, r, lost, t, nslots)) continue;
+                int64_t x, gs = gv[v];
+                if (mode == kEntangled) {
+                    x = ent(cv[t][v], t == 0 ? prev0[v] : cv[t == 0 ? 0 : t - 1][v], l);
+                    gs = ent(gv[v], gv[v], l);  // footnote 3: the added vector is entangled too
+                } else if (mode == kChecksum && t == M) {
+                    x = csum[v];
+                    gs = (int64_t)M * gv[v];  // checksum of the M added operands
+                } else {
+                    x = cv[t][v];
+                }
+                uint64_t y;
+                switch (op) {
+                case NE_OP_SCALE: y = (uint64_t)x * (uint64_t)sv; break;
+                case NE_OP_ADD: y = (uint64_t)x + (uint64_t)gs; break;
+                case NE_OP_INNER: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
+                default: y = (uint64_t)x; break;  // permutation: the gather above
+                }
+                if (op == NE_OP_INNER)
+                    iacc[t] += (p + v < n) ? y : 0;
+                else
+                    dl[t][v] = (int64_t)y;
+            }
+        }
+        if (op == NE_OP_INNER) continue;
+        recover_inplace<NS, V>(mode, M, r, lost, l, dl, flag);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            if (t >= M || (mode != kEntangled && mode != kChecksum && lost && t == r)) continue;
+            int64_t *o = G->out[sst[t]] + p;
+            if (full) {
+#pragma unroll
+                for (int v = 0; v < V; v += 2) *reinterpret_cast<I64x2 *>(o + v) = I64x2{dl[t][v], dl[t][v + 1]};
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (p + v < n) o[v] = dl[t][v];
+            }
+        }
     }
     if (op == NE_OP_INNER) {
         __shared__ uint64_t part[kBlock / 64][NS];

@@ -38,7 +38,7 @@ struct ne_plan {
 namespace {
 
 constexpr int kConvStepsDefault = 4;
-constexpr int kStreamStepsDefault = 16;
+constexpr int kStreamStepsDefault = 4;
 constexpr size_t kMaxLds = 160 * 1024;
 
 // Fewest balanced base-256 digits (each in [-128, 127]) that represent every
@@ -97,7 +97,7 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
         if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
         if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
         for (int m = 0; m < u.M; ++m) {
-            if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 8))
+            if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 16))
                 return fail(NE_EINVAL);
         }
         int64_t n_out;
@@ -113,6 +113,7 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
         if (u.op == NE_OP_ADD || u.op == NE_OP_INNER || u.op == NE_OP_PERM) {
             if (u.n_operand != u.n || (u.n > 0 && !u.operand)) return fail(NE_EINVAL);
         }
+        if (u.operand && !aligned(u.operand, 16)) return fail(NE_EINVAL);
         if (u.op == NE_OP_PERM && u.n > INT32_MAX) return fail(NE_EUNSUP);
 
         // Worst-case output magnitude from the declared input range.
@@ -217,8 +218,9 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
             st.mfma_macs += slots_run * nstrips * conv_steps * (int64_t)kConvTile * 64 * G.nch *
                             la * lb;
         } else {
+            // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = stream_steps;
-            const int64_t strip = (int64_t)stream_steps * 256;
+            const int64_t strip = (int64_t)stream_steps * 256 * (cls == 0 ? kStreamV0 : kStreamV1);
             const int64_t nstrips = (u.n + strip - 1) / strip;
             auto key = std::make_tuple(0, cls, 0, 0);
             auto &v = bucket_items[key];
