@@ -49,8 +49,11 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--conv-steps", type=int, default=0)
     p.add_argument("--stream-steps", type=int, default=0)
-    p.add_argument("--config", default="batched", choices=("batched", "small", "uneven", "long"),
+    p.add_argument("--config", default="batched",
+                   choices=("batched", "small", "uneven", "long", "serve"),
                    help="workload; the benchmark line is the batched one")
+    p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
+    p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
     p.add_argument("--only", default=None, choices=("entangled", "plain", "plain_same", "checksum"),
                    help="time one mode only (profiling)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -112,6 +115,8 @@ def main():
 
     dev = torch.device("cuda:0")
     ne.load()
+    if args.config == "serve":
+        return serve_line(args, wl)
     t_gen = time.perf_counter()
     cfg = CONFIGS[args.config]
     groups, in_bits, describe = cfg(wl, args)
@@ -238,6 +243,33 @@ def main():
 
     if not args.no_cpu and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(groups, np)
+    print(json.dumps(line), flush=True)
+
+
+def serve_line(args, wl):
+    """Serving: Poisson arrivals (2000 jobs/s), M in {3,4,5}, n log-uniform
+    [2^10, 2^20], taps log-uniform [16, 1024], 1% single-stream drops,
+    admission by HBM footprint, continuous batching over 4 HIP streams."""
+    from paper_1509_03838_amd.serve import Server
+    warm = wl.serving_jobs(seed=wl.SEED_BASE + 40, count=200)
+    srv = Server(hbm_budget=args.budget_mib << 20, lanes=4, max_batch=64)
+    srv.run(warm)
+    jobs = wl.serving_jobs(count=args.jobs)
+    rep = srv.run(jobs)
+    line = {
+        "metric": METRIC, "value": round(rep.gout_per_s, 3), "unit": "Gout-samples/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(rep.makespan_s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson 2000 jobs/s, M in {3,4,5}, n log-uniform "
+                               "[2^10,2^20] int32 in [-2^10,2^10), taps log-uniform [16,1024], "
+                               "1% single-stream drops, HBM-footprint admission, 4 lanes",
+                   "jobs": rep.jobs, "budget_mib": args.budget_mib},
+        "latency_ms": {"p50": round(rep.p50_ms, 3), "p99": round(rep.p99_ms, 3),
+                       "mean": round(rep.mean_ms, 3), "max": round(rep.max_ms, 3)},
+        "serving": {k: (round(v, 4) if isinstance(v, float) else v)
+                    for k, v in rep.as_dict().items()},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -43,6 +43,7 @@
 #ifndef NE_H
 #define NE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -279,6 +280,24 @@ typedef struct ne_plan ne_plan;
  */
 ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
                          const ne_tuning *tuning, ne_plan **plan);
+/*
+ * Device bytes a plan over these groups needs when the caller provides the
+ * memory (ne_plan_create_in). Host-only; validates like ne_plan_create.
+ */
+ne_status ne_plan_workspace_size(const ne_group *groups, int32_t n_groups, int32_t mode,
+                                 const ne_tuning *tuning, size_t *bytes);
+/*
+ * ne_plan_create without any device allocation or synchronisation: the plan
+ * tables live in the caller's `workspace` (device memory, 256-byte aligned,
+ * at least ne_plan_workspace_size bytes) and are uploaded asynchronously on
+ * `stream`; the plan must be run on that stream (or after it). For callers
+ * that run many short plans concurrently (serving): ne_plan_destroy then only
+ * frees host memory, and must be called only after `stream` has completed the
+ * upload (for example after the plan's last run has completed).
+ */
+ne_status ne_plan_create_in(const ne_group *groups, int32_t n_groups, int32_t mode,
+                            const ne_tuning *tuning, void *workspace, size_t workspace_bytes,
+                            ne_stream stream, ne_plan **plan);
 /* Enqueue one run of the whole batch on `stream`. Allocates nothing. */
 ne_status ne_plan_run(ne_plan *plan, ne_stream stream);
 /* Record one run into a hipGraph (by stream capture on `stream`); later

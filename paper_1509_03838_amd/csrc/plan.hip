@@ -24,6 +24,11 @@ struct ne_plan {
     int mode = 0;
     std::vector<GroupDev> host_groups;
     std::vector<Bucket> buckets;
+    std::vector<Item> items;
+    std::vector<uint32_t> inner;
+    std::vector<unsigned char> image;  // host copy of the device tables, uploaded verbatim
+    size_t sz_groups = 0, sz_items = 0, sz_inner = 0, sz_acc = 0, sz_flags = 0;
+    bool owns_arena = false;
     unsigned char *arena = nullptr;  // device: groups | items | inner idx | acc | flags
     GroupDev *d_groups = nullptr;
     Item *d_items = nullptr;
@@ -60,8 +65,8 @@ inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0
 
 extern "C" {
 
-ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
-                         const ne_tuning *tuning, ne_plan **out_plan)
+static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mode,
+                            const ne_tuning *tuning, ne_plan **out_plan)
 {
     if (!out_plan || n_groups < 0 || (n_groups > 0 && !groups)) return NE_EINVAL;
     if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
@@ -257,46 +262,103 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
 
     // One device arena: groups | items | inner index | accumulators | flags.
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t sz_groups = up(sizeof(GroupDev) * std::max(1, n_groups));
-    const size_t sz_items = up(sizeof(Item) * std::max<size_t>(1, all_items.size()));
-    const size_t sz_inner = up(sizeof(uint32_t) * std::max<size_t>(1, inner_groups.size()));
-    const size_t sz_acc = up(sizeof(uint64_t) * kMaxSlots * std::max<size_t>(1, inner_groups.size()));
-    const size_t sz_flags = 256;
-    const size_t total = sz_groups + sz_items + sz_inner + sz_acc + sz_flags;
-    hipError_t e = hipMalloc((void **)&plan->arena, total);
+    plan->sz_groups = up(sizeof(GroupDev) * std::max(1, n_groups));
+    plan->sz_items = up(sizeof(Item) * std::max<size_t>(1, all_items.size()));
+    plan->sz_inner = up(sizeof(uint32_t) * std::max<size_t>(1, inner_groups.size()));
+    plan->sz_acc = up(sizeof(uint64_t) * kMaxSlots * std::max<size_t>(1, inner_groups.size()));
+    plan->sz_flags = 256;
+    plan->items = std::move(all_items);
+    plan->inner = std::move(inner_groups);
+    plan->stats = st;
+    *out_plan = plan;
+    return NE_OK;
+}
+
+static size_t plan_bytes(const ne_plan *p)
+{
+    return p->sz_groups + p->sz_items + p->sz_inner + p->sz_acc + p->sz_flags;
+}
+
+// Points the plan at its device arena and lays out the host image of the
+// tables (accumulators and flags zero) for one verbatim upload.
+static void plan_place(ne_plan *plan, unsigned char *arena)
+{
+    plan->arena = arena;
+    unsigned char *p = arena;
+    plan->d_groups = (GroupDev *)p;
+    p += plan->sz_groups;
+    plan->d_items = (Item *)p;
+    p += plan->sz_items;
+    plan->d_inner = (uint32_t *)p;
+    p += plan->sz_inner;
+    uint64_t *d_acc = (uint64_t *)p;
+    p += plan->sz_acc;
+    plan->d_flags = (uint32_t *)p;
+    for (size_t i = 0; i < plan->inner.size(); ++i)
+        plan->host_groups[plan->inner[i]].acc = d_acc + kMaxSlots * i;
+    plan->image.assign(plan_bytes(plan), 0);
+    unsigned char *h = plan->image.data();
+    memcpy(h, plan->host_groups.data(), sizeof(GroupDev) * plan->host_groups.size());
+    memcpy(h + plan->sz_groups, plan->items.data(), sizeof(Item) * plan->items.size());
+    memcpy(h + plan->sz_groups + plan->sz_items, plan->inner.data(),
+           sizeof(uint32_t) * plan->inner.size());
+}
+
+ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
+                         const ne_tuning *tuning, ne_plan **out_plan)
+{
+    ne_plan *plan = nullptr;
+    ne_status st = plan_build(groups, n_groups, mode, tuning, &plan);
+    if (st != NE_OK) return st;
+    unsigned char *arena = nullptr;
+    hipError_t e = hipMalloc((void **)&arena, plan_bytes(plan));
     if (e != hipSuccess) {
         delete plan;
         (void)hipGetLastError();
         return NE_ENOMEM;
     }
-    unsigned char *p = plan->arena;
-    plan->d_groups = (GroupDev *)p;
-    p += sz_groups;
-    plan->d_items = (Item *)p;
-    p += sz_items;
-    plan->d_inner = (uint32_t *)p;
-    p += sz_inner;
-    uint64_t *d_acc = (uint64_t *)p;
-    p += sz_acc;
-    plan->d_flags = (uint32_t *)p;
-    for (size_t i = 0; i < inner_groups.size(); ++i)
-        plan->host_groups[inner_groups[i]].acc = d_acc + kMaxSlots * i;
-
-    std::vector<unsigned char> zeros(sz_acc + sz_flags, 0);
-    e = hipMemcpy(plan->d_groups, plan->host_groups.data(), sizeof(GroupDev) * n_groups,
-                  hipMemcpyHostToDevice);
-    if (e == hipSuccess && !all_items.empty())
-        e = hipMemcpy(plan->d_items, all_items.data(), sizeof(Item) * all_items.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess && !inner_groups.empty())
-        e = hipMemcpy(plan->d_inner, inner_groups.data(), sizeof(uint32_t) * inner_groups.size(),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_acc, zeros.data(), sz_acc + sz_flags, hipMemcpyHostToDevice);
+    plan->owns_arena = true;
+    plan_place(plan, arena);
+    e = hipMemcpy(arena, plan->image.data(), plan->image.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         ne_plan_destroy(plan);
         return hip_fail(e);
     }
-    plan->stats = st;
+    *out_plan = plan;
+    return NE_OK;
+}
+
+ne_status ne_plan_workspace_size(const ne_group *groups, int32_t n_groups, int32_t mode,
+                                 const ne_tuning *tuning, size_t *bytes)
+{
+    if (!bytes) return NE_EINVAL;
+    ne_plan *plan = nullptr;
+    ne_status st = plan_build(groups, n_groups, mode, tuning, &plan);
+    if (st != NE_OK) return st;
+    *bytes = plan_bytes(plan);
+    delete plan;
+    return NE_OK;
+}
+
+ne_status ne_plan_create_in(const ne_group *groups, int32_t n_groups, int32_t mode,
+                            const ne_tuning *tuning, void *workspace, size_t workspace_bytes,
+                            ne_stream stream, ne_plan **out_plan)
+{
+    if (!workspace || ((uintptr_t)workspace & 255u)) return NE_EINVAL;
+    ne_plan *plan = nullptr;
+    ne_status st = plan_build(groups, n_groups, mode, tuning, &plan);
+    if (st != NE_OK) return st;
+    if (plan_bytes(plan) > workspace_bytes) {
+        delete plan;
+        return NE_EINVAL;
+    }
+    plan_place(plan, (unsigned char *)workspace);
+    hipError_t e = hipMemcpyAsync(workspace, plan->image.data(), plan->image.size(),
+                                  hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(e);
+    }
     *out_plan = plan;
     return NE_OK;
 }
@@ -383,7 +445,7 @@ ne_status ne_plan_destroy(ne_plan *plan)
     if (!plan) return NE_OK;
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->arena) (void)hipFree(plan->arena);
+    if (plan->arena && plan->owns_arena) (void)hipFree(plan->arena);
     delete plan;
     return NE_OK;
 }

@@ -23,7 +23,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
            "ne_plain_apply", "ne_checksum", "ne_checksum_recover", "ne_plan_create",
            "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
-           "ne_plan_stats_get", "ne_plan_destroy")
+           "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -89,6 +89,10 @@ def load() -> ctypes.CDLL:
         "ne_plan_flags": (_i32, [_P, ctypes.POINTER(ctypes.c_uint32), _i32]),
         "ne_plan_stats_get": (_i32, [_P, ctypes.POINTER(StatsC)]),
         "ne_plan_destroy": (_i32, [_P]),
+        "ne_plan_workspace_size": (_i32, [ctypes.POINTER(GroupC), _i32, _i32,
+                                          ctypes.POINTER(TuningC), ctypes.POINTER(ctypes.c_size_t)]),
+        "ne_plan_create_in": (_i32, [ctypes.POINTER(GroupC), _i32, _i32, ctypes.POINTER(TuningC),
+                                     _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_void_p)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -269,20 +273,40 @@ class GroupSpec:
         return g
 
 
+def workspace_size(groups: Sequence[GroupSpec], mode: str = "entangled", conv_steps: int = 0,
+                   stream_steps: int = 0) -> int:
+    arr = (GroupC * max(1, len(groups)))()
+    for i, g in enumerate(groups):
+        arr[i] = g.to_c()
+    tun = TuningC(conv_steps, stream_steps)
+    size = ctypes.c_size_t()
+    _check("ne_plan_workspace_size", load().ne_plan_workspace_size(
+        arr, len(groups), MODES[mode], ctypes.byref(tun), ctypes.byref(size)))
+    return size.value
+
+
 class Plan:
-    """A batched run of many groups (ne_plan_*)."""
+    """A batched run of many groups (ne_plan_*). With `workspace` (a device
+    uint8 tensor of at least workspace_size() bytes) and `stream`, the plan
+    allocates nothing and uploads its tables asynchronously on that stream."""
 
     def __init__(self, groups: Sequence[GroupSpec], mode: str = "entangled", conv_steps: int = 0,
-                 stream_steps: int = 0):
+                 stream_steps: int = 0, workspace=None, stream=None):
         L = load()
         self._groups = list(groups)  # keeps the tensors alive
+        self._ws = workspace
         arr = (GroupC * max(1, len(self._groups)))()
         for i, g in enumerate(self._groups):
             arr[i] = g.to_c()
         tun = TuningC(conv_steps, stream_steps)
         h = ctypes.c_void_p()
-        _check("ne_plan_create", L.ne_plan_create(arr, len(self._groups), MODES[mode],
-                                                  ctypes.byref(tun), ctypes.byref(h)))
+        if workspace is None:
+            _check("ne_plan_create", L.ne_plan_create(arr, len(self._groups), MODES[mode],
+                                                      ctypes.byref(tun), ctypes.byref(h)))
+        else:
+            _check("ne_plan_create_in", L.ne_plan_create_in(
+                arr, len(self._groups), MODES[mode], ctypes.byref(tun), _ptr(workspace),
+                workspace.numel() * workspace.element_size(), _stream(stream), ctypes.byref(h)))
         self._h = h
 
     def run(self, stream=None):
