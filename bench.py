@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     p.add_argument("--conv-steps", type=int, default=0)
     p.add_argument("--stream-steps", type=int, default=0)
+    p.add_argument("--no-autotune", action="store_true",
+                   help="use the default tile steps instead of the autotuner's")
     p.add_argument("--config", default="batched",
                    choices=("batched", "small", "uneven", "long", "serve"),
                    help="workload; the benchmark line is the batched one")
@@ -129,9 +131,18 @@ def main():
            for g, no in zip(groups, n_outs)]
     stream = torch.cuda.Stream()
 
+    tuner = None
+    if not args.no_autotune and not args.conv_steps and not args.stream_steps:
+        from paper_1509_03838_amd.tune import Tuner
+        tuner = Tuner(os.environ.get("NE_TUNE_CACHE", os.path.join(ROOT, "gpurun_out",
+                                                                   "ne_tune.json")))
+    tuned = {}
+
     def make_plan(mode, lost=-1):
         specs = [ne.GroupSpec(g.op, c_dev[i], k_dev[i], out[i], g.scalar, lost, in_bits)
                  for i, g in enumerate(groups)]
+        if tuner is not None:
+            tuned.update(tuner.tune(specs, mode))
         plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps)
         plan.capture(stream)
         return plan
@@ -228,6 +239,7 @@ def main():
                        out_samples=samples, **({"l": ne.params(M0)[0]} if M0 >= 3 else {})),
         "roofline": roof,
         "wall_ms_per_step": round(ms_wall, 4),
+        "tuned_steps": tuned_summary(tuned, main_mode),
     }
     if "plain" in results:
         line["baselines"] = {
@@ -271,6 +283,18 @@ def serve_line(args, wl):
                     for k, v in rep.as_dict().items()},
     }
     print(json.dumps(line), flush=True)
+
+
+def tuned_summary(tuned, mode):
+    """The autotuner's choices for the timed mode: the table itself when it
+    is short, else a histogram {steps: classes}."""
+    mine = {k: v for k, v in tuned.items() if k.startswith(mode + "|")}
+    if len(mine) <= 8:
+        return mine
+    hist = {}
+    for v in mine.values():
+        hist[str(v)] = hist.get(str(v), 0) + 1
+    return {"classes": len(mine), "steps_histogram": hist}
 
 
 def stats_kernel_name(stats, groups, mode):

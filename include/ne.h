@@ -240,6 +240,10 @@ typedef struct ne_group {
     int32_t in_bits;     /* 1..31 (conv) or 1..32: every sample and operand
                             value v satisfies -2^(in_bits-1) <= v < 2^(in_bits-1);
                             violations are flagged (NE_FLAG_INPUT_RANGE) */
+    int32_t steps;       /* tile steps per block for this group (conv: 1024
+                            outputs each; element-wise: see ne_tuning); 0: the
+                            plan's ne_tuning value */
+    int32_t reserved;    /* 0 */
     const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
     const int32_t *operand;           /* device int32 taps / vector /
                                          permutation indices, 16-byte aligned;

@@ -100,6 +100,9 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         if (u.M < minM || u.M > kFusedMaxM || u.n < 0 || u.in_bits < 1 || u.in_bits > 32)
             return fail(NE_EINVAL);
         if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
+        if (u.steps < 0 || u.steps > 4096) return fail(NE_EINVAL);
+        const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
+        const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
         if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
         for (int m = 0; m < u.M; ++m) {
             if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 16))
@@ -201,7 +204,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // Neighbouring digit sums merge in int32 when
             // |acc_s| + 256 |acc_{s+1}| < 2^31, |acc_s| <= min(la, lb) 64 nch 2^14.
             G.acc16 = (int64_t)257 * std::min(la, lb) * 64 * G.nch * 16384 < ((int64_t)1 << 31);
-            G.steps = conv_steps;
+            G.steps = g_conv_steps;
             // int32 accumulation: a digit product is at most 2^14, summed over
             // 64 nch inputs and at most min(la, lb) digit pairs per shift.
             if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
@@ -211,21 +214,21 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // (M x 4 KiB, only when it fits: the prefetch is an optimisation)
             size_t lds = (size_t)G.nch * lb * 1024 + (size_t)nplanes * (la | 1) * G.ring;
             if (lds > kMaxLds) return fail(NE_EUNSUP);
-            G.dma = lds + (size_t)u.M * 4096 <= kMaxLds && conv_steps > 1;
+            G.dma = lds + (size_t)u.M * 4096 <= kMaxLds && g_conv_steps > 1;
             if (G.dma) lds += (size_t)u.M * 4096;
-            const int64_t strip = (int64_t)conv_steps * kConvTile;
+            const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
             auto key = std::make_tuple(1, cls, la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             bucket_lds[key] = std::max(bucket_lds[key], lds);
             const int64_t slots_run = G.nslots - G.lost;
-            st.mfma_macs += slots_run * nstrips * conv_steps * (int64_t)kConvTile * 64 * G.nch *
+            st.mfma_macs += slots_run * nstrips * g_conv_steps * (int64_t)kConvTile * 64 * G.nch *
                             la * lb;
         } else {
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
-            G.steps = stream_steps;
-            const int64_t strip = (int64_t)stream_steps * 256 * (cls == 0 ? kStreamV0 : kStreamV1);
+            G.steps = g_stream_steps;
+            const int64_t strip = (int64_t)g_stream_steps * 256 * (cls == 0 ? kStreamV0 : kStreamV1);
             const int64_t nstrips = (u.n + strip - 1) / strip;
             auto key = std::make_tuple(0, cls, 0, 0);
             auto &v = bucket_items[key];

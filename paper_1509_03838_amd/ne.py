@@ -35,6 +35,7 @@ class GroupC(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("M", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("n_operand", ctypes.c_int64), ("scalar", ctypes.c_int64),
                 ("lost", ctypes.c_int32), ("in_bits", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("c", ctypes.c_void_p * FUSED_MAX_M), ("operand", ctypes.c_void_p),
                 ("out", ctypes.c_void_p * FUSED_MAX_M)]
 
@@ -247,9 +248,10 @@ class GroupSpec:
     for scale), M int64 output tensors of n_out elements."""
 
     def __init__(self, op: str, c: Sequence, operand, out: Sequence, scalar: int = 0,
-                 lost: int = -1, in_bits: int = 32):
+                 lost: int = -1, in_bits: int = 32, steps: int = 0):
         self.op, self.c, self.operand, self.out = op, list(c), operand, list(out)
         self.scalar, self.lost, self.in_bits = int(scalar), int(lost), int(in_bits)
+        self.steps = int(steps)
 
     def to_c(self) -> GroupC:
         import torch
@@ -265,6 +267,7 @@ class GroupSpec:
         g.scalar = self.scalar
         g.lost = self.lost
         g.in_bits = self.in_bits
+        g.steps = self.steps
         for m, t in enumerate(self.c):
             g.c[m] = _ptr(t)
         for m, t in enumerate(self.out):

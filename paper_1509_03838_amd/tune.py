@@ -1,0 +1,108 @@
+"""Autotuner for the fused executor's tile steps.
+
+The fused kernels process a strip of `steps` tiles per block (convolution:
+1024 outputs per step; element-wise: 256 lanes x 4 or 2 positions per
+step). Longer strips amortise the per-block set-up (the Toeplitz operand, the
+first window with its halo) but leave fewer blocks to balance the load; the
+best length depends on the operation, M, the digit counts and the sizes. The
+tuner groups a batch into workload classes, times every candidate step count
+on a few representative groups of each class with HIP events, and keeps the
+fastest per class in a JSON cache on disk, so later plans (and later
+processes) reuse the choice without timing.
+
+Class key: convolution (mode, M, in_bits, K bucket, n bucket); element-wise
+(mode, op, M <= 4 or not, n bucket); K buckets are powers of two, n buckets
+powers of four.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Sequence
+
+from . import ne
+
+CONV_CANDIDATES = (1, 2, 4, 8, 16)
+STREAM_CANDIDATES = (1, 2, 4, 8)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ne_tune.json")
+
+
+def _bucket(x: int) -> int:
+    return max(0, int(x).bit_length() - 1)
+
+
+def class_key(spec: ne.GroupSpec, mode: str) -> str:
+    n = spec.c[0].numel() if spec.c else 0
+    nb = _bucket(n) // 2
+    if spec.op == "conv":
+        K = spec.operand.numel() if spec.operand is not None else 0
+        return f"{mode}|conv|M{len(spec.c)}|b{spec.in_bits}|K{_bucket(K)}|n{nb}"
+    return f"{mode}|{spec.op}|M{'<=4' if len(spec.c) <= 4 else '>4'}|n{nb}"
+
+
+class Tuner:
+    def __init__(self, cache_path: str | None = DEFAULT_CACHE, repeats: int = 3,
+                 max_groups: int = 8):
+        self.path, self.repeats, self.max_groups = cache_path, repeats, max_groups
+        self.cache: dict[str, int] = {}
+        if cache_path and os.path.exists(cache_path):
+            try:
+                with open(cache_path) as f:
+                    data = json.load(f)
+                self.cache = {k: int(v) for k, v in data.get("steps", {}).items()}
+            except (OSError, ValueError):
+                self.cache = {}
+
+    def save(self):
+        if not self.path:
+            return
+        os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
+        tmp = self.path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump({"steps": self.cache}, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def _time(self, specs: Sequence[ne.GroupSpec], mode: str, steps: int) -> float:
+        import torch
+        for sp in specs:
+            sp.steps = steps
+        plan = ne.Plan(specs, mode)
+        try:
+            plan.run()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(self.repeats):
+                plan.run()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / self.repeats
+        finally:
+            plan.close()
+
+    def tune(self, specs: Sequence[ne.GroupSpec], mode: str = "entangled") -> dict[str, int]:
+        """Sets `steps` on every spec (timing the classes not cached yet) and
+        returns the class -> steps table used."""
+        classes: dict[str, list[ne.GroupSpec]] = {}
+        for sp in specs:
+            classes.setdefault(class_key(sp, mode), []).append(sp)
+        changed = False
+        for key, members in classes.items():
+            if key in self.cache:
+                continue
+            # representatives: the largest groups of the class
+            reps = sorted(members, key=lambda s: -s.c[0].numel())[:self.max_groups]
+            saved = [s.steps for s in reps]
+            cands = CONV_CANDIDATES if reps[0].op == "conv" else STREAM_CANDIDATES
+            times = {c: self._time(reps, mode, c) for c in cands}
+            for s, v in zip(reps, saved):
+                s.steps = v
+            self.cache[key] = min(times, key=times.get)
+            changed = True
+        if changed:
+            self.save()
+        for key, members in classes.items():
+            for sp in members:
+                sp.steps = self.cache[key]
+        return {k: self.cache[k] for k in classes}
