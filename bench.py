@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
 CSRC = os.path.join(ROOT, "paper_1509_03838_amd", "csrc")
 # Sources that define the fused convolution kernel and its launch.
-KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("fused_kernels.h", "fused.h", "fused_conv_impl.h",
-                                               "plan.hip")]
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("fused_kernels.h", "fused.h", "fused_conv.hip",
+                                               "conv_variants.h", "plan.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_fused_batched_traffic.txt")
 
 

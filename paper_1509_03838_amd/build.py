@@ -12,8 +12,13 @@ LIB = os.path.join(HERE, "libne.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "fused_conv4.hip",
-           "fused_conv9.hip", "plan.hip"]
+SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "plan.hip"]
+
+# fused_conv.hip is compiled once per (kernel class, slot count): entangled
+# groups of 3..8 streams, plain groups of 1..8, checksum groups of 2..8 data
+# streams (3..9 slots).
+CONV_VARIANTS = ([(0, n) for n in range(3, 9)] + [(1, n) for n in range(1, 9)] +
+                 [(2, n) for n in range(3, 10)])
 
 # Packed-FP32 instructions are disabled for all device code. Matrix-core
 # results stay in ordinary VGPRs (no accumulation-register copies in the
@@ -24,20 +29,29 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    units = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
+    units += [("fused_conv.hip", f"fused_conv_{k}_{n}.o", [f"-DNE_KCLASS={k}", f"-DNE_SLOTS={n}"])
+              for k, n in CONV_VARIANTS]
     objs = []
-    procs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, "_build", src.replace(".hip", ".o"))
-        os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd)))
-        objs.append(obj)
-    for src, p in procs:
+    pending = list(units)
+    running = []
+    while pending or running:
+        while pending and len(running) < jobs:
+            src, o, defs = pending.pop(0)
+            obj = os.path.join(CSRC, "_build", o)
+            os.makedirs(os.path.dirname(obj), exist_ok=True)
+            cmd = [HIPCC, *FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((o, subprocess.Popen(cmd)))
+            objs.append(obj)
+        o, p = running.pop(0)
         if p.wait() != 0:
-            raise RuntimeError(f"hipcc failed on {src}")
+            for _, q in running:
+                q.wait()
+            raise RuntimeError(f"hipcc failed on {o}")
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

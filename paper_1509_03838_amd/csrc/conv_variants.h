@@ -1,0 +1,88 @@
+// Digit counts of the fused convolution and the set of kernel variants they
+// call for (private to libne). Shared by the planner, which picks the digit
+// counts of a group, and by the kernel translation units, which instantiate
+// exactly the variants some group can need, so the two cannot disagree.
+//
+// A variant is (kernel class, slot count, LA, LB):
+//   kernel class 0: entangled groups, M = slots (M >= 3);
+//   kernel class 1: plain and plain-same groups, M = slots;
+//   kernel class 2: checksum groups, M = slots - 1 data streams + their sum.
+#pragma once
+
+#include <stdint.h>
+
+namespace ne {
+
+constexpr int kConvClassEntangled = 0;
+constexpr int kConvClassPlain = 1;
+constexpr int kConvClassChecksum = 2;
+
+// Fewest balanced base-256 digits (each in [-128, 127]) that represent every
+// integer in [-neg, pos]: L digits reach -128 R and 127 R, R = (256^L - 1)/255.
+constexpr int digits_for(unsigned __int128 neg, unsigned __int128 pos)
+{
+    unsigned __int128 R = 0, p = 1;
+    for (int L = 1; L <= 16; ++L) {
+        R += p;
+        p *= 256;
+        if (128 * R >= neg && 127 * R >= pos) return L;
+    }
+    return 17;
+}
+
+// Shift l of Table I's rule at w = 64 (l = ceil(w/M), k = w - (M-1) l, or
+// l = k = floor(w/M) when k would be negative).
+constexpr int table1_shift64(int M)
+{
+    int l = (64 + M - 1) / M;
+    if (64 - (M - 1) * l < 0) l = 64 / M;
+    return l;
+}
+
+struct DigitCounts {
+    int la, lb;
+};
+
+// Digits of the data words and of the taps of a convolution group whose
+// inputs and taps lie in [-2^(b-1), 2^(b-1) - 1]. Entangled words
+// c + 2^l c' lie in (2^l + 1) times that range (plain-same groups use the
+// same digit count on raw words, so that both modes run one datapath); the
+// checksum stream in M times that range.
+// mode: 0 entangled, 1 plain, 2 plain-same, 3 checksum (the plan's modes).
+constexpr DigitCounts conv_digits(int mode, int M, int in_bits)
+{
+    const unsigned __int128 B = (unsigned __int128)1 << (in_bits - 1);
+    unsigned __int128 neg = B, pos = B - 1;
+    if (mode == 0 || mode == 2) {
+        const unsigned __int128 f = ((unsigned __int128)1 << table1_shift64(M < 3 ? 3 : M)) + 1;
+        neg *= f;
+        pos *= f;
+    } else if (mode == 3) {
+        neg *= (unsigned)M;
+        pos *= (unsigned)M;
+    }
+    return DigitCounts{digits_for(neg, pos), digits_for(B, B - 1)};
+}
+
+constexpr int conv_class_of_mode(int mode) { return mode == 0 ? 0 : (mode == 3 ? 2 : 1); }
+
+// Slots of a group: M, or M + 1 with the checksum stream.
+constexpr int conv_slots(int mode, int M) { return mode == 3 ? M + 1 : M; }
+
+// Whether some group of this kernel class and slot count, with inputs of
+// 1..31 bits, uses digit counts (la, lb).
+constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb)
+{
+    for (int mode = 0; mode < 4; ++mode) {
+        if (conv_class_of_mode(mode) != kclass) continue;
+        const int M = mode == 3 ? slots - 1 : slots;
+        if (M < (mode == 0 ? 3 : (mode == 3 ? 2 : 1))) continue;
+        for (int b = 1; b <= 31; ++b) {
+            const DigitCounts d = conv_digits(mode, M, b);
+            if (d.la == la && d.lb == lb) return true;
+        }
+    }
+    return false;
+}
+
+}  // namespace ne

@@ -46,8 +46,15 @@ struct GroupDev {
     int32_t ring;     // bytes per LDS digit-plane ring (= wlen) (conv)
     int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv)
     int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
+    int32_t skip;     // slot whose operation is not run (the lost stream), or -1
+    int32_t pad_;
     int64_t n, K, n_out;
     int64_t scalar;
+    // Inputs and outputs in slot order. Slot t of an entangled group is
+    // stream (r + 1 + t) mod M, so that slot t entangles with slot t - 1
+    // (slot 0 with slot M - 1, stream r), slots 0 .. M-2 are the M-1 streams
+    // recovery reads and the lost stream, if any, is slot M - 1. In the other
+    // modes slot t is stream t (slot M: the checksum, which has no pointer).
     const int32_t *c[kFusedMaxM];
     const int32_t *operand;
     int64_t *out[kFusedMaxM];
@@ -59,15 +66,16 @@ struct Item {
     uint32_t strip;   // strip index within the group
 };
 
-// Launchers of the fused kernels (fused_conv*.hip, fused.hip).
-template <int NS>
-hipError_t conv_prepare_ns(int la, int lb, size_t lds);
-template <int NS>
-void conv_launch_ns(int la, int lb, const GroupDev *g, const Item *items, uint32_t nitems,
-                    uint32_t *flags, size_t lds, hipStream_t s);
-hipError_t fused_conv_prepare(int cls, int la, int lb, size_t lds);
-void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *items,
-                       uint32_t nitems, uint32_t *flags, size_t lds, hipStream_t s);
+// One fused convolution kernel variant (fused_conv.hip, compiled once per
+// kernel class and slot count).
+struct ConvKernel {
+    void (*launch)(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
+                   size_t lds, hipStream_t s);
+    hipError_t (*prepare)(size_t lds);  // raises the kernel's dynamic LDS limit
+};
+// The variant for (kernel class, slots, LA, LB), or null if none is built.
+const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);
+
 void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
                          uint32_t *flags, hipStream_t s);
 void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,

@@ -1,21 +1,59 @@
-// Launchers of the fused element-wise kernels and dispatch of the fused
-// convolution kernels by slot capacity.
+// Launchers of the fused element-wise kernels and lookup of the fused
+// convolution kernel variants.
 #include "fused_kernels.h"
 
 namespace ne {
 
-hipError_t fused_conv_prepare(int cls, int la, int lb, size_t lds)
-{
-    return cls == 0 ? conv_prepare_ns<4>(la, lb, lds) : conv_prepare_ns<kMaxSlots>(la, lb, lds);
-}
+// Variants built by fused_conv.hip: entangled groups of 3..8 streams, plain
+// groups of 1..8, checksum groups of 2..8 data streams (3..9 slots).
+const ConvKernel *conv_kernel_0_3(int la, int lb);
+const ConvKernel *conv_kernel_0_4(int la, int lb);
+const ConvKernel *conv_kernel_0_5(int la, int lb);
+const ConvKernel *conv_kernel_0_6(int la, int lb);
+const ConvKernel *conv_kernel_0_7(int la, int lb);
+const ConvKernel *conv_kernel_0_8(int la, int lb);
+const ConvKernel *conv_kernel_1_1(int la, int lb);
+const ConvKernel *conv_kernel_1_2(int la, int lb);
+const ConvKernel *conv_kernel_1_3(int la, int lb);
+const ConvKernel *conv_kernel_1_4(int la, int lb);
+const ConvKernel *conv_kernel_1_5(int la, int lb);
+const ConvKernel *conv_kernel_1_6(int la, int lb);
+const ConvKernel *conv_kernel_1_7(int la, int lb);
+const ConvKernel *conv_kernel_1_8(int la, int lb);
+const ConvKernel *conv_kernel_2_3(int la, int lb);
+const ConvKernel *conv_kernel_2_4(int la, int lb);
+const ConvKernel *conv_kernel_2_5(int la, int lb);
+const ConvKernel *conv_kernel_2_6(int la, int lb);
+const ConvKernel *conv_kernel_2_7(int la, int lb);
+const ConvKernel *conv_kernel_2_8(int la, int lb);
+const ConvKernel *conv_kernel_2_9(int la, int lb);
 
-void fused_conv_launch(int cls, int la, int lb, const GroupDev *g, const Item *items,
-                       uint32_t nitems, uint32_t *flags, size_t lds, hipStream_t s)
+const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb)
 {
-    if (cls == 0)
-        conv_launch_ns<4>(la, lb, g, items, nitems, flags, lds, s);
-    else
-        conv_launch_ns<kMaxSlots>(la, lb, g, items, nitems, flags, lds, s);
+    switch (kclass * 16 + slots) {
+    case 3: return conv_kernel_0_3(la, lb);
+    case 4: return conv_kernel_0_4(la, lb);
+    case 5: return conv_kernel_0_5(la, lb);
+    case 6: return conv_kernel_0_6(la, lb);
+    case 7: return conv_kernel_0_7(la, lb);
+    case 8: return conv_kernel_0_8(la, lb);
+    case 17: return conv_kernel_1_1(la, lb);
+    case 18: return conv_kernel_1_2(la, lb);
+    case 19: return conv_kernel_1_3(la, lb);
+    case 20: return conv_kernel_1_4(la, lb);
+    case 21: return conv_kernel_1_5(la, lb);
+    case 22: return conv_kernel_1_6(la, lb);
+    case 23: return conv_kernel_1_7(la, lb);
+    case 24: return conv_kernel_1_8(la, lb);
+    case 35: return conv_kernel_2_3(la, lb);
+    case 36: return conv_kernel_2_4(la, lb);
+    case 37: return conv_kernel_2_5(la, lb);
+    case 38: return conv_kernel_2_6(la, lb);
+    case 39: return conv_kernel_2_7(la, lb);
+    case 40: return conv_kernel_2_8(la, lb);
+    case 41: return conv_kernel_2_9(la, lb);
+    default: return nullptr;
+    }
 }
 
 void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,

@@ -52,7 +52,18 @@ __device__ __forceinline__ int64_t ent(int64_t cur, int64_t prev, int l)
     return (int64_t)((uint64_t)cur + ((uint64_t)prev << l));
 }
 
-__device__ __forceinline__ int64_t *out_ptr(const GroupDev *G, int m) { return G->out[m]; }
+// Global-memory views of the descriptor's stream pointers (the descriptor
+// holds generic pointers; global accesses take scalar base addresses and do
+// not count against the LDS wait counter).
+typedef __attribute__((address_space(1))) int64_t gi64_t;
+typedef __attribute__((address_space(1))) const v4i gv4i_t;
+
+__device__ __forceinline__ void store_out(int64_t *p, int64_t v) { *(gi64_t *)p = v; }
+__device__ __forceinline__ v4i load_in4(const int32_t *p) { return *(gv4i_t *)p; }
+__device__ __forceinline__ int32_t load_in1(const int32_t *p)
+{
+    return *(const __attribute__((address_space(1))) int32_t *)p;
+}
 
 // Running bounds of every input value a thread reads; checked once against
 // the declared range at the end of the kernel.
@@ -63,26 +74,30 @@ struct Bounds {
         lo = min(lo, v);
         hi = max(hi, v);
     }
+    __device__ __forceinline__ void add2(int32_t a, int32_t b)
+    {
+        lo = min(lo, min(a, b));
+        hi = max(hi, max(a, b));
+    }
 };
 
 // Results of one lane: V positions base + loc[v], one entangled (or plain)
-// output per slot. Slot t of an entangled group is stream (r + 1 + t) mod M,
-// so that slots 0 .. M-2 are exactly the M-1 streams recovery reads and slot
-// M-1 is stream r. Slot t of the other modes is stream t (slot M: the
-// checksum).
+// output per slot (slot order: the descriptor's comment).
 //
 // Entangled recovery (64-bit form of eq. (16)-(19), as in the streaming
-// extraction kernel): d_temp's low (M-1)l bits give d_{r-1}; then
-// d_{j-1} = (delta_j - d_j) >> l walking back to d_r. When stream r was not
-// lost its slot is redundant and is checked against the recovered outputs.
+// extraction kernel): d_temp's low (M-1)l bits give the output of slot M-2
+// (stream r - 1); then d_{t-1} = (delta_t - d_t) >> l walks back through
+// slots M-3, ..., 0 to slot M-1 (stream r). When slot M-1 was computed too
+// (no loss) it is redundant and is checked against the recovered outputs.
 template <int NS, int V>
-__device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int r, int lost,
-                                         int l, int64_t base, int64_t lim, const int (&loc)[V],
+__device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int skip, int l,
+                                         int64_t base, int64_t lim, const int (&loc)[V],
                                          const int64_t (&dl)[NS][V], uint32_t &flag)
 {
     if (mode == kEntangled) {
         const int s = 64 - (M - 1) * l;
-        int64_t *o_last = out_ptr(G, (r + M - 1) % M) + base;
+        int64_t *o_last = G->out[M - 2] + base;
+        int64_t *o_wrap = G->out[M - 1] + base;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const bool ok = loc[v] < lim;
@@ -94,19 +109,19 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
                     acc = (acc << l) + (((M + t) & 1) ? (uint64_t)0 - x : x);
                 }
             }
-            int64_t cur = ((int64_t)(acc << s)) >> s;  // d_{r-1}
+            int64_t cur = ((int64_t)(acc << s)) >> s;  // output of slot M-2
             const int64_t d_prev = cur;
-            if (ok) o_last[loc[v]] = cur;
+            if (ok) store_out(o_last + loc[v], cur);
 #pragma unroll
             for (int t = NS - 2; t >= 0; --t) {
                 if (t <= M - 2) {
-                    cur = (int64_t)((uint64_t)dl[t][v] - (uint64_t)cur) >> l;
-                    const int m = (t == 0) ? r : (r + t) % M;
-                    if (ok) (out_ptr(G, m) + base)[loc[v]] = cur;
+                    cur = (int64_t)((uint64_t)dl[t][v] - (uint64_t)cur) >> l;  // slot t-1
+                    int64_t *o = t == 0 ? o_wrap : G->out[t == 0 ? 0 : t - 1] + base;
+                    if (ok) store_out(o + loc[v], cur);
                 }
             }
-            // cur is d_r; with stream r computed, delta_r = d_r + 2^l d_{r-1}
-            if (!lost && ok) {
+            // cur is the output of slot M-1; delta_{M-1} = d_{M-1} + 2^l d_{M-2}
+            if (skip < 0 && ok) {
                 int64_t dr_slot = 0;
 #pragma unroll
                 for (int t = 0; t < NS; ++t)
@@ -125,38 +140,30 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
                 if (t == M) e = (uint64_t)dl[t][v];
 #pragma unroll
             for (int t = 0; t < NS - 1; ++t)
-                if (t < M && !(lost && t == r)) {
+                if (t < M && t != skip) {
                     sum += (uint64_t)dl[t][v];
-                    (out_ptr(G, t) + base)[loc[v]] = dl[t][v];
+                    store_out(G->out[t] + base + loc[v], dl[t][v]);
                 }
-            if (lost)
-                (out_ptr(G, r) + base)[loc[v]] = (int64_t)(e - sum);
+            if (skip >= 0)
+                store_out(G->out[skip] + base + loc[v], (int64_t)(e - sum));
             else if (e != sum)
                 flag |= kFlagMismatch;
         }
     } else {
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            if (t >= M || (lost && t == r)) continue;
-            int64_t *o = out_ptr(G, t) + base;
+            if (t >= M || t == skip) continue;
+            int64_t *o = G->out[t] + base;
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (loc[v] < lim) o[loc[v]] = dl[t][v];
+                if (loc[v] < lim) store_out(o + loc[v], dl[t][v]);
         }
     }
 }
 
-// Stream (plane) that slot t holds.
-__device__ __forceinline__ int slot_stream(int mode, int M, int r, int t)
+__device__ __forceinline__ bool slot_live(int skip, int t, int nslots)
 {
-    return mode == kEntangled ? (r + 1 + t) % M : t;
-}
-
-__device__ __forceinline__ bool slot_live(int mode, int M, int r, int lost, int t, int nslots)
-{
-    if (t >= nslots) return false;
-    if (!lost) return true;
-    return mode == kEntangled ? t != M - 1 : t != r;
+    return t < nslots && t != skip;
 }
 
 // Byte transpose: w[a] = byte a of v[0], v[1], v[2], v[3] (in that order).
@@ -195,86 +202,61 @@ __device__ __forceinline__ constexpr int lap() { return LA | 1; }
 
 __device__ __forceinline__ int plane_off(int o, int lapv) { return (o >> 4) * 16 * lapv + (o & 15); }
 
-// Raw int32 inputs of 4 consecutive positions of every stream, in flight
-// between their (prefetched) global loads and their conversion into digit
-// planes. cl: the stream that entangles into stream 0 (c_{M-1}).
-template <int NS>
+// Raw int32 inputs of 4 consecutive positions of the DM data streams (slot
+// order), in flight between their (prefetched) global loads and their
+// conversion into digit planes.
+template <int DM>
 struct Raw4 {
-    static constexpr int DM = NS < kFusedMaxM ? NS : kFusedMaxM;
     int32_t cv[DM][4];
-    int32_t cl[4];
 };
 
-template <int NS>
-__device__ __forceinline__ void load4(const GroupDev *G, int mode, int M, int64_t p, int64_t n,
-                                      Raw4<NS> &raw)
+template <int DM>
+__device__ __forceinline__ void load4(const GroupDev *G, int64_t p, int64_t n, Raw4<DM> &raw)
 {
-    constexpr int DM = Raw4<NS>::DM;
     const bool full = p >= 0 && p + 4 <= n;
 #pragma unroll
     for (int m = 0; m < DM; ++m) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) raw.cv[m][q] = 0;
-        if (m < M) {
-            if (full) {
-                const int4 v = *reinterpret_cast<const int4 *>(G->c[m] + p);
-                raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (p + q >= 0 && p + q < n) raw.cv[m][q] = G->c[m][p + q];
-            }
-        }
-    }
-    if (mode == kEntangled) {
-        // c_{M-1}, the partner of stream 0, loaded again by pointer (an L1
-        // hit) instead of selected out of the registers with a runtime M.
-        const int32_t *cl = G->c[M - 1];
         if (full) {
-            const int4 v = *reinterpret_cast<const int4 *>(cl + p);
-            raw.cl[0] = v.x; raw.cl[1] = v.y; raw.cl[2] = v.z; raw.cl[3] = v.w;
+            const v4i v = load_in4(G->c[m] + p);
+            raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) raw.cl[q] = (p + q >= 0 && p + q < n) ? cl[p + q] : 0;
+            for (int q = 0; q < 4; ++q)
+                raw.cv[m][q] = (p + q >= 0 && p + q < n) ? load_in1(G->c[m] + p + q) : 0;
         }
     }
 }
 
-// Converts raw inputs of 4 positions into the LA digit planes at ring offset
-// `off`: entanglement (or the checksum sum) happens here.
-template <int LA, int NS>
-__device__ __forceinline__ void store4(const Raw4<NS> &raw, int mode, int M, int l, int nplanes,
-                                       unsigned char *planes, int ring, int off, Bounds &bd)
+// Converts raw inputs of 4 positions into the LA digit planes (one per slot,
+// NP slots) at ring offset `off`: entanglement (or the checksum sum) happens
+// here. Slot t entangles with slot t - 1, slot 0 with slot DM - 1.
+template <int LA, int DM, int NP, int MODE>
+__device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char *planes, int ring,
+                                       int off, Bounds &bd)
 {
-    constexpr int DM = Raw4<NS>::DM;
     constexpr uint64_t C = digit_offset<LA>();
     constexpr int LAP = lap<LA>();
-    int32_t csum[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        csum[q] = 0;
 #pragma unroll
-        for (int m = 0; m < DM; ++m)
-            if (m < M) {
-                bd.add(raw.cv[m][q]);
-                csum[q] += raw.cv[m][q];
-            }
+        for (int m = 0; m + 1 < DM; m += 2) bd.add2(raw.cv[m][q], raw.cv[m + 1][q]);
+        if (DM & 1) bd.add(raw.cv[DM - 1][q]);
     }
 #pragma unroll
-    for (int pl = 0; pl < NS; ++pl) {
-        if (pl >= nplanes) continue;
+    for (int pl = 0; pl < NP; ++pl) {
         uint32_t lo[4], hi[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int64_t x;
-            const int32_t own = pl < DM ? raw.cv[pl < DM ? pl : 0][q] : 0;
-            if (mode == kEntangled) {
-                const int32_t prev = pl == 0 ? raw.cl[q] : raw.cv[pl == 0 ? 0 : (pl - 1) % DM][q];
-                x = ent(own, prev, l);
-            } else if (mode == kChecksum && pl == M) {
-                x = csum[q];
+            if (MODE == kChecksum && pl == DM) {
+                int32_t sum = 0;
+#pragma unroll
+                for (int m = 0; m < DM; ++m) sum += raw.cv[m][q];
+                x = sum;
+            } else if (MODE == kEntangled) {
+                x = ent(raw.cv[pl % DM][q], raw.cv[(pl + DM - 1) % DM][q], l);
             } else {
-                x = own;
+                x = raw.cv[pl % DM][q];
             }
             // (x has LA digits whenever the inputs lie in the declared range,
             // which the plan sized LA for and the kernel verifies.)
@@ -293,23 +275,29 @@ __device__ __forceinline__ void store4(const Raw4<NS> &raw, int mode, int M, int
 
 // ----------------------------------------------------- convolution kernel
 
-template <int LA, int LB, int NS>
+// One variant per kernel class (0 entangled, 1 plain, 2 checksum) and slot
+// count NS, so that the mode, M and the slot loop are compile-time: the
+// descriptor's mode and M must match (the planner picks the variant).
+template <int LA, int LB, int NS, int KCLASS>
 __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
                                                        const Item *__restrict__ items,
                                                        uint32_t nitems, uint32_t *flags)
 {
+    constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
+    constexpr int M = KCLASS == 2 ? NS - 1 : NS;  // data streams
+    constexpr int nplanes = NS;
+    static_assert(M >= 1 && M <= kFusedMaxM, "slot count");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t ii = item_index(nitems);
     if (ii >= nitems) return;
     const Item it = items[ii];
     const GroupDev *G = groups + it.g;
-    const int mode = G->mode, M = G->M, r = G->r, lost = G->lost, l = G->l;
-    const int nslots = G->nslots, nch = G->nch, kp = G->kp, wlen = G->wlen, ring = G->ring;
+    const int skip = G->skip, l = G->l;
+    const int nch = G->nch, kp = G->kp, wlen = G->wlen, ring = G->ring;
     const int steps = G->steps, acc16 = G->acc16, use_dma = G->dma;
     const int64_t n = G->n, K = G->K, n_out = G->n_out;
     const int32_t *__restrict__ g = G->operand;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nplanes = (mode == kChecksum) ? M + 1 : M;
     uint32_t flag = 0;
     Bounds bd;
 
@@ -350,14 +338,14 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     // The digit planes are rings of `ring` bytes (the window 1024 + kp, a
     // multiple of 16, so no 16-byte access wraps): ring offset 0 is position
     // T0 - kp. The first step stages the whole window, every later step only
-    // its 1024 new positions.
+    // its 1024 new positions, at ring offsets that advance by 1024 per step.
     const int64_t T0 = (int64_t)it.strip * steps * kConvTile;
     const int64_t base = T0 - kp;
     {
-        Raw4<NS> raw;
+        Raw4<M> raw;
         for (int gi = tid; gi < (wlen >> 2); gi += kBlock) {
-            load4<NS>(G, mode, M, base + 4 * gi, n, raw);
-            store4<LA, NS>(raw, mode, M, l, nplanes, planes, ring, 4 * gi, bd);
+            load4<M>(G, base + 4 * gi, n, raw);
+            store4<LA, M, nplanes, mode>(raw, l, planes, ring, 4 * gi, bd);
         }
     }
     // The raw int32 inputs of the next step travel HBM -> LDS by direct
@@ -372,8 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         const int64_t p = Tq + 4 * tid;
         if (use_dma && p + 4 <= n) {
 #pragma unroll
-            for (int m = 0; m < Raw4<NS>::DM; ++m)
-                if (m < M)
+            for (int m = 0; m < M; ++m)
                     __builtin_amdgcn_global_load_lds(
                         (const void *)(G->c[m] + p),
                         (__attribute__((address_space(3))) void *)(rawb + m * 4096 + wave * 1024),
@@ -385,6 +372,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     int loc[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) loc[v] = 16 * (4 * (lane >> 4) + v) + (lane & 15);
+    // Ring offsets: this lane's A-fragment row (16 positions) of the current
+    // step, and this thread's 4 staged positions of the next step.
+    int aoff = 256 * wave + 16 * (lane & 15) + 16 * (lane >> 4);
+    int soff = 4 * tid;
 
     for (int step = 0; step < steps; ++step) {
         const int64_t T = T0 + (int64_t)step * kConvTile;
@@ -393,113 +384,114 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
 
         // Each wave: its 16x16 output tile, for every live slot.
         const int64_t P0 = T + 256 * wave;
-        const int aoff =
-            (int)(((T - T0) + 256 * wave + 16 * (lane & 15) + 16 * (lane >> 4)) % ring);
         int64_t dl[NS][4];
 #pragma unroll
-        for (int t = 0; t < NS; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dl[t][v] = 0;
-#pragma unroll
         for (int t = 0; t < NS; ++t) {
-            if (!slot_live(mode, M, r, lost, t, nslots)) continue;
-            const int pl = slot_stream(mode, M, r, t);
-            const unsigned char *pbase = planes + (size_t)pl * lap<LA>() * ring;
-            // One accumulator per digit pair (a, b), each MFMA reading and
-            // writing its own; a pair with a + b >= 8 is a multiple of 2^64
-            // and is skipped. Chunk 0 starts from zero.
-            v4i acc[LA][LB];
-            for (int c = 0; c < nch; ++c) {
-                int o = aoff + 64 * c;  // < 2 ring
-                o = o >= ring ? o - ring : o;
+            if (t == skip) {
+                // never read; a copy of a defined value keeps the compiler
+                // from carrying undefined registers around the step loop
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dl[t][v] = t > 0 ? dl[t > 0 ? t - 1 : 0][v] : 0;
+                continue;
+            }
+            const unsigned char *pbase = planes + (size_t)t * lap<LA>() * ring;
+            // One accumulator per digit weight s = a + b: the matrix core
+            // sums the digit pairs of equal weight. A pair with a + b >= 8 is
+            // a multiple of 2^64 and is skipped. Chunk 0 (there is always
+            // one) starts every weight from zero.
+            constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+            v4i acc[S];
+            int o = aoff;
+            auto chunk = [&](int c, v4i(&bf)[LB], v4i(&af)[LA]) {
                 const unsigned char *pa = pbase + plane_off(o, lap<LA>());
-                v4i bf[LB], af[LA];
+                o += 64;
+                o = o >= ring ? o - ring : o;
 #pragma unroll
                 for (int b = 0; b < LB; ++b) bf[b] = bfrag[(c * LB + b) * 64 + lane];
 #pragma unroll
                 for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
-                if (c == 0) {
+            };
+            {
+                v4i bf[LB], af[LA];
+                chunk(0, bf, af);
 #pragma unroll
-                    for (int b = 0; b < LB; ++b)
+                for (int b = 0; b < LB; ++b)
 #pragma unroll
-                        for (int a = 0; a < LA; ++a)
-                            if (a + b < 8)
-                                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                    af[a], bf[b], v4i{0, 0, 0, 0}, 0, 0, 0);
-                } else {
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bf[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
+                                0, 0, 0);
+            }
+            for (int c = 1; c < nch; ++c) {
+                v4i bf[LB], af[LA];
+                chunk(c, bf, af);
 #pragma unroll
-                    for (int b = 0; b < LB; ++b)
+                for (int b = 0; b < LB; ++b)
 #pragma unroll
-                        for (int a = 0; a < LA; ++a)
-                            if (a + b < 8)
-                                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
-                                                                                  acc[a][b], 0, 0, 0);
-                }
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
+                                                                              acc[a + b], 0, 0, 0);
             }
             // y = sum_s 256^s acc_s (mod 2^64). When the plan has shown every
             // acc_s + 256 acc_{s+1} fits in int32 (acc16), neighbouring digit
             // sums are merged in 32 bits first and the 64-bit Horner steps
             // over 16-bit shifts.
-            constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
             constexpr int H = (S + 1) / 2;
+            if (acc16) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                // digit sums of equal weight 256^s (exact in int32, plan-checked)
-                int32_t sh[S];
-#pragma unroll
-                for (int k = 0; k < S; ++k) sh[k] = 0;
-#pragma unroll
-                for (int b = 0; b < LB; ++b)
-#pragma unroll
-                    for (int a = 0; a < LA; ++a)
-                        if (a + b < 8) sh[a + b] += acc[a][b][v];
-                uint64_t y;
-                if (acc16) {
+                for (int v = 0; v < 4; ++v) {
                     int32_t z[H];
 #pragma unroll
                     for (int k = 0; k < H; ++k)
-                        z[k] = (int32_t)((uint32_t)sh[2 * k] +
-                                         (2 * k + 1 < S ? (uint32_t)sh[(2 * k + 1) % S] << 8 : 0u));
-                    y = (uint64_t)(int64_t)z[H - 1];
+                        z[k] = (int32_t)((uint32_t)acc[2 * k][v] +
+                                         (2 * k + 1 < S ? (uint32_t)acc[(2 * k + 1) % S][v] << 8
+                                                        : 0u));
+                    uint64_t y = (uint64_t)(int64_t)z[H - 1];
 #pragma unroll
                     for (int k = H - 2; k >= 0; --k) y = (y << 16) + (uint64_t)(int64_t)z[k];
-                } else {
-                    y = (uint64_t)(int64_t)sh[S - 1];
-#pragma unroll
-                    for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)sh[s];
+                    dl[t][v] = (int64_t)y;
                 }
-                dl[t][v] = (int64_t)y;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    uint64_t y = (uint64_t)(int64_t)acc[S - 1][v];
+#pragma unroll
+                    for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[s][v];
+                    dl[t][v] = (int64_t)y;
+                }
             }
         }
-        epilogue<NS, 4>(G, mode, M, r, lost, l, P0, n_out - P0, loc, dl, flag);
 
+        // Raw inputs of the next step are fetched before this step's outputs
+        // are stored, so that waiting for the direct loads does not also wait
+        // for those stores.
         const int64_t Tn = T + kConvTile;
         if (step + 1 < steps && Tn < n_out) {
-            Raw4<NS> raw;
+            Raw4<M> raw;
             const int64_t p = Tn + 4 * tid;
             if (use_dma && p + 4 <= n) {
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
 #pragma unroll
-                for (int m = 0; m < Raw4<NS>::DM; ++m) {
-                    if (m < M) {
-                        const int4 v = *reinterpret_cast<const int4 *>(rawb + m * 4096 + 16 * tid);
-                        raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) raw.cv[m][q] = 0;
-                    }
-                }
-                if (mode == kEntangled) {
-                    const int4 v = *reinterpret_cast<const int4 *>(rawb + (M - 1) * 4096 + 16 * tid);
-                    raw.cl[0] = v.x; raw.cl[1] = v.y; raw.cl[2] = v.z; raw.cl[3] = v.w;
+                for (int m = 0; m < M; ++m) {
+                    const int4 v = *reinterpret_cast<const int4 *>(rawb + m * 4096 + 16 * tid);
+                    raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
                 }
             } else {
-                load4<NS>(G, mode, M, p, n, raw);
+                load4<M>(G, p, n, raw);
             }
+            epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);
             __syncthreads();  // every wave is done with the ring slots reused here
-            store4<LA, NS>(raw, mode, M, l, nplanes, planes, ring, (int)((p - base) % ring), bd);
+            store4<LA, M, nplanes, mode>(raw, l, planes, ring, soff, bd);
             if (step + 2 < steps && Tn + kConvTile < n_out) dma(Tn + kConvTile);
+        } else {
+            epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);
         }
+        aoff += kConvTile;
+        aoff = aoff >= ring ? aoff - ring : aoff;
+        soff += kConvTile;
+        soff = soff >= ring ? soff - ring : soff;
     }
     if (bd.lo < G->in_lo || bd.hi > G->in_hi) flag |= kFlagInputRange;
     if (flag) atomicOr(flags, flag);
@@ -525,7 +517,7 @@ __device__ __forceinline__ void load_vec(const int32_t *src, T (&x)[V])
 // stream (r + 1 + t) mod M; otherwise stream t), for t < M. Same arithmetic
 // as epilogue(); with stream r computed, the redundant slot is checked.
 template <int NS, int V>
-__device__ __forceinline__ void recover_inplace(int mode, int M, int r, int lost, int l,
+__device__ __forceinline__ void recover_inplace(int mode, int M, int skip, int l,
                                                 int64_t (&dl)[NS][V], uint32_t &flag)
 {
     if (mode == kEntangled) {
@@ -552,7 +544,7 @@ __device__ __forceinline__ void recover_inplace(int mode, int M, int r, int lost
 #pragma unroll
             for (int t = 0; t < NS; ++t)
                 if (t == M - 1) {
-                    if (!lost && (uint64_t)dl[t][v] != (uint64_t)cur + ((uint64_t)d_prev << l))
+                    if (skip < 0 && (uint64_t)dl[t][v] != (uint64_t)cur + ((uint64_t)d_prev << l))
                         flag |= kFlagMismatch;
                     dl[t][v] = cur;
                 }
@@ -566,11 +558,11 @@ __device__ __forceinline__ void recover_inplace(int mode, int M, int r, int lost
                 if (t == M) e = (uint64_t)dl[t][v];
 #pragma unroll
             for (int t = 0; t < NS - 1; ++t)
-                if (t < M && !(lost && t == r)) sum += (uint64_t)dl[t][v];
-            if (lost) {
+                if (t < M && t != skip) sum += (uint64_t)dl[t][v];
+            if (skip >= 0) {
 #pragma unroll
                 for (int t = 0; t < NS - 1; ++t)
-                    if (t == r) dl[t][v] = (int64_t)(e - sum);
+                    if (t == skip) dl[t][v] = (int64_t)(e - sum);
             } else if (e != sum) {
                 flag |= kFlagMismatch;
             }
@@ -580,10 +572,9 @@ __device__ __forceinline__ void recover_inplace(int mode, int M, int r, int lost
 
 // Scale, add, permutation and inner product: V consecutive positions per
 // lane per step (8- or 16-byte loads, 16-byte stores), all M streams of the group at
-// once (entangle -> op -> recover in registers). Inputs are loaded directly
-// in slot order (slot t of an entangled group is stream (r + 1 + t) mod M),
-// so the previous stream of slot t >= 1 is slot t - 1 and no register is
-// selected at run time. Inner products accumulate per slot into the group's
+// once (entangle -> op -> recover in registers). The descriptor holds the
+// streams in slot order, so the previous stream of slot t >= 1 is slot t - 1
+// (of slot 0: slot M - 1) and no register is selected at run time. Inner products accumulate per slot into the group's
 // accumulators; k_inner_finalize recovers them.
 //
 // Items are taken in plain block order (no per-XCD runs): neighbouring
@@ -599,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     if (ii >= nitems) return;
     const Item it = items[ii];
     const GroupDev *G = groups + it.g;
-    const int op = G->op, mode = G->mode, M = G->M, r = G->r, lost = G->lost, l = G->l;
+    const int op = G->op, mode = G->mode, M = G->M, skip = G->skip, l = G->l;
     const int nslots = G->nslots, steps = G->steps;
     const int64_t n = G->n, sv = G->scalar;
     const int32_t *__restrict__ opd = G->operand;
@@ -608,15 +599,6 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     uint64_t iacc[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) iacc[t] = 0;
-    int sst[NS];  // stream of each slot (wave-uniform)
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        int st = mode == kEntangled ? r + 1 + t : t;
-        st = st >= M ? st - M : st;
-        st = st >= M ? st - M : st;
-        sst[t] = st < M ? st : 0;
-    }
-
     const int64_t strip0 = (int64_t)it.strip * steps * kBlock * V;
     for (int q = 0; q < steps; ++q) {
         const int64_t pb = strip0 + (int64_t)q * kBlock * V;
@@ -653,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
             for (int v = 0; v < V; ++v) cv[t][v] = 0;
             if (t < M) {
-                load(G->c[sst[t]], cv[t]);
+                load(G->c[t], cv[t]);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     bd.add(cv[t][v]);
@@ -661,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
                 }
             }
         }
-        if (mode == kEntangled) load(G->c[r], prev0);
+        if (mode == kEntangled) load(G->c[M - 1], prev0);
         if (op == NE_OP_ADD || op == NE_OP_INNER) {
             if (full) {
                 load_vec<V>(opd + p, gv);
@@ -678,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 dl[t][v] = 0;
-                if (!slot_live(mode, M, r, lost, t, nslots)) continue;
+                if (!slot_live(skip, t, nslots)) continue;
                 int64_t x, gs = gv[v];
                 if (mode == kEntangled) {
                     x = ent(cv[t][v], t == 0 ? prev0[v] : cv[t == 0 ? 0 : t - 1][v], l);
@@ -703,11 +685,11 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
             }
         }
         if (op == NE_OP_INNER) continue;
-        recover_inplace<NS, V>(mode, M, r, lost, l, dl, flag);
+        recover_inplace<NS, V>(mode, M, skip, l, dl, flag);
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
-            if (t >= M || (mode != kEntangled && mode != kChecksum && lost && t == r)) continue;
-            int64_t *o = G->out[sst[t]] + p;
+            if (t >= M || (mode != kEntangled && mode != kChecksum && t == skip)) continue;
+            int64_t *o = G->out[t] + p;
             if (full) {
 #pragma unroll
                 for (int v = 0; v < V; v += 2) *reinterpret_cast<I64x2 *>(o + v) = I64x2{dl[t][v], dl[t][v + 1]};
@@ -759,7 +741,7 @@ __global__ __launch_bounds__(64) void k_inner_finalize(const GroupDev *__restric
         G->acc[t] = 0;
     }
     const int loc[1] = {0};
-    epilogue<NS, 1>(G, G->mode, G->M, G->r, G->lost, G->l, 0, 1, loc, dl, flag);
+    epilogue<NS, 1>(G, G->mode, G->M, G->skip, G->l, 0, 1, loc, dl, flag);
     if (flag) atomicOr(flags, flag);
 }
 

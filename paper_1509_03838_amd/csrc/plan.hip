@@ -8,6 +8,7 @@
 #include <tuple>
 #include <vector>
 
+#include "conv_variants.h"
 #include "fused.h"
 #include "ne_internal.h"
 
@@ -15,7 +16,8 @@ using namespace ne;
 
 struct Bucket {
     int conv;             // 1: convolution kernel, 0: element-wise kernel
-    int cls, la, lb;
+    int cls, la, lb;      // element-wise: slot class; convolution: slots and digits
+    const ConvKernel *ck; // convolution kernel variant
     size_t lds;
     uint32_t first, count;  // range in the item array
 };
@@ -46,22 +48,21 @@ constexpr int kConvStepsDefault = 4;
 constexpr int kStreamStepsDefault = 4;
 constexpr size_t kMaxLds = 160 * 1024;
 
-// Fewest balanced base-256 digits (each in [-128, 127]) that represent every
-// integer in [-neg, pos]: L digits reach -128 R and 127 R, R = (256^L - 1)/255.
-int digits_for(unsigned __int128 neg, unsigned __int128 pos)
-{
-    unsigned __int128 R = 0, p = 1;
-    for (int L = 1; L <= 16; ++L) {
-        R += p;
-        p *= 256;
-        if (128 * R >= neg && 127 * R >= pos) return L;
-    }
-    return 17;
-}
-
 inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
 }  // namespace
+
+// Kernel variants whose LDS exceeds the default limit get it raised (once per
+// plan creation; the plan tables are host-only until then).
+static hipError_t plan_prepare(const ne_plan *plan)
+{
+    for (const Bucket &b : plan->buckets) {
+        if (!b.conv || b.lds <= 64 * 1024) continue;
+        const hipError_t e = b.ck->prepare(b.lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 extern "C" {
 
@@ -162,9 +163,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         G.K = u.op == NE_OP_CONV ? u.n_operand : 0;
         G.n_out = n_out;
         G.scalar = u.scalar;
-        for (int m = 0; m < u.M; ++m) {
-            G.c[m] = u.c[m];
-            G.out[m] = u.out[m];
+        G.skip = G.lost ? (mode == kEntangled ? u.M - 1 : G.r) : -1;
+        for (int t = 0; t < u.M; ++t) {
+            const int m = mode == kEntangled ? (G.r + 1 + t) % u.M : t;
+            G.c[t] = u.c[m];
+            G.out[t] = u.out[m];
         }
         G.operand = u.operand;
         const int cls = G.nslots <= 4 ? 0 : 1;
@@ -178,22 +181,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
 
         if (n_out == 0) continue;
         if (u.op == NE_OP_CONV) {
-            // Digits of the data words: inputs lie in [-B, B-1]; entangled
-            // words c + 2^l c' in (2^l + 1) times that; the checksum stream in
-            // M times that (the same digit count serves every slot).
-            unsigned __int128 neg = B, pos = B - 1;
-            if (mode == kEntangled || mode == kPlainSame) {
-                int32_t ll = 0, kk;
-                int64_t dd;
-                if (ne_params(u.M < 3 ? 3 : u.M, 64, &ll, &kk, &dd) != NE_OK) return fail(NE_ERANGE);
-                const unsigned __int128 f = ((unsigned __int128)1 << ll) + 1;
-                neg *= f;
-                pos *= f;
-            } else if (mode == kChecksum) {
-                neg *= (unsigned)u.M;
-                pos *= (unsigned)u.M;
-            }
-            const int la = digits_for(neg, pos), lb = digits_for(B, B - 1);
+            const DigitCounts dc = conv_digits(mode, u.M, u.in_bits);
+            const int la = dc.la, lb = dc.lb;
             if (la > kLimbsA || lb > kLimbsB) return fail(NE_EUNSUP);
             G.la = la;
             G.lb = lb;
@@ -218,7 +207,9 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             if (G.dma) lds += (size_t)u.M * 4096;
             const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
-            auto key = std::make_tuple(1, cls, la, lb);
+            const int kclass = conv_class_of_mode(mode);
+            if (!conv_kernel(kclass, G.nslots, la, lb)) return fail(NE_EUNSUP);
+            auto key = std::make_tuple(1, kclass * 16 + G.nslots, la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             bucket_lds[key] = std::max(bucket_lds[key], lds);
@@ -246,17 +237,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv ? bucket_lds[kv.first] : 0;
+        b.ck = b.conv ? conv_kernel(b.cls / 16, b.cls % 16, b.la, b.lb) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
         all_items.insert(all_items.end(), kv.second.begin(), kv.second.end());
         plan->buckets.push_back(b);
-        if (b.conv && b.lds > 64 * 1024) {
-            hipError_t e = fused_conv_prepare(b.cls, b.la, b.lb, b.lds);
-            if (e != hipSuccess) {
-                delete plan;
-                return hip_fail(e);
-            }
-        }
         st.lds_bytes = std::max<int64_t>(st.lds_bytes, (int64_t)b.lds);
     }
     plan->n_inner = (uint32_t)inner_groups.size();
@@ -313,8 +298,13 @@ ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
     ne_plan *plan = nullptr;
     ne_status st = plan_build(groups, n_groups, mode, tuning, &plan);
     if (st != NE_OK) return st;
+    hipError_t e = plan_prepare(plan);
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(e);
+    }
     unsigned char *arena = nullptr;
-    hipError_t e = hipMalloc((void **)&arena, plan_bytes(plan));
+    e = hipMalloc((void **)&arena, plan_bytes(plan));
     if (e != hipSuccess) {
         delete plan;
         (void)hipGetLastError();
@@ -355,8 +345,13 @@ ne_status ne_plan_create_in(const ne_group *groups, int32_t n_groups, int32_t mo
         delete plan;
         return NE_EINVAL;
     }
+    hipError_t e = plan_prepare(plan);
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(e);
+    }
     plan_place(plan, (unsigned char *)workspace);
-    hipError_t e = hipMemcpyAsync(workspace, plan->image.data(), plan->image.size(),
+    e = hipMemcpyAsync(workspace, plan->image.data(), plan->image.size(),
                                   hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e != hipSuccess) {
         delete plan;
@@ -373,8 +368,7 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
     for (const Bucket &b : plan->buckets) {
         if (b.count == 0) continue;
         if (b.conv)
-            fused_conv_launch(b.cls, b.la, b.lb, plan->d_groups, plan->d_items + b.first, b.count,
-                              plan->d_flags, b.lds, s);
+            b.ck->launch(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
         else
             fused_stream_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count,
                                 plan->d_flags, s);

@@ -144,3 +144,22 @@ def test_plan_rejects_misaligned_inputs(lib):
     g.c[1] = FAKE + 4  # int32 streams must be 16-byte aligned
     h = ctypes.c_void_p()
     assert lib.ne_plan_create((ne.GroupC * 1)(g), 1, 0, None, ctypes.byref(h)) == -1
+
+
+@pytest.mark.parametrize("mode,m_lo", [(0, 3), (1, 1), (2, 1), (3, 2)])
+def test_every_planned_convolution_has_a_kernel_variant(lib, mode, m_lo):
+    """The planner picks the digit counts of a convolution group from its
+    declared input bits; a kernel variant must exist for every choice it can
+    make (sizing only: ne_plan_workspace_size touches no device)."""
+    accepted = 0
+    for M in range(m_lo, 9):
+        for bits in range(1, 32):
+            g = _group(M=M, in_bits=bits, n_operand=1)
+            for m in range(M):
+                g.c[m] = FAKE + 256 * m
+                g.out[m] = FAKE + 4096 + 1024 * m
+            size = ctypes.c_size_t()
+            st = lib.ne_plan_workspace_size((ne.GroupC * 1)(g), 1, mode, None, ctypes.byref(size))
+            assert st in (0, -2), (mode, M, bits, st)  # OK, or the range check (never EUNSUP)
+            accepted += st == 0
+    assert accepted > 0

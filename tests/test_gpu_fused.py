@@ -198,3 +198,27 @@ def test_tuning_steps(steps):
     dg = DevGroup(grp, 12, 1)
     run([dg], conv_steps=steps, stream_steps=steps)
     assert np.array_equal(dg.result(), ref)
+
+
+@pytest.mark.parametrize("mode,m_lo", [("entangled", 3), ("plain", 1), ("plain_same", 1),
+                                       ("checksum", 2)])
+def test_every_convolution_variant(mode, m_lo):
+    """Every (M, digit-count) kernel variant the planner can pick for this
+    mode, on a short convolution with a ragged tail, with and without a lost
+    stream: inputs of 1, 2, 8, 9, 16, 17, 24, 25 and 31 bits."""
+    ran = 0
+    for M in range(m_lo, 9):
+        for bits in (1, 2, 8, 9, 16, 17, 24, 25, 31):
+            grp = make("conv", M, 1500, 7, bits, seed=7000 + 100 * M + bits)
+            ref = oracle.apply("conv", grp.c, grp.operand)
+            for lost in ([-1, M - 1] if mode in ("entangled", "checksum") else [-1]):
+                dg = DevGroup(grp, bits, lost, mode)
+                try:
+                    _, flags = run([dg], mode)
+                except ne.NeError as e:
+                    assert e.status == -2, (mode, M, bits, e)  # only the range check may refuse
+                    continue
+                assert flags == 0, (mode, M, bits, lost, flags)
+                assert np.array_equal(dg.result(), ref), (mode, M, bits, lost)
+                ran += 1
+    assert ran > 0
