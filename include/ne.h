@@ -243,7 +243,10 @@ typedef struct ne_group {
     int32_t steps;       /* tile steps per block for this group (conv: 1024
                             outputs each; element-wise: see ne_tuning); 0: the
                             plan's ne_tuning value */
-    int32_t reserved;    /* 0 */
+    int32_t ring_waves;  /* conv: waves that share one staging ring: 4 (one
+                            ring per block of 4 waves, two block barriers per
+                            step) or 1 (a ring per wave, no barrier in the
+                            step loop); 0: the plan's choice */
     const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
     const int32_t *operand;           /* device int32 taps / vector /
                                          permutation indices, 16-byte aligned;

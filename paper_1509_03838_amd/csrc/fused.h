@@ -40,10 +40,10 @@ struct GroupDev {
     int32_t nslots;   // streams whose operation runs: M, or M + 1 (checksum)
     int32_t nch;      // 64-wide chunks of the inner dimension (conv)
     int32_t kp;       // window lead: 64 * nch - 16 (conv)
-    int32_t wlen;     // staged window length: kConvTile + kp (conv)
+    int32_t ring_waves;  // waves sharing one staging ring: 4 or 1 (conv)
     int32_t in_lo, in_hi;  // declared input range [in_lo, in_hi]
     int32_t steps;    // conv tile steps (or streaming positions / 256) per block
-    int32_t ring;     // bytes per LDS digit-plane ring (= wlen) (conv)
+    int32_t ring;     // positions per LDS digit-plane ring: 256 * ring_waves + kp (conv)
     int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv)
     int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
     int32_t skip;     // slot whose operation is not run (the lost stream), or -1
@@ -68,10 +68,11 @@ struct Item {
 
 // One fused convolution kernel variant (fused_conv.hip, compiled once per
 // kernel class and slot count).
+// Index 0: one staging ring per block (4 waves); 1: one ring per wave.
 struct ConvKernel {
-    void (*launch)(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
-                   size_t lds, hipStream_t s);
-    hipError_t (*prepare)(size_t lds);  // raises the kernel's dynamic LDS limit
+    void (*launch[2])(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
+                      size_t lds, hipStream_t s);
+    hipError_t (*prepare[2])(size_t lds);  // raises the kernel's dynamic LDS limit
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);

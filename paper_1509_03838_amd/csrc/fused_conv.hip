@@ -15,20 +15,20 @@ namespace ne {
 
 namespace {
 
-template <int LA, int LB>
+template <int LA, int LB, int GW>
 void launch_one(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
                 size_t lds, hipStream_t s)
 {
     const uint32_t grid = ((nitems + 7u) >> 3) << 3;
-    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS>), dim3(grid),
+    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW>), dim3(grid),
                        dim3(fk::kBlock), lds, s, g, items, nitems, flags);
 }
 
-template <int LA, int LB>
+template <int LA, int LB, int GW>
 hipError_t prepare_one(size_t lds)
 {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS>),
+        reinterpret_cast<const void *>(&fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -36,9 +36,10 @@ template <int LA, int LB>
 constexpr ConvKernel entry()
 {
     if constexpr (conv_variant_needed(NE_KCLASS, NE_SLOTS, LA, LB))
-        return ConvKernel{&launch_one<LA, LB>, &prepare_one<LA, LB>};
+        return ConvKernel{{&launch_one<LA, LB, 4>, &launch_one<LA, LB, 1>},
+                          {&prepare_one<LA, LB, 4>, &prepare_one<LA, LB, 1>}};
     else
-        return ConvKernel{nullptr, nullptr};
+        return ConvKernel{{nullptr, nullptr}, {nullptr, nullptr}};
 }
 
 #define NE_ROW(LA) {entry<LA, 1>(), entry<LA, 2>(), entry<LA, 3>(), entry<LA, 4>()}
@@ -52,7 +53,7 @@ const ConvKernel *NE_NAME(conv_kernel_, NE_KCLASS, NE_SLOTS)(int la, int lb)
 {
     if (la < 1 || la > kLimbsA || lb < 1 || lb > kLimbsB) return nullptr;
     const ConvKernel *k = &table[la - 1][lb - 1];
-    return k->launch ? k : nullptr;
+    return k->launch[0] ? k : nullptr;
 }
 
 }  // namespace ne

@@ -278,7 +278,16 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
 // One variant per kernel class (0 entangled, 1 plain, 2 checksum) and slot
 // count NS, so that the mode, M and the slot loop are compile-time: the
 // descriptor's mode and M must match (the planner picks the variant).
-template <int LA, int LB, int NS, int KCLASS>
+//
+// GW waves share one staging ring. GW = 4: the block's ring covers 1024
+// outputs per step (each wave a 256-output tile of it); every wave stages a
+// quarter of the new positions, so two block barriers per step order the
+// staging against the reads. GW = 1: each wave owns a ring and a sub-strip
+// of steps x 256 outputs (the block's strip split in four) and stages its
+// own positions; a wave's LDS accesses take effect in program order, so the
+// step loop has no barrier at all, at the price of a window of kp extra
+// positions per wave instead of per block.
+template <int LA, int LB, int NS, int KCLASS, int GW>
 __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
                                                        const Item *__restrict__ items,
                                                        uint32_t nitems, uint32_t *flags)
@@ -287,22 +296,28 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     constexpr int M = KCLASS == 2 ? NS - 1 : NS;  // data streams
     constexpr int nplanes = NS;
     static_assert(M >= 1 && M <= kFusedMaxM, "slot count");
+    static_assert(GW == 1 || GW == 4, "waves per ring");
+    constexpr int SPAN = 256 * GW;   // positions a ring advances per step
+    constexpr int GT = 64 * GW;      // threads staging one ring
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t ii = item_index(nitems);
     if (ii >= nitems) return;
     const Item it = items[ii];
     const GroupDev *G = groups + it.g;
     const int skip = G->skip, l = G->l;
-    const int nch = G->nch, kp = G->kp, wlen = G->wlen, ring = G->ring;
+    const int nch = G->nch, kp = G->kp;
+    const int ring = SPAN + kp;  // window of one step, a multiple of 16
     const int steps = G->steps, acc16 = G->acc16, use_dma = G->dma;
     const int64_t n = G->n, K = G->K, n_out = G->n_out;
     const int32_t *__restrict__ g = G->operand;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = wave / GW, wg = wave % GW, gt = tid % GT;  // ring, wave and thread in it
     uint32_t flag = 0;
     Bounds bd;
 
     v4i *bfrag = reinterpret_cast<v4i *>(smem);
-    unsigned char *planes = smem + (size_t)nch * LB * 1024;
+    unsigned char *planes =
+        smem + (size_t)nch * LB * 1024 + (size_t)grp * nplanes * lap<LA>() * ring;
 
     // Toeplitz operand B, in the lane layout of the MFMA: lane (j, h) holds
     // B[64c + 16h + q][j] for q = 0..15, split into LB digit planes.
@@ -335,29 +350,31 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         }
     }
 
-    // The digit planes are rings of `ring` bytes (the window 1024 + kp, a
+    // The digit planes are rings of `ring` bytes (the window SPAN + kp, a
     // multiple of 16, so no 16-byte access wraps): ring offset 0 is position
     // T0 - kp. The first step stages the whole window, every later step only
-    // its 1024 new positions, at ring offsets that advance by 1024 per step.
-    const int64_t T0 = (int64_t)it.strip * steps * kConvTile;
+    // its SPAN new positions, at ring offsets that advance by SPAN per step.
+    const int64_t T0 = (int64_t)it.strip * steps * kConvTile + (int64_t)grp * steps * SPAN;
     const int64_t base = T0 - kp;
     {
         Raw4<M> raw;
-        for (int gi = tid; gi < (wlen >> 2); gi += kBlock) {
+        for (int gi = gt; gi < (ring >> 2); gi += GT) {
             load4<M>(G, base + 4 * gi, n, raw);
             store4<LA, M, nplanes, mode>(raw, l, planes, ring, 4 * gi, bd);
         }
     }
+    __syncthreads();  // operand fragments (and the first windows) complete
     // The raw int32 inputs of the next step travel HBM -> LDS by direct
     // loads (global_load_lds_dwordx4, no registers held) while this step
-    // computes; wave w lane j fetches positions 256w + 4j .. +3 of every
-    // stream, exactly the positions thread 64w + j converts at the step
+    // computes; the lane of staging thread j fetches positions 4j .. +3 of
+    // every stream, exactly the positions thread j converts at the step
     // boundary, so only the wave's own wait is needed before converting.
     // Lanes whose 4 positions are not all inside [0, n) load nothing; their
     // positions are read with bounds checks at conversion.
-    unsigned char *rawb = planes + (size_t)nplanes * lap<LA>() * ring;
+    unsigned char *rawb = smem + (size_t)nch * LB * 1024 +
+                          (size_t)(4 / GW) * nplanes * lap<LA>() * ring;
     auto dma = [&](int64_t Tq) {
-        const int64_t p = Tq + 4 * tid;
+        const int64_t p = Tq + 4 * gt;
         if (use_dma && p + 4 <= n) {
 #pragma unroll
             for (int m = 0; m < M; ++m)
@@ -367,23 +384,23 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                         16, 0, 0);
         }
     };
-    if (steps > 1 && T0 + kConvTile < n_out) dma(T0 + kConvTile);
+    if (steps > 1 && T0 + SPAN < n_out) dma(T0 + SPAN);
 
     int loc[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) loc[v] = 16 * (4 * (lane >> 4) + v) + (lane & 15);
     // Ring offsets: this lane's A-fragment row (16 positions) of the current
     // step, and this thread's 4 staged positions of the next step.
-    int aoff = 256 * wave + 16 * (lane & 15) + 16 * (lane >> 4);
-    int soff = 4 * tid;
+    int aoff = 256 * wg + 16 * (lane & 15) + 16 * (lane >> 4);
+    int soff = 4 * gt;
 
     for (int step = 0; step < steps; ++step) {
-        const int64_t T = T0 + (int64_t)step * kConvTile;
+        const int64_t T = T0 + (int64_t)step * SPAN;
         if (T >= n_out) break;
-        __syncthreads();  // digit planes of this step complete
+        if (GW > 1 && step > 0) __syncthreads();  // digit planes of this step complete
 
         // Each wave: its 16x16 output tile, for every live slot.
-        const int64_t P0 = T + 256 * wave;
+        const int64_t P0 = T + 256 * wg;
         int64_t dl[NS][4];
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
@@ -467,10 +484,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         // Raw inputs of the next step are fetched before this step's outputs
         // are stored, so that waiting for the direct loads does not also wait
         // for those stores.
-        const int64_t Tn = T + kConvTile;
+        const int64_t Tn = T + SPAN;
         if (step + 1 < steps && Tn < n_out) {
             Raw4<M> raw;
-            const int64_t p = Tn + 4 * tid;
+            const int64_t p = Tn + 4 * gt;
             if (use_dma && p + 4 <= n) {
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
 #pragma unroll
@@ -482,15 +499,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                 load4<M>(G, p, n, raw);
             }
             epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);
-            __syncthreads();  // every wave is done with the ring slots reused here
+            if (GW > 1) __syncthreads();  // every wave is done with the ring slots reused here
             store4<LA, M, nplanes, mode>(raw, l, planes, ring, soff, bd);
-            if (step + 2 < steps && Tn + kConvTile < n_out) dma(Tn + kConvTile);
+            if (step + 2 < steps && Tn + SPAN < n_out) dma(Tn + SPAN);
         } else {
             epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);
         }
-        aoff += kConvTile;
+        aoff += SPAN;
         aoff = aoff >= ring ? aoff - ring : aoff;
-        soff += kConvTile;
+        soff += SPAN;
         soff = soff >= ring ? soff - ring : soff;
     }
     if (bd.lo < G->in_lo || bd.hi > G->in_hi) flag |= kFlagInputRange;

@@ -16,7 +16,8 @@ using namespace ne;
 
 struct Bucket {
     int conv;             // 1: convolution kernel, 0: element-wise kernel
-    int cls, la, lb;      // element-wise: slot class; convolution: slots and digits
+    int cls, la, lb;      // element-wise: slot class; convolution: variant id
+                          // (((class * 16 + slots) << 1) | per-wave rings) and digits
     const ConvKernel *ck; // convolution kernel variant
     size_t lds;
     uint32_t first, count;  // range in the item array
@@ -58,7 +59,7 @@ static hipError_t plan_prepare(const ne_plan *plan)
 {
     for (const Bucket &b : plan->buckets) {
         if (!b.conv || b.lds <= 64 * 1024) continue;
-        const hipError_t e = b.ck->prepare(b.lds);
+        const hipError_t e = b.ck->prepare[b.cls & 1](b.lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -102,6 +103,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             return fail(NE_EINVAL);
         if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
         if (u.steps < 0 || u.steps > 4096) return fail(NE_EINVAL);
+        if (u.ring_waves != 0 && u.ring_waves != 1 && u.ring_waves != 4) return fail(NE_EINVAL);
         const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
         const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
         if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
@@ -188,8 +190,6 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             G.lb = lb;
             G.nch = (int)((u.n_operand + 15 + 63) / 64);
             G.kp = 64 * G.nch - 16;
-            G.wlen = kConvTile + G.kp;
-            G.ring = G.wlen;
             // Neighbouring digit sums merge in int32 when
             // |acc_s| + 256 |acc_{s+1}| < 2^31, |acc_s| <= min(la, lb) 64 nch 2^14.
             G.acc16 = (int64_t)257 * std::min(la, lb) * 64 * G.nch * 16384 < ((int64_t)1 << 31);
@@ -199,17 +199,34 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
                 return fail(NE_EUNSUP);
             const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
-            // B fragments | digit planes | raw int32 staging of one step
-            // (M x 4 KiB, only when it fits: the prefetch is an optimisation)
-            size_t lds = (size_t)G.nch * lb * 1024 + (size_t)nplanes * (la | 1) * G.ring;
+            // B fragments | digit-plane rings (one per block, or one per
+            // wave with a window of 256 + kp each) | raw int32 staging of one
+            // step (M x 4 KiB, only when it fits: the prefetch is an
+            // optimisation).
+            auto ring_lds = [&](int gw) {
+                return (size_t)G.nch * lb * 1024 +
+                       (size_t)(4 / gw) * nplanes * (la | 1) * (size_t)(256 * gw + G.kp);
+            };
+            int gw = u.ring_waves;
+            if (gw == 0) {
+                // Per-wave rings (no barriers) when they let as many blocks
+                // share a CU (at most 4: the register budget) as one ring per
+                // block does.
+                const size_t raw = (size_t)u.M * 4096;
+                auto per_cu = [&](int w) { return std::min<size_t>(4, kMaxLds / (ring_lds(w) + raw)); };
+                gw = per_cu(1) >= per_cu(4) ? 1 : 4;
+            }
+            size_t lds = ring_lds(gw);
             if (lds > kMaxLds) return fail(NE_EUNSUP);
+            G.ring_waves = gw;
+            G.ring = 256 * gw + G.kp;
             G.dma = lds + (size_t)u.M * 4096 <= kMaxLds && g_conv_steps > 1;
             if (G.dma) lds += (size_t)u.M * 4096;
             const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
             const int kclass = conv_class_of_mode(mode);
             if (!conv_kernel(kclass, G.nslots, la, lb)) return fail(NE_EUNSUP);
-            auto key = std::make_tuple(1, kclass * 16 + G.nslots, la, lb);
+            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 1) | (gw == 1), la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             bucket_lds[key] = std::max(bucket_lds[key], lds);
@@ -237,7 +254,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv ? bucket_lds[kv.first] : 0;
-        b.ck = b.conv ? conv_kernel(b.cls / 16, b.cls % 16, b.la, b.lb) : nullptr;
+        b.ck = b.conv ? conv_kernel((b.cls >> 1) / 16, (b.cls >> 1) % 16, b.la, b.lb) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
         all_items.insert(all_items.end(), kv.second.begin(), kv.second.end());
@@ -368,7 +385,7 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
     for (const Bucket &b : plan->buckets) {
         if (b.count == 0) continue;
         if (b.conv)
-            b.ck->launch(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
+            b.ck->launch[b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
         else
             fused_stream_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count,
                                 plan->d_flags, s);

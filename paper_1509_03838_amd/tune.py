@@ -4,11 +4,13 @@ The fused kernels process a strip of `steps` tiles per block (convolution:
 1024 outputs per step; element-wise: 256 lanes x 4 or 2 positions per
 step). Longer strips amortise the per-block set-up (the Toeplitz operand, the
 first window with its halo) but leave fewer blocks to balance the load; the
-best length depends on the operation, M, the digit counts and the sizes. The
-tuner groups a batch into workload classes, times every candidate step count
-on a few representative groups of each class with HIP events, and keeps the
-fastest per class in a JSON cache on disk, so later plans (and later
-processes) reuse the choice without timing.
+best length depends on the operation, M, the digit counts and the sizes.
+Convolutions also choose how many waves share one staging ring (4: one ring
+per block, barriers in the step loop; 1: a ring per wave, none, but a halo
+per wave). The tuner groups a batch into workload classes, times every
+candidate on a few representative groups of each class with HIP events, and
+keeps the fastest per class in a JSON cache on disk, so later plans (and
+later processes) reuse the choice without timing.
 
 Class key: convolution (mode, M, in_bits, K bucket, n bucket); element-wise
 (mode, op, M <= 4 or not, n bucket); K buckets are powers of two, n buckets
@@ -22,8 +24,8 @@ from typing import Sequence
 
 from . import ne
 
-CONV_CANDIDATES = (1, 2, 4, 8, 16)
-STREAM_CANDIDATES = (1, 2, 4, 8)
+CONV_CANDIDATES = tuple((st, rw) for st in (1, 2, 4, 8, 16) for rw in (4, 1))
+STREAM_CANDIDATES = tuple((st, 0) for st in (1, 2, 4, 8))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ne_tune.json")
 
 
@@ -40,17 +42,24 @@ def class_key(spec: ne.GroupSpec, mode: str) -> str:
     return f"{mode}|{spec.op}|M{'<=4' if len(spec.c) <= 4 else '>4'}|n{nb}"
 
 
+def _choice(v):
+    """A cached choice: [steps, ring_waves] (a bare int: steps)."""
+    if isinstance(v, int):
+        return (v, 0)
+    return (int(v[0]), int(v[1]))
+
+
 class Tuner:
     def __init__(self, cache_path: str | None = DEFAULT_CACHE, repeats: int = 3,
                  max_groups: int = 8):
         self.path, self.repeats, self.max_groups = cache_path, repeats, max_groups
-        self.cache: dict[str, int] = {}
+        self.cache: dict[str, tuple[int, int]] = {}
         if cache_path and os.path.exists(cache_path):
             try:
                 with open(cache_path) as f:
                     data = json.load(f)
-                self.cache = {k: int(v) for k, v in data.get("steps", {}).items()}
-            except (OSError, ValueError):
+                self.cache = {k: _choice(v) for k, v in data.get("steps", {}).items()}
+            except (OSError, ValueError, TypeError, IndexError):
                 self.cache = {}
 
     def save(self):
@@ -59,14 +68,22 @@ class Tuner:
         os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
         tmp = self.path + f".tmp{os.getpid()}"
         with open(tmp, "w") as f:
-            json.dump({"steps": self.cache}, f, indent=1, sort_keys=True)
+            json.dump({"steps": {k: list(v) for k, v in self.cache.items()}}, f, indent=1,
+                      sort_keys=True)
         os.replace(tmp, self.path)
 
-    def _time(self, specs: Sequence[ne.GroupSpec], mode: str, steps: int) -> float:
-        import torch
+    @staticmethod
+    def _apply(specs, choice):
         for sp in specs:
-            sp.steps = steps
-        plan = ne.Plan(specs, mode)
+            sp.steps, sp.ring_waves = choice
+
+    def _time(self, specs: Sequence[ne.GroupSpec], mode: str, choice) -> float:
+        import torch
+        self._apply(specs, choice)
+        try:
+            plan = ne.Plan(specs, mode)
+        except ne.NeError:
+            return float("inf")  # e.g. per-wave windows that do not fit in LDS
         try:
             plan.run()
             torch.cuda.synchronize()
@@ -81,9 +98,10 @@ class Tuner:
         finally:
             plan.close()
 
-    def tune(self, specs: Sequence[ne.GroupSpec], mode: str = "entangled") -> dict[str, int]:
-        """Sets `steps` on every spec (timing the classes not cached yet) and
-        returns the class -> steps table used."""
+    def tune(self, specs: Sequence[ne.GroupSpec], mode: str = "entangled") -> dict:
+        """Sets `steps` (and, for convolutions, `ring_waves`) on every spec,
+        timing the classes not cached yet, and returns the class -> choice
+        table used."""
         classes: dict[str, list[ne.GroupSpec]] = {}
         for sp in specs:
             classes.setdefault(class_key(sp, mode), []).append(sp)
@@ -93,16 +111,15 @@ class Tuner:
                 continue
             # representatives: the largest groups of the class
             reps = sorted(members, key=lambda s: -s.c[0].numel())[:self.max_groups]
-            saved = [s.steps for s in reps]
+            saved = [(s.steps, s.ring_waves) for s in reps]
             cands = CONV_CANDIDATES if reps[0].op == "conv" else STREAM_CANDIDATES
             times = {c: self._time(reps, mode, c) for c in cands}
             for s, v in zip(reps, saved):
-                s.steps = v
+                s.steps, s.ring_waves = v
             self.cache[key] = min(times, key=times.get)
             changed = True
         if changed:
             self.save()
         for key, members in classes.items():
-            for sp in members:
-                sp.steps = self.cache[key]
+            self._apply(members, self.cache[key])
         return {k: self.cache[k] for k in classes}

@@ -27,14 +27,16 @@ def host(ts):
 class DevGroup:
     """A workloads.Group on the device with output buffers."""
 
-    def __init__(self, grp: wl.Group, in_bits: int, lost: int = -1, mode: str = "entangled"):
+    def __init__(self, grp: wl.Group, in_bits: int, lost: int = -1, mode: str = "entangled",
+                 ring_waves: int = 0):
         self.grp = grp
         self.c = [dev32(row) for row in grp.c]
         self.operand = None if grp.op == "scale" else dev32(grp.operand)
         self.n_out = ne.n_out(grp.op, grp.n, 0 if grp.operand is None else grp.operand.size)
         self.out = [torch.full((max(self.n_out, 1),), POISON, dtype=torch.int64, device=DEV)[:self.n_out]
                     for _ in range(grp.M)]
-        self.spec = ne.GroupSpec(grp.op, self.c, self.operand, self.out, grp.scalar, lost, in_bits)
+        self.spec = ne.GroupSpec(grp.op, self.c, self.operand, self.out, grp.scalar, lost, in_bits,
+                                 ring_waves=ring_waves)
 
     def result(self):
         return host(self.out)
@@ -89,10 +91,15 @@ def test_conv_modes(mode, M, n, K, bits):
     ref = oracle.apply("conv", grp.c, grp.operand)
     losses = [-1] + list(range(M)) if mode in ("entangled", "checksum") else [-1]
     for lost in losses:
-        dg = DevGroup(grp, bits, lost, mode)
-        _, flags = run([dg], mode)
-        assert flags == 0, (mode, lost, flags)
-        assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost)
+        for rw in (4, 1):  # one staging ring per block / per wave
+            dg = DevGroup(grp, bits, lost, mode, ring_waves=rw)
+            try:
+                _, flags = run([dg], mode, conv_steps=3)
+            except ne.NeError as e:
+                assert e.status == -4 and rw == 1, (mode, M, K, rw, e)  # windows too large for LDS
+                continue
+            assert flags == 0, (mode, lost, flags, rw)
+            assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost, rw)
 
 
 @pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
@@ -192,10 +199,11 @@ def test_long_kernel_config_shape():
 
 
 @pytest.mark.parametrize("steps", [1, 2, 7])
-def test_tuning_steps(steps):
+@pytest.mark.parametrize("ring_waves", [1, 4])
+def test_tuning_steps(steps, ring_waves):
     grp = make("conv", 4, 30001, 129, 12, 8)
     ref = oracle.apply("conv", grp.c, grp.operand)
-    dg = DevGroup(grp, 12, 1)
+    dg = DevGroup(grp, 12, 1, ring_waves=ring_waves)
     run([dg], conv_steps=steps, stream_steps=steps)
     assert np.array_equal(dg.result(), ref)
 
@@ -211,8 +219,9 @@ def test_every_convolution_variant(mode, m_lo):
         for bits in (1, 2, 8, 9, 16, 17, 24, 25, 31):
             grp = make("conv", M, 1500, 7, bits, seed=7000 + 100 * M + bits)
             ref = oracle.apply("conv", grp.c, grp.operand)
-            for lost in ([-1, M - 1] if mode in ("entangled", "checksum") else [-1]):
-                dg = DevGroup(grp, bits, lost, mode)
+            for lost, rw in ([(-1, 4), (M - 1, 1)] if mode in ("entangled", "checksum")
+                             else [(-1, 4), (-1, 1)]):
+                dg = DevGroup(grp, bits, lost, mode, ring_waves=rw)
                 try:
                     _, flags = run([dg], mode)
                 except ne.NeError as e:

@@ -19,7 +19,8 @@ class FakeTensor:
 
 def spec(op, M, n, K=0, bits=12):
     return types.SimpleNamespace(op=op, c=[FakeTensor(n)] * M,
-                                 operand=FakeTensor(K) if K else None, in_bits=bits, steps=0)
+                                 operand=FakeTensor(K) if K else None, in_bits=bits, steps=0,
+                                 ring_waves=0)
 
 
 def test_class_keys_bucket_sizes():
@@ -35,14 +36,20 @@ def test_class_keys_bucket_sizes():
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "t.json")
     t = tune.Tuner(path)
-    t.cache = {"entangled|conv|M3|b12|K6|n10": 8}
+    t.cache = {"entangled|conv|M3|b12|K6|n10": (8, 1)}
     t.save()
-    assert json.load(open(path))["steps"]["entangled|conv|M3|b12|K6|n10"] == 8
+    assert json.load(open(path))["steps"]["entangled|conv|M3|b12|K6|n10"] == [8, 1]
     t2 = tune.Tuner(path)
     sp = [spec("conv", 3, 1 << 20, 64) for _ in range(3)]
     table = t2.tune(sp, "entangled")  # cached: no timing, no GPU
-    assert table == {"entangled|conv|M3|b12|K6|n10": 8}
-    assert all(s.steps == 8 for s in sp)
+    assert table == {"entangled|conv|M3|b12|K6|n10": (8, 1)}
+    assert all(s.steps == 8 and s.ring_waves == 1 for s in sp)
+
+
+def test_cache_reads_bare_step_counts(tmp_path):
+    path = tmp_path / "old.json"
+    path.write_text(json.dumps({"steps": {"entangled|scale|M<=4|n6": 4}}))
+    assert tune.Tuner(str(path)).cache == {"entangled|scale|M<=4|n6": (4, 0)}
 
 
 @pytest.mark.gpu
