@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
             v4i acc[S];
             int o = aoff;
-            auto chunk = [&](int c, v4i(&bf)[LB], v4i(&af)[LA]) {
+            auto load = [&](int c, v4i(&bf)[LB], v4i(&af)[LA]) {
                 const unsigned char *pa = pbase + plane_off(o, lap<LA>());
                 o += 64;
                 o = o >= ring ? o - ring : o;
@@ -428,21 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
 #pragma unroll
                 for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
             };
-            {
-                v4i bf[LB], af[LA];
-                chunk(0, bf, af);
-#pragma unroll
-                for (int b = 0; b < LB; ++b)
-#pragma unroll
-                    for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af[a], bf[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
-                                0, 0, 0);
-            }
-            for (int c = 1; c < nch; ++c) {
-                v4i bf[LB], af[LA];
-                chunk(c, bf, af);
+            auto mma = [&](const v4i(&bf)[LB], const v4i(&af)[LA]) {
 #pragma unroll
                 for (int b = 0; b < LB; ++b)
 #pragma unroll
@@ -450,6 +436,62 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                         if (a + b < 8)
                             acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
                                                                               acc[a + b], 0, 0, 0);
+            };
+            if constexpr (GW == 1) {
+                // Per-wave rings serve short kernels (few chunks): one
+                // fragment buffer, fewer registers, more waves per SIMD.
+                {
+                    v4i bf[LB], af[LA];
+                    load(0, bf, af);
+#pragma unroll
+                    for (int b = 0; b < LB; ++b)
+#pragma unroll
+                        for (int a = 0; a < LA; ++a)
+                            if (a + b < 8)
+                                acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                    af[a], bf[b],
+                                    (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b], 0, 0,
+                                    0);
+                }
+                for (int c = 1; c < nch; ++c) {
+                    v4i bf[LB], af[LA];
+                    load(c, bf, af);
+                    mma(bf, af);
+                }
+            } else {
+                // Block rings serve long kernels (many chunks). Two fragment
+                // buffers: the loads of chunk c + 1 are in flight
+                // while the matrix cores work on chunk c. Each half step first
+                // waits for every LDS load (only the current buffer's are in
+                // flight), then issues the next chunk's loads, then the current
+                // chunk's products; the scheduling barriers keep that order.
+                auto half = [&](int cn, bool more, v4i(&bfn)[LB], v4i(&afn)[LA],
+                                const v4i(&bfc)[LB], const v4i(&afc)[LA]) {
+                    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more) load(cn, bfn, afn);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma(bfc, afc);
+                };
+                v4i bf0[LB], af0[LA], bf1[LB], af1[LA];
+                load(0, bf0, af0);
+                __builtin_amdgcn_s_waitcnt(0xc07f);
+                __builtin_amdgcn_sched_barrier(0);
+                if (nch > 1) load(1, bf1, af1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af0[a], bf0[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
+                                0, 0, 0);
+                for (int c = 1; c < nch; c += 2) {
+                    half(c + 1, c + 1 < nch, bf0, af0, bf1, af1);  // products of chunk c
+                    if (c + 1 >= nch) break;
+                    half(c + 2, c + 2 < nch, bf1, af1, bf0, af0);  // products of chunk c + 1
+                }
             }
             // y = sum_s 256^s acc_s (mod 2^64). When the plan has shown every
             // acc_s + 256 acc_{s+1} fits in int32 (acc16), neighbouring digit
