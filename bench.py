@@ -36,7 +36,8 @@ CSRC = os.path.join(ROOT, "paper_1509_03838_amd", "csrc")
 # Sources that define the fused convolution kernel and its launch.
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("fused_kernels.h", "fused.h", "fused_conv.hip",
                                                "conv_variants.h", "plan.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv_fused_batched_traffic.txt")
+def traffic_file(config: str) -> str:
+    return os.path.join(ROOT, "profiles", f"conv_fused_{config}_traffic.txt")
 
 
 def parse():
@@ -72,13 +73,14 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(bytes_per_launch_hint: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(config: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this workload, if it was taken on the current kernel source; else None."""
+    path = traffic_file(config)
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -201,8 +203,7 @@ def main():
     achieved = alg_bytes / (ms_ev * 1e-3) / 1e9
     mfma_tops = 2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12
     hbm_frac, mfma_frac = achieved / HBM_PEAK_GBS, mfma_tops / INT8_PEAK_TOPS
-    traffic = read_traffic(alg_bytes) if args.config == "batched" and main_mode == "entangled" \
-        else None
+    traffic = read_traffic(args.config) if main_mode == "entangled" else None
 
     def thr(ms):
         return samples / (ms * 1e-3) / 1e9
