@@ -61,6 +61,16 @@ struct GroupDev {
     uint64_t *acc;    // inner product: kMaxSlots accumulators
 };
 
+// Bytes of one copy of one tap-digit plane of the convolution kernel: the
+// reversed taps Q[v] = g[kp + 15 - v], v in [0, 64 nch + 16), behind up to
+// 3 bytes of alignment padding, rounded to 16. The kernel keeps 4 copies
+// per digit plane (one per byte alignment) so that every operand fragment
+// read is dword-aligned.
+__host__ __device__ constexpr size_t conv_tap_plane_bytes(int nch)
+{
+    return ((size_t)64 * nch + 16 + 3 + 15) & ~(size_t)15;
+}
+
 struct Item {
     uint32_t g;       // group index
     uint32_t strip;   // strip index within the group

@@ -315,40 +315,39 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     uint32_t flag = 0;
     Bounds bd;
 
-    v4i *bfrag = reinterpret_cast<v4i *>(smem);
-    unsigned char *planes =
-        smem + (size_t)nch * LB * 1024 + (size_t)grp * nplanes * lap<LA>() * ring;
-
-    // Toeplitz operand B, in the lane layout of the MFMA: lane (j, h) holds
-    // B[64c + 16h + q][j] for q = 0..15, split into LB digit planes.
+    // LDS: tap-digit planes | data digit-plane rings | raw inputs.
+    //
+    // The Toeplitz operand B[s][j] = g[j + kp - s] is not stored expanded
+    // (each tap would appear 16 times): with the reversed taps
+    // Q[v] = g[kp + 15 - v], lane (j, h) of chunk c needs the 16 bytes
+    // Q[64c + 16h + 15 - j ...], consecutive but at a byte alignment set by
+    // j. Each digit plane of Q is kept in 4 copies, copy r shifted by
+    // (4 - r) mod 4 bytes, so that the lane reads its fragment as 4
+    // dword-aligned words from the copy matching its alignment.
+    const int tpb = (int)conv_tap_plane_bytes(nch);
+    unsigned char *taps = smem;
+    const size_t ring0 = (size_t)4 * LB * tpb;
+    unsigned char *planes = smem + ring0 + (size_t)grp * nplanes * lap<LA>() * ring;
     {
         constexpr uint64_t CB = digit_offset<LB>();
-        for (int e = tid; e < nch * 64; e += kBlock) {
-            const int c = e >> 6, ln = e & 63, j = ln & 15, h = ln >> 4;
-            uint32_t words[LB][4];
-#pragma unroll
-            for (int qg = 0; qg < 4; ++qg) {
-                uint32_t u4[4];
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int q = 4 * qg + q4;
-                    const int64_t idx = (int64_t)j + kp - (64 * c + 16 * h + q);
-                    const int32_t gv = (idx >= 0 && idx < K) ? g[idx] : 0;
-                    bd.add(gv);
-                    u4[q4] = (uint32_t)((uint64_t)(int64_t)gv + CB);
-                }
-                uint32_t w[4];
-                transpose4(u4, w);
-#pragma unroll
-                for (int b = 0; b < LB; ++b) words[b][qg] = w[b] ^ 0x80808080u;
-            }
+        const int vlen = 64 * nch + 16;
+        for (int v = tid; v < vlen; v += kBlock) {
+            const int64_t idx = (int64_t)kp + 15 - v;
+            const int32_t gv = (idx >= 0 && idx < K) ? g[idx] : 0;
+            bd.add(gv);
+            const uint64_t u = (uint64_t)(int64_t)gv + CB;
 #pragma unroll
             for (int b = 0; b < LB; ++b) {
-                v4i v = {(int)words[b][0], (int)words[b][1], (int)words[b][2], (int)words[b][3]};
-                bfrag[(c * LB + b) * 64 + ln] = v;
+                const unsigned char d = (unsigned char)((u >> (8 * b)) & 0xffu) ^ 0x80u;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) taps[(b * 4 + r) * tpb + ((4 - r) & 3) + v] = d;
             }
         }
     }
+    // This lane's fragment offset within plane b, chunk c: + (4 b) tpb + 64 c.
+    const int tj = lane & 15, th = lane >> 4;
+    const int tr = (15 - tj) & 3;
+    const int tap_lane = tr * tpb + ((4 - tr) & 3) + 16 * th + 15 - tj;
 
     // The digit planes are rings of `ring` bytes (the window SPAN + kp, a
     // multiple of 16, so no 16-byte access wraps): ring offset 0 is position
@@ -363,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             store4<LA, M, nplanes, mode>(raw, l, planes, ring, 4 * gi, bd);
         }
     }
-    __syncthreads();  // operand fragments (and the first windows) complete
+    __syncthreads();  // tap planes (and the first windows) complete
     // The raw int32 inputs of the next step travel HBM -> LDS by direct
     // loads (global_load_lds_dwordx4, no registers held) while this step
     // computes; the lane of staging thread j fetches positions 4j .. +3 of
@@ -371,8 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     // boundary, so only the wave's own wait is needed before converting.
     // Lanes whose 4 positions are not all inside [0, n) load nothing; their
     // positions are read with bounds checks at conversion.
-    unsigned char *rawb = smem + (size_t)nch * LB * 1024 +
-                          (size_t)(4 / GW) * nplanes * lap<LA>() * ring;
+    unsigned char *rawb = smem + ring0 + (size_t)(4 / GW) * nplanes * lap<LA>() * ring;
     auto dma = [&](int64_t Tq) {
         const int64_t p = Tq + 4 * gt;
         if (use_dma && p + 4 <= n) {
@@ -424,7 +422,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                 o += 64;
                 o = o >= ring ? o - ring : o;
 #pragma unroll
-                for (int b = 0; b < LB; ++b) bf[b] = bfrag[(c * LB + b) * 64 + lane];
+                for (int b = 0; b < LB; ++b) {
+                    const uint32_t *q = reinterpret_cast<const uint32_t *>(
+                        taps + tap_lane + 4 * b * tpb + 64 * c);
+                    bf[b] = v4i{(int)q[0], (int)q[1], (int)q[2], (int)q[3]};
+                }
 #pragma unroll
                 for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
             };

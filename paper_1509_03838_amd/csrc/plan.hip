@@ -199,29 +199,30 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
                 return fail(NE_EUNSUP);
             const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
-            // B fragments | digit-plane rings (one per block, or one per
-            // wave with a window of 256 + kp each) | raw int32 staging of one
-            // step (M x 4 KiB, only when it fits: the prefetch is an
-            // optimisation).
+            // LDS: tap-digit planes | digit-plane rings (one per block, or
+            // one per wave with a window of 256 + kp each) | raw int32
+            // staging of one step (the prefetch, below).
             auto ring_lds = [&](int gw) {
-                return (size_t)G.nch * lb * 1024 +
+                return (size_t)4 * lb * conv_tap_plane_bytes(G.nch) +
                        (size_t)(4 / gw) * nplanes * (la | 1) * (size_t)(256 * gw + G.kp);
             };
+            // Blocks of this variant that can share a CU (LDS-bound; at most
+            // 4, the register budget), with the raw-input prefetch buffer
+            // (M x 4 KiB) when it costs no block.
+            const size_t raw = (size_t)u.M * 4096;
+            auto fit = [&](int w, bool dma) {
+                const size_t b = ring_lds(w) + (dma ? raw : 0);
+                return b > kMaxLds ? (size_t)0 : std::min<size_t>(4, kMaxLds / b);
+            };
+            auto use_dma = [&](int w) { return g_conv_steps > 1 && fit(w, true) >= fit(w, false); };
+            auto blocks = [&](int w) { return fit(w, use_dma(w)); };
             int gw = u.ring_waves;
-            if (gw == 0) {
-                // Per-wave rings (no barriers) when they let as many blocks
-                // share a CU (at most 4: the register budget) as one ring per
-                // block does.
-                const size_t raw = (size_t)u.M * 4096;
-                auto per_cu = [&](int w) { return std::min<size_t>(4, kMaxLds / (ring_lds(w) + raw)); };
-                gw = per_cu(1) >= per_cu(4) ? 1 : 4;
-            }
-            size_t lds = ring_lds(gw);
-            if (lds > kMaxLds) return fail(NE_EUNSUP);
+            if (gw == 0) gw = blocks(1) >= blocks(4) ? 1 : 4;  // per-wave rings: no barriers
+            if (blocks(gw) == 0) return fail(NE_EUNSUP);
             G.ring_waves = gw;
             G.ring = 256 * gw + G.kp;
-            G.dma = lds + (size_t)u.M * 4096 <= kMaxLds && g_conv_steps > 1;
-            if (G.dma) lds += (size_t)u.M * 4096;
+            G.dma = use_dma(gw);
+            const size_t lds = ring_lds(gw) + (G.dma ? raw : 0);
             const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
             const int kclass = conv_class_of_mode(mode);

@@ -13,7 +13,8 @@ import os
 from typing import Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libne.so")
+# NE_LIB names another build of the library to load instead (to compare builds).
+LIB_PATH = os.environ.get("NE_LIB") or os.path.join(HERE, "libne.so")
 
 CONV, SCALE, ADD, INNER, PERM = 0, 1, 2, 3, 4
 OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM}
