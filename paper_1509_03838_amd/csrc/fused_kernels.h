@@ -397,6 +397,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         if (T >= n_out) break;
         if (GW > 1 && step > 0) __syncthreads();  // digit planes of this step complete
 
+        // Without the LDS prefetch, block-ring variants load the next
+        // step's raw inputs into registers here, so that they arrive while
+        // this step computes (per-wave ring variants, which keep fewer
+        // registers, load them at the step boundary).
+        const int64_t Tn = T + SPAN;
+        const bool more = step + 1 < steps && Tn < n_out;
+        Raw4<M> pre;
+        if (GW > 1 && !use_dma && more) load4<M>(G, Tn + 4 * gt, n, pre);
+
         // Each wave: its 16x16 output tile, for every live slot.
         const int64_t P0 = T + 256 * wg;
         int64_t dl[NS][4];
@@ -528,11 +537,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         // Raw inputs of the next step are fetched before this step's outputs
         // are stored, so that waiting for the direct loads does not also wait
         // for those stores.
-        const int64_t Tn = T + SPAN;
-        if (step + 1 < steps && Tn < n_out) {
-            Raw4<M> raw;
+        if (more) {
+            Raw4<M> raw = pre;
             const int64_t p = Tn + 4 * gt;
-            if (use_dma && p + 4 <= n) {
+            if (GW > 1 && !use_dma) {
+                // loaded at the top of the step
+            } else if (use_dma && p + 4 <= n) {
                 __builtin_amdgcn_s_waitcnt(0);  // this wave's direct loads have landed
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
