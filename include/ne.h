@@ -281,7 +281,10 @@ typedef struct ne_plan ne_plan;
  * in_bits, check that every group's worst-case output is admissible
  * (|d| <= D of eq. (11)/(13) in NE_MODE_ENTANGLED, |d| < 2^63 otherwise;
  * NE_ERANGE if not), build the work items and upload them. Allocates device
- * memory for the plan only (freed by ne_plan_destroy). The caller keeps
+ * memory for the plan only (freed by ne_plan_destroy): its tables, plus, per
+ * permutation group, n rows of 16 (at most 4 slots) or 32 bytes into which
+ * every run first interleaves the group's streams (so that each gather at
+ * pi[i] reads one row). The caller keeps
  * owning every buffer the groups point to; they must stay valid while the
  * plan is used. tuning may be NULL.
  */

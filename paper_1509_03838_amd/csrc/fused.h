@@ -13,6 +13,7 @@ constexpr int kLimbsA = 8;          // largest limb count of a data word
 constexpr int kLimbsB = 4;          // largest limb count of an operand value
 constexpr int kStreamV0 = 4;        // element-wise kernel: positions per lane, <= 4 slots
 constexpr int kStreamV1 = 2;        // element-wise kernel: positions per lane, <= 9 slots
+constexpr int kInterleaveStep = 1024;  // permutation layout pass: positions per block step
 
 // Execution modes of a plan.
 enum Mode : int32_t {
@@ -59,6 +60,8 @@ struct GroupDev {
     const int32_t *operand;
     int64_t *out[kFusedMaxM];
     uint64_t *acc;    // inner product: kMaxSlots accumulators
+    int32_t *rows;    // permutation: the streams interleaved, one row of 4 (<= 4 slots)
+                      // or 8 int32 per position, in the plan's workspace
 };
 
 // Bytes of one copy of one tap-digit plane of the convolution kernel: the
@@ -89,6 +92,8 @@ const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);
 
 void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
                          uint32_t *flags, hipStream_t s);
+void fused_interleave_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
+                             hipStream_t s);
 void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,
                           uint32_t *flags, hipStream_t s);
 

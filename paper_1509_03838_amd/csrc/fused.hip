@@ -67,6 +67,17 @@ void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t
                            dim3(fk::kBlock), 0, s, g, items, nitems, flags);
 }
 
+void fused_interleave_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
+                             hipStream_t s)
+{
+    if (cls == 0)
+        hipLaunchKernelGGL((fk::k_interleave<4>), dim3(nitems), dim3(fk::kBlock), 0, s, g, items,
+                           nitems);
+    else
+        hipLaunchKernelGGL((fk::k_interleave<8>), dim3(nitems), dim3(fk::kBlock), 0, s, g, items,
+                           nitems);
+}
+
 void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,
                           uint32_t *flags, hipStream_t s)
 {

@@ -641,6 +641,55 @@ __device__ __forceinline__ void recover_inplace(int mode, int M, int skip, int l
     }
 }
 
+// Permutation groups first have their streams interleaved into rows of RW
+// int32 (RW = 4 for up to 4 slots, else 8; unused entries zero) in the plan's
+// workspace: a row holds every stream's sample of one position, so that the
+// gather at pi[i] reads one 16- or 32-byte row instead of M scattered words.
+// A layout change only; no arithmetic. 4 positions per lane per step.
+template <int RW>
+__global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restrict__ groups,
+                                                       const Item *__restrict__ items,
+                                                       uint32_t nitems)
+{
+    const uint32_t ii = blockIdx.x;
+    if (ii >= nitems) return;
+    const Item it = items[ii];
+    const GroupDev *G = groups + it.g;
+    const int M = G->M, steps = G->steps;
+    const int64_t n = G->n;
+    int32_t *__restrict__ rows = G->rows;
+    const int64_t strip0 = (int64_t)it.strip * steps * kBlock * 4;
+    for (int q = 0; q < steps; ++q) {
+        const int64_t p = strip0 + (int64_t)q * kBlock * 4 + 4 * threadIdx.x;
+        if (p >= n) break;
+        const bool full = p + 4 <= n;
+        int32_t x[RW][4];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) x[t][v] = 0;
+            if (t < M) {
+                if (full) {
+                    const v4i w = load_in4(G->c[t] + p);
+                    x[t][0] = w.x; x[t][1] = w.y; x[t][2] = w.z; x[t][3] = w.w;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (p + v < n) x[t][v] = load_in1(G->c[t] + p + v);
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (p + v >= n) continue;
+#pragma unroll
+            for (int h = 0; h < RW; h += 4)
+                *reinterpret_cast<v4i *>(rows + (p + v) * RW + h) =
+                    v4i{x[h][v], x[h + 1][v], x[h + 2][v], x[h + 3][v]};
+        }
+    }
+}
+
 // Scale, add, permutation and inner product: V consecutive positions per
 // lane per step (8- or 16-byte loads, 16-byte stores), all M streams of the group at
 // once (entangle -> op -> recover in registers). The descriptor holds the
@@ -697,16 +746,37 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
                 for (int v = 0; v < V; ++v) x[v] = p + v < n ? base[src[v]] : 0;
             }
         };
-        // Inputs in slot order; prev0: the partner of slot 0 (stream r).
+        // Inputs in slot order; prev0: the partner of slot 0 (slot M - 1).
         int32_t cv[NS][V], prev0[V], csum[V], gv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) csum[v] = prev0[v] = gv[v] = 0;
 #pragma unroll
-        for (int t = 0; t < NS; ++t) {
+        for (int t = 0; t < NS; ++t)
 #pragma unroll
             for (int v = 0; v < V; ++v) cv[t][v] = 0;
+        if (op == NE_OP_PERM) {
+            // one interleaved row per position (k_interleave)
+            constexpr int RW = NS <= 4 ? 4 : 8;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (p + v >= n) continue;
+                const int32_t *row = G->rows + src[v] * RW;
+#pragma unroll
+                for (int h = 0; h < RW; h += 4) {
+                    const v4i w = *reinterpret_cast<const v4i *>(row + h);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (h + e < NS) cv[h + e][v] = w[e];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (t < M) load(G->c[t], cv[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
             if (t < M) {
-                load(G->c[t], cv[t]);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     bd.add(cv[t][v]);
@@ -714,7 +784,13 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
                 }
             }
         }
-        if (mode == kEntangled) load(G->c[M - 1], prev0);
+        if (mode == kEntangled) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t)
+                if (t == M - 1)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) prev0[v] = cv[t][v];
+        }
         if (op == NE_OP_ADD || op == NE_OP_INNER) {
             if (full) {
                 load_vec<V>(opd + p, gv);

@@ -30,7 +30,8 @@ struct ne_plan {
     std::vector<Item> items;
     std::vector<uint32_t> inner;
     std::vector<unsigned char> image;  // host copy of the device tables, uploaded verbatim
-    size_t sz_groups = 0, sz_items = 0, sz_inner = 0, sz_acc = 0, sz_flags = 0;
+    size_t sz_groups = 0, sz_items = 0, sz_inner = 0, sz_acc = 0, sz_flags = 0, sz_rows = 0;
+    std::vector<std::pair<uint32_t, size_t>> rows;  // permutation groups: (group, row offset)
     bool owns_arena = false;
     unsigned char *arena = nullptr;  // device: groups | items | inner idx | acc | flags
     GroupDev *d_groups = nullptr;
@@ -58,7 +59,7 @@ inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0
 static hipError_t plan_prepare(const ne_plan *plan)
 {
     for (const Bucket &b : plan->buckets) {
-        if (!b.conv || b.lds <= 64 * 1024) continue;
+        if (b.conv <= 0 || b.lds <= 64 * 1024) continue;
         const hipError_t e = b.ck->prepare[b.cls & 1](b.lds);
         if (e != hipSuccess) return e;
     }
@@ -87,6 +88,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     std::map<std::tuple<int, int, int, int>, std::vector<Item>> bucket_items;
     std::map<std::tuple<int, int, int, int>, size_t> bucket_lds;
     std::vector<uint32_t> inner_groups;
+    size_t rows_bytes = 0;
     ne_plan_stats st{};
     st.groups = n_groups;
 
@@ -243,6 +245,17 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             if (u.op == NE_OP_INNER) inner_groups.push_back((uint32_t)gi);
+            if (u.op == NE_OP_PERM && u.n > 0) {
+                // interleaved rows (4 or 8 int32 per position) in the arena,
+                // written by a layout pass launched before the element-wise kernels
+                const size_t rw = cls == 0 ? 4 : 8;
+                plan->rows.push_back({(uint32_t)gi, rows_bytes});
+                rows_bytes += ((size_t)u.n * rw * 4 + 255) & ~(size_t)255;
+                const int64_t istrip = (int64_t)g_stream_steps * kInterleaveStep;
+                auto &iv = bucket_items[std::make_tuple(-1, cls, 0, 0)];
+                for (int64_t s = 0; s < (u.n + istrip - 1) / istrip; ++s)
+                    iv.push_back(Item{(uint32_t)gi, (uint32_t)s});
+            }
         }
     }
 
@@ -254,8 +267,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.cls = std::get<1>(kv.first);
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
-        b.lds = b.conv ? bucket_lds[kv.first] : 0;
-        b.ck = b.conv ? conv_kernel((b.cls >> 1) / 16, (b.cls >> 1) % 16, b.la, b.lb) : nullptr;
+        b.lds = b.conv > 0 ? bucket_lds[kv.first] : 0;
+        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 1) / 16, (b.cls >> 1) % 16, b.la, b.lb) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
         all_items.insert(all_items.end(), kv.second.begin(), kv.second.end());
@@ -273,6 +286,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     plan->sz_inner = up(sizeof(uint32_t) * std::max<size_t>(1, inner_groups.size()));
     plan->sz_acc = up(sizeof(uint64_t) * kMaxSlots * std::max<size_t>(1, inner_groups.size()));
     plan->sz_flags = 256;
+    plan->sz_rows = rows_bytes;
     plan->items = std::move(all_items);
     plan->inner = std::move(inner_groups);
     plan->stats = st;
@@ -280,10 +294,14 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     return NE_OK;
 }
 
-static size_t plan_bytes(const ne_plan *p)
+// Device tables (uploaded from the host image) and the whole arena (the
+// tables, then the permutation rows, which the layout pass writes).
+static size_t table_bytes(const ne_plan *p)
 {
     return p->sz_groups + p->sz_items + p->sz_inner + p->sz_acc + p->sz_flags;
 }
+
+static size_t plan_bytes(const ne_plan *p) { return table_bytes(p) + p->sz_rows; }
 
 // Points the plan at its device arena and lays out the host image of the
 // tables (accumulators and flags zero) for one verbatim upload.
@@ -300,9 +318,11 @@ static void plan_place(ne_plan *plan, unsigned char *arena)
     uint64_t *d_acc = (uint64_t *)p;
     p += plan->sz_acc;
     plan->d_flags = (uint32_t *)p;
+    p += plan->sz_flags;
+    for (const auto &r : plan->rows) plan->host_groups[r.first].rows = (int32_t *)(p + r.second);
     for (size_t i = 0; i < plan->inner.size(); ++i)
         plan->host_groups[plan->inner[i]].acc = d_acc + kMaxSlots * i;
-    plan->image.assign(plan_bytes(plan), 0);
+    plan->image.assign(table_bytes(plan), 0);
     unsigned char *h = plan->image.data();
     memcpy(h, plan->host_groups.data(), sizeof(GroupDev) * plan->host_groups.size());
     memcpy(h + plan->sz_groups, plan->items.data(), sizeof(Item) * plan->items.size());
@@ -385,7 +405,9 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
     hipStream_t s = (hipStream_t)stream;
     for (const Bucket &b : plan->buckets) {
         if (b.count == 0) continue;
-        if (b.conv)
+        if (b.conv < 0)
+            fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
+        else if (b.conv)
             b.ck->launch[b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
         else
             fused_stream_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count,
