@@ -51,8 +51,11 @@ def _choice(v):
 
 class Tuner:
     def __init__(self, cache_path: str | None = DEFAULT_CACHE, repeats: int = 3,
-                 max_groups: int = 8):
-        self.path, self.repeats, self.max_groups = cache_path, repeats, max_groups
+                 max_groups: int = 256, min_work: int = 1 << 26):
+        """min_work: input samples the representatives of a class should
+        hold (at least one group; at most max_groups)."""
+        self.path, self.repeats = cache_path, repeats
+        self.max_groups, self.min_work = max_groups, min_work
         self.cache: dict[str, tuple[int, int]] = {}
         if cache_path and os.path.exists(cache_path):
             try:
@@ -109,8 +112,14 @@ class Tuner:
         for key, members in classes.items():
             if key in self.cache:
                 continue
-            # representatives: the largest groups of the class
-            reps = sorted(members, key=lambda s: -s.c[0].numel())[:self.max_groups]
+            # representatives: the largest groups of the class, enough of
+            # them to fill the device the way the whole batch does
+            reps, work = [], 0
+            for sp in sorted(members, key=lambda s: -s.c[0].numel()):
+                if len(reps) >= self.max_groups or work >= self.min_work:
+                    break
+                reps.append(sp)
+                work += len(sp.c) * sp.c[0].numel()
             saved = [(s.steps, s.ring_waves) for s in reps]
             cands = CONV_CANDIDATES if reps[0].op == "conv" else STREAM_CANDIDATES
             times = {c: self._time(reps, mode, c) for c in cands}

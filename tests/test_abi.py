@@ -163,3 +163,33 @@ def test_every_planned_convolution_has_a_kernel_variant(lib, mode, m_lo):
             assert st in (0, -2), (mode, M, bits, st)  # OK, or the range check (never EUNSUP)
             accepted += st == 0
     assert accepted > 0
+
+
+def _ws(lib, groups, mode=0):
+    size = ctypes.c_size_t()
+    st = lib.ne_plan_workspace_size((ne.GroupC * len(groups))(*groups), len(groups), mode, None,
+                                    ctypes.byref(size))
+    return st, size.value
+
+
+def test_workspace_holds_permutation_rows(lib):
+    """A permutation group adds n rows of 16 bytes (<= 4 slots) or 32 bytes
+    (more slots) to the plan's workspace; other operations add none."""
+    n = 10_000
+    st0, base = _ws(lib, [_group(op=1, n=n, n_operand=0, scalar=3)])  # scale
+    st1, perm3 = _ws(lib, [_group(op=4, n=n, n_operand=n)])
+    g6 = _group(op=4, M=6, n=n, n_operand=n)
+    for m in range(6):
+        g6.c[m] = FAKE + 256 * m
+        g6.out[m] = FAKE + 4096 + 1024 * m
+    st2, perm6 = _ws(lib, [g6])
+    assert st0 == st1 == st2 == 0
+    up = lambda x: (x + 255) // 256 * 256
+    assert perm3 - base >= up(16 * n) and perm3 - base < up(16 * n) + 4096
+    assert perm6 - base >= up(32 * n) and perm6 - base < up(32 * n) + 4096
+
+
+@pytest.mark.parametrize("rw,status", [(0, 0), (1, 0), (4, 0), (2, -1), (-1, -1)])
+def test_ring_waves_values(lib, rw, status):
+    g = _group(ring_waves=rw)
+    assert _ws(lib, [g])[0] == status
