@@ -14,7 +14,8 @@ ARCH = "gfx950"
 
 SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "plan.hip"]
 
-# fused_conv.hip is compiled once per (kernel class, slot count): entangled
+# fused_conv.hip is compiled once per (kernel class, slot count), and
+# fused_stream.hip once per kernel class: entangled
 # groups of 3..8 streams, plain groups of 1..8, checksum groups of 2..8 data
 # streams (3..9 slots).
 CONV_VARIANTS = ([(0, n) for n in range(3, 9)] + [(1, n) for n in range(1, 9)] +
@@ -34,6 +35,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     units = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
     units += [("fused_conv.hip", f"fused_conv_{k}_{n}.o", [f"-DNE_KCLASS={k}", f"-DNE_SLOTS={n}"])
               for k, n in CONV_VARIANTS]
+    units += [("fused_stream.hip", f"fused_stream_{k}.o", [f"-DNE_KCLASS={k}"]) for k in range(3)]
     objs = []
     pending = list(units)
     running = []

@@ -15,6 +15,12 @@ constexpr int kStreamV0 = 4;        // element-wise kernel: positions per lane, 
 constexpr int kStreamV1 = 2;        // element-wise kernel: positions per lane, <= 9 slots
 constexpr int kInterleaveStep = 1024;  // permutation layout pass: positions per block step
 
+// Element-wise kernel: positions per lane per step for a slot count.
+__host__ __device__ constexpr int stream_positions(int slots)
+{
+    return slots <= 4 ? kStreamV0 : kStreamV1;
+}
+
 // Execution modes of a plan.
 enum Mode : int32_t {
     kEntangled = 0,  // the method: entangle, op per stream, extract
@@ -90,8 +96,12 @@ struct ConvKernel {
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);
 
-void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
-                         uint32_t *flags, hipStream_t s);
+// One element-wise kernel variant (fused_stream.hip, compiled once per kernel
+// class): operation x slot count.
+using StreamLaunch = void (*)(const GroupDev *g, const Item *items, uint32_t nitems,
+                              uint32_t *flags, hipStream_t s);
+// The variant for (operation, kernel class, slots), or null if none is built.
+StreamLaunch stream_kernel(int op, int kclass, int slots);
 void fused_interleave_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
                              hipStream_t s);
 void fused_inner_finalize(const GroupDev *g, const uint32_t *gidx, uint32_t count,

@@ -56,15 +56,20 @@ const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb)
     }
 }
 
-void fused_stream_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
-                         uint32_t *flags, hipStream_t s)
+// Element-wise variants built by fused_stream.hip (one translation unit per
+// kernel class).
+StreamLaunch stream_kernel_0(int op, int slots);
+StreamLaunch stream_kernel_1(int op, int slots);
+StreamLaunch stream_kernel_2(int op, int slots);
+
+StreamLaunch stream_kernel(int op, int kclass, int slots)
 {
-    if (cls == 0)
-        hipLaunchKernelGGL((fk::k_stream_fused<4, kStreamV0>), dim3(nitems), dim3(fk::kBlock), 0, s,
-                           g, items, nitems, flags);
-    else
-        hipLaunchKernelGGL((fk::k_stream_fused<kMaxSlots, kStreamV1>), dim3(nitems),
-                           dim3(fk::kBlock), 0, s, g, items, nitems, flags);
+    switch (kclass) {
+    case 0: return stream_kernel_0(op, slots);
+    case 1: return stream_kernel_1(op, slots);
+    case 2: return stream_kernel_2(op, slots);
+    default: return nullptr;
+    }
 }
 
 void fused_interleave_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,

@@ -697,21 +697,29 @@ __global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restric
 // (of slot 0: slot M - 1) and no register is selected at run time. Inner products accumulate per slot into the group's
 // accumulators; k_inner_finalize recovers them.
 //
+// One variant per operation, kernel class (0 entangled, 1 plain, 2 checksum)
+// and slot count NS: operation, mode, M and the slot loops are compile-time.
+//
 // Items are taken in plain block order (no per-XCD runs): neighbouring
 // blocks then work on the same group at the same time, so a permutation's
 // random gathers fall into a working set the memory-side cache holds.
-template <int NS, int V>
+template <int OP, int KCLASS, int NS>
 __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
                                                          const Item *__restrict__ items,
                                                          uint32_t nitems, uint32_t *flags)
 {
+    constexpr int V = stream_positions(NS);
+    constexpr int op = OP;
+    constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
+    constexpr int M = KCLASS == 2 ? NS - 1 : NS;
+    constexpr int nslots = NS;
     static_assert(V == 2 || V == 4, "2 or 4 positions per lane");
     const uint32_t ii = blockIdx.x;
     if (ii >= nitems) return;
     const Item it = items[ii];
     const GroupDev *G = groups + it.g;
-    const int op = G->op, mode = G->mode, M = G->M, skip = G->skip, l = G->l;
-    const int nslots = G->nslots, steps = G->steps;
+    const int skip = G->skip, l = G->l;
+    const int steps = G->steps;
     const int64_t n = G->n, sv = G->scalar;
     const int32_t *__restrict__ opd = G->operand;
     uint32_t flag = 0;

@@ -16,9 +16,11 @@ using namespace ne;
 
 struct Bucket {
     int conv;             // 1: convolution kernel, 0: element-wise kernel
-    int cls, la, lb;      // element-wise: slot class; convolution: variant id
-                          // (((class * 16 + slots) << 1) | per-wave rings) and digits
+    int cls, la, lb;      // convolution: variant id (((class * 16 + slots) << 1) |
+                          // per-wave rings) and digits; element-wise: variant id
+                          // ((op * 4 + class) * 16 + slots); layout pass: slot class
     const ConvKernel *ck; // convolution kernel variant
+    StreamLaunch sk;      // element-wise kernel variant
     size_t lds;
     uint32_t first, count;  // range in the item array
 };
@@ -239,9 +241,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         } else {
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = g_stream_steps;
-            const int64_t strip = (int64_t)g_stream_steps * 256 * (cls == 0 ? kStreamV0 : kStreamV1);
+            const int64_t strip = (int64_t)g_stream_steps * 256 * stream_positions(G.nslots);
             const int64_t nstrips = (u.n + strip - 1) / strip;
-            auto key = std::make_tuple(0, cls, 0, 0);
+            const int kclass = conv_class_of_mode(mode);
+            if (!stream_kernel(u.op, kclass, G.nslots)) return fail(NE_EUNSUP);
+            auto key = std::make_tuple(0, (u.op * 4 + kclass) * 16 + G.nslots, 0, 0);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             if (u.op == NE_OP_INNER) inner_groups.push_back((uint32_t)gi);
@@ -269,6 +273,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv > 0 ? bucket_lds[kv.first] : 0;
         b.ck = b.conv > 0 ? conv_kernel((b.cls >> 1) / 16, (b.cls >> 1) % 16, b.la, b.lb) : nullptr;
+        b.sk = b.conv == 0 ? stream_kernel(b.cls / 64, (b.cls / 16) % 4, b.cls % 16) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
         all_items.insert(all_items.end(), kv.second.begin(), kv.second.end());
@@ -410,8 +415,7 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
         else if (b.conv)
             b.ck->launch[b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
         else
-            fused_stream_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count,
-                                plan->d_flags, s);
+            b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);
     }
     if (plan->n_inner)
         fused_inner_finalize(plan->d_groups, plan->d_inner, plan->n_inner, plan->d_flags, s);
