@@ -41,7 +41,26 @@ constexpr int table1_shift64(int M)
 
 struct DigitCounts {
     int la, lb;
+    int sparse;  // 1: the taps' top digit is nonzero only for a sliver of their range
 };
+
+// Balanced digits reach 127 * R on the positive side (R = (256^L - 1)/255),
+// one step short of a power of two: taps of 16 bits need a third digit, but
+// only for values above 127 * 257. When LB - 1 digits cover all but such a
+// sliver (at most 1/32 of the values), the kernel runs the top digit plane
+// only for the chunks of taps that need it.
+constexpr int sparse_top_digit(int in_bits, int lb)
+{
+    if (lb < 2) return 0;
+    const unsigned __int128 B = (unsigned __int128)1 << (in_bits - 1);
+    unsigned __int128 R = 0, p = 1;
+    for (int L = 1; L < lb; ++L) {
+        R += p;
+        p *= 256;
+    }
+    if (128 * R < B || 127 * R >= B - 1) return 0;
+    return (B - 1 - 127 * R) * 32 <= 2 * B ? 1 : 0;
+}
 
 // Digits of the data words and of the taps of a convolution group whose
 // inputs and taps lie in [-2^(b-1), 2^(b-1) - 1]. Entangled words
@@ -61,7 +80,8 @@ constexpr DigitCounts conv_digits(int mode, int M, int in_bits)
         neg *= (unsigned)M;
         pos *= (unsigned)M;
     }
-    return DigitCounts{digits_for(neg, pos), digits_for(B, B - 1)};
+    const int lb = digits_for(B, B - 1);
+    return DigitCounts{digits_for(neg, pos), lb, sparse_top_digit(in_bits, lb)};
 }
 
 constexpr int conv_class_of_mode(int mode) { return mode == 0 ? 0 : (mode == 3 ? 2 : 1); }
@@ -70,8 +90,8 @@ constexpr int conv_class_of_mode(int mode) { return mode == 0 ? 0 : (mode == 3 ?
 constexpr int conv_slots(int mode, int M) { return mode == 3 ? M + 1 : M; }
 
 // Whether some group of this kernel class and slot count, with inputs of
-// 1..31 bits, uses digit counts (la, lb).
-constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb)
+// 1..31 bits, uses digit counts (la, lb) with a sparse top tap digit or not.
+constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb, int sparse)
 {
     for (int mode = 0; mode < 4; ++mode) {
         if (conv_class_of_mode(mode) != kclass) continue;
@@ -79,7 +99,7 @@ constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb)
         if (M < (mode == 0 ? 3 : (mode == 3 ? 2 : 1))) continue;
         for (int b = 1; b <= 31; ++b) {
             const DigitCounts d = conv_digits(mode, M, b);
-            if (d.la == la && d.lb == lb) return true;
+            if (d.la == la && d.lb == lb && d.sparse == sparse) return true;
         }
     }
     return false;

@@ -80,6 +80,12 @@ __host__ __device__ constexpr size_t conv_tap_plane_bytes(int nch)
     return ((size_t)64 * nch + 16 + 3 + 15) & ~(size_t)15;
 }
 
+// LDS bytes of the convolution kernel's tap planes and chunk mask.
+__host__ __device__ constexpr size_t conv_tap_lds(int nch, int lb)
+{
+    return (size_t)4 * lb * conv_tap_plane_bytes(nch) + 16;
+}
+
 struct Item {
     uint32_t g;       // group index
     uint32_t strip;   // strip index within the group
@@ -87,11 +93,13 @@ struct Item {
 
 // One fused convolution kernel variant (fused_conv.hip, compiled once per
 // kernel class and slot count).
-// Index 0: one staging ring per block (4 waves); 1: one ring per wave.
+// First index: the taps' top digit is dense (0) or sparse (1); second: one
+// staging ring per block of 4 waves (0) or one per wave (1). Null where no
+// group needs the variant.
 struct ConvKernel {
-    void (*launch[2])(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
-                      size_t lds, hipStream_t s);
-    hipError_t (*prepare[2])(size_t lds);  // raises the kernel's dynamic LDS limit
+    void (*launch[2][2])(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
+                         size_t lds, hipStream_t s);
+    hipError_t (*prepare[2][2])(size_t lds);  // raises the kernel's dynamic LDS limit
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);

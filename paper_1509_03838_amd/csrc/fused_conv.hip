@@ -15,31 +15,61 @@ namespace ne {
 
 namespace {
 
-template <int LA, int LB, int GW>
+template <int LA, int LB, int GW, int SP>
 void launch_one(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
                 size_t lds, hipStream_t s)
 {
     const uint32_t grid = ((nitems + 7u) >> 3) << 3;
-    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW>), dim3(grid),
+    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW, SP>), dim3(grid),
                        dim3(fk::kBlock), lds, s, g, items, nitems, flags);
 }
 
-template <int LA, int LB, int GW>
+template <int LA, int LB, int GW, int SP>
 hipError_t prepare_one(size_t lds)
 {
     return hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW>),
+        reinterpret_cast<const void *>(&fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW, SP>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+using LaunchFn = void (*)(const GroupDev *, const Item *, uint32_t, uint32_t *, size_t,
+                          hipStream_t);
+using PrepareFn = hipError_t (*)(size_t);
+
+template <int LA, int LB, int SP>
+constexpr bool needed()
+{
+    if constexpr (SP == 1 && LB < 2)
+        return false;
+    else
+        return conv_variant_needed(NE_KCLASS, NE_SLOTS, LA, LB, SP);
+}
+
+template <int LA, int LB, int GW, int SP>
+constexpr LaunchFn launcher()
+{
+    if constexpr (needed<LA, LB, SP>())
+        return &launch_one<LA, LB, GW, SP>;
+    else
+        return nullptr;
+}
+
+template <int LA, int LB, int GW, int SP>
+constexpr PrepareFn preparer()
+{
+    if constexpr (needed<LA, LB, SP>())
+        return &prepare_one<LA, LB, GW, SP>;
+    else
+        return nullptr;
 }
 
 template <int LA, int LB>
 constexpr ConvKernel entry()
 {
-    if constexpr (conv_variant_needed(NE_KCLASS, NE_SLOTS, LA, LB))
-        return ConvKernel{{&launch_one<LA, LB, 4>, &launch_one<LA, LB, 1>},
-                          {&prepare_one<LA, LB, 4>, &prepare_one<LA, LB, 1>}};
-    else
-        return ConvKernel{{nullptr, nullptr}, {nullptr, nullptr}};
+    return ConvKernel{{{launcher<LA, LB, 4, 0>(), launcher<LA, LB, 1, 0>()},
+                       {launcher<LA, LB, 4, 1>(), launcher<LA, LB, 1, 1>()}},
+                      {{preparer<LA, LB, 4, 0>(), preparer<LA, LB, 1, 0>()},
+                       {preparer<LA, LB, 4, 1>(), preparer<LA, LB, 1, 1>()}}};
 }
 
 #define NE_ROW(LA) {entry<LA, 1>(), entry<LA, 2>(), entry<LA, 3>(), entry<LA, 4>()}
@@ -53,7 +83,7 @@ const ConvKernel *NE_NAME(conv_kernel_, NE_KCLASS, NE_SLOTS)(int la, int lb)
 {
     if (la < 1 || la > kLimbsA || lb < 1 || lb > kLimbsB) return nullptr;
     const ConvKernel *k = &table[la - 1][lb - 1];
-    return k->launch[0] ? k : nullptr;
+    return (k->launch[0][0] || k->launch[1][0]) ? k : nullptr;
 }
 
 }  // namespace ne

@@ -287,7 +287,7 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
 // own positions; a wave's LDS accesses take effect in program order, so the
 // step loop has no barrier at all, at the price of a window of kp extra
 // positions per wave instead of per block.
-template <int LA, int LB, int NS, int KCLASS, int GW>
+template <int LA, int LB, int NS, int KCLASS, int GW, int SP>
 __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
                                                        const Item *__restrict__ items,
                                                        uint32_t nitems, uint32_t *flags)
@@ -297,6 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     constexpr int nplanes = NS;
     static_assert(M >= 1 && M <= kFusedMaxM, "slot count");
     static_assert(GW == 1 || GW == 4, "waves per ring");
+    static_assert(SP == 0 || (SP == 1 && LB >= 2), "sparse top tap digit");
+    constexpr int LBM = LB - SP;     // tap digit planes of the main pass
     constexpr int SPAN = 256 * GW;   // positions a ring advances per step
     constexpr int GT = 64 * GW;      // threads staging one ring
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -326,8 +328,15 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     // dword-aligned words from the copy matching its alignment.
     const int tpb = (int)conv_tap_plane_bytes(nch);
     unsigned char *taps = smem;
-    const size_t ring0 = (size_t)4 * LB * tpb;
+    // Bit c of tmask: chunk c's top tap-digit plane has a nonzero digit
+    // (sparse-top variants; chunks from 64 on always run it).
+    uint32_t *tmask = reinterpret_cast<uint32_t *>(smem + (size_t)4 * LB * tpb);
+    const size_t ring0 = (size_t)4 * LB * tpb + 16;
     unsigned char *planes = smem + ring0 + (size_t)grp * nplanes * lap<LA>() * ring;
+    if (SP) {
+        if (tid < 2) tmask[tid] = 0;
+        __syncthreads();
+    }
     {
         constexpr uint64_t CB = digit_offset<LB>();
         const int vlen = 64 * nch + 16;
@@ -341,6 +350,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                 const unsigned char d = (unsigned char)((u >> (8 * b)) & 0xffu) ^ 0x80u;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) taps[(b * 4 + r) * tpb + ((4 - r) & 3) + v] = d;
+                if (SP && b == LB - 1 && d != 0) {
+                    // the chunks whose fragments read Q[v]: 64c <= v <= 64c + 78
+                    for (int c = v >> 6; c >= 0 && 64 * c + 78 >= v; --c)
+                        if (c < 64) atomicOr(&tmask[c >> 5], 1u << (c & 31));
+                }
             }
         }
     }
@@ -363,6 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         }
     }
     __syncthreads();  // tap planes (and the first windows) complete
+    uint64_t topmask = 0;
+    if (SP)
+        topmask = ((uint64_t)__builtin_amdgcn_readfirstlane(tmask[1]) << 32) |
+                  __builtin_amdgcn_readfirstlane(tmask[0]);
     // The raw int32 inputs of the next step travel HBM -> LDS by direct
     // loads (global_load_lds_dwordx4, no registers held) while this step
     // computes; the lane of staging thread j fetches positions 4j .. +3 of
@@ -426,12 +444,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
             v4i acc[S];
             int o = aoff;
-            auto load = [&](int c, v4i(&bf)[LB], v4i(&af)[LA]) {
+            auto load = [&](int c, v4i(&bf)[LBM], v4i(&af)[LA]) {
                 const unsigned char *pa = pbase + plane_off(o, lap<LA>());
                 o += 64;
                 o = o >= ring ? o - ring : o;
 #pragma unroll
-                for (int b = 0; b < LB; ++b) {
+                for (int b = 0; b < LBM; ++b) {
                     const uint32_t *q = reinterpret_cast<const uint32_t *>(
                         taps + tap_lane + 4 * b * tpb + 64 * c);
                     bf[b] = v4i{(int)q[0], (int)q[1], (int)q[2], (int)q[3]};
@@ -439,70 +457,91 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
 #pragma unroll
                 for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
             };
-            auto mma = [&](const v4i(&bf)[LB], const v4i(&af)[LA]) {
+            auto mma = [&](const v4i(&bf)[LBM], const v4i(&af)[LA]) {
 #pragma unroll
-                for (int b = 0; b < LB; ++b)
+                for (int b = 0; b < LBM; ++b)
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
                         if (a + b < 8)
                             acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
                                                                               acc[a + b], 0, 0, 0);
             };
+            // chunk 0 starts every weight the main pass reaches (its first pair
+            // writes it with a zero accumulator); a weight only the sparse top
+            // plane reaches starts at zero
+            auto mma_first = [&](const v4i(&bf)[LBM], const v4i(&af)[LA]) {
+                if (SP && LA + LB - 2 < 8) acc[LA + LB - 2] = v4i{0, 0, 0, 0};
+#pragma unroll
+                for (int b = 0; b < LBM; ++b)
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bf[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
+                                0, 0, 0);
+            };
             if constexpr (GW == 1) {
                 // Per-wave rings serve short kernels (few chunks): one
                 // fragment buffer, fewer registers, more waves per SIMD.
                 {
-                    v4i bf[LB], af[LA];
+                    v4i bf[LBM], af[LA];
                     load(0, bf, af);
-#pragma unroll
-                    for (int b = 0; b < LB; ++b)
-#pragma unroll
-                        for (int a = 0; a < LA; ++a)
-                            if (a + b < 8)
-                                acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                    af[a], bf[b],
-                                    (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b], 0, 0,
-                                    0);
+                    mma_first(bf, af);
                 }
                 for (int c = 1; c < nch; ++c) {
-                    v4i bf[LB], af[LA];
+                    v4i bf[LBM], af[LA];
                     load(c, bf, af);
                     mma(bf, af);
                 }
             } else {
                 // Block rings serve long kernels (many chunks). Two fragment
-                // buffers: the loads of chunk c + 1 are in flight
-                // while the matrix cores work on chunk c. Each half step first
-                // waits for every LDS load (only the current buffer's are in
-                // flight), then issues the next chunk's loads, then the current
-                // chunk's products; the scheduling barriers keep that order.
-                auto half = [&](int cn, bool more, v4i(&bfn)[LB], v4i(&afn)[LA],
-                                const v4i(&bfc)[LB], const v4i(&afc)[LA]) {
+                // buffers: the loads of chunk c + 1 are in flight while the
+                // matrix cores work on chunk c. Each half step first waits for
+                // every LDS load (only the current buffer's are in flight),
+                // then issues the next chunk's loads, then the current chunk's
+                // products; the scheduling barriers keep that order.
+                auto half = [&](int cn, bool more, v4i(&bfn)[LBM], v4i(&afn)[LA],
+                                const v4i(&bfc)[LBM], const v4i(&afc)[LA]) {
                     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
                     __builtin_amdgcn_sched_barrier(0);
                     if (more) load(cn, bfn, afn);
                     __builtin_amdgcn_sched_barrier(0);
                     mma(bfc, afc);
                 };
-                v4i bf0[LB], af0[LA], bf1[LB], af1[LA];
+                v4i bf0[LBM], af0[LA], bf1[LBM], af1[LA];
                 load(0, bf0, af0);
                 __builtin_amdgcn_s_waitcnt(0xc07f);
                 __builtin_amdgcn_sched_barrier(0);
                 if (nch > 1) load(1, bf1, af1);
                 __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int b = 0; b < LB; ++b)
-#pragma unroll
-                    for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af0[a], bf0[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
-                                0, 0, 0);
+                mma_first(bf0, af0);
                 for (int c = 1; c < nch; c += 2) {
                     half(c + 1, c + 1 < nch, bf0, af0, bf1, af1);  // products of chunk c
                     if (c + 1 >= nch) break;
                     half(c + 2, c + 2 < nch, bf1, af1, bf0, af0);  // products of chunk c + 1
                 }
+            }
+            if constexpr (SP) {
+                // the top tap-digit plane, only for the chunks whose taps need it
+                auto top = [&](int c) {
+                    int ot = aoff + 64 * c;
+                    ot = ot >= ring ? ot - ring : ot;
+                    const unsigned char *pa = pbase + plane_off(ot, lap<LA>());
+                    const uint32_t *q = reinterpret_cast<const uint32_t *>(
+                        taps + tap_lane + 4 * (LB - 1) * tpb + 64 * c);
+                    const v4i bt = {(int)q[0], (int)q[1], (int)q[2], (int)q[3]};
+                    v4i af[LA];
+#pragma unroll
+                    for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + LB - 1 < 8)
+                            acc[a + LB - 1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bt, acc[a + LB - 1], 0, 0, 0);
+                };
+                uint64_t m = nch >= 64 ? topmask : topmask & ((1ull << nch) - 1);
+                for (; m; m &= m - 1) top(__builtin_ctzll(m));
+                for (int c = 64; c < nch; ++c) top(c);
             }
             // y = sum_s 256^s acc_s (mod 2^64). When the plan has shown every
             // acc_s + 256 acc_{s+1} fits in int32 (acc16), neighbouring digit

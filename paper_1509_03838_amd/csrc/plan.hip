@@ -16,8 +16,8 @@ using namespace ne;
 
 struct Bucket {
     int conv;             // 1: convolution kernel, 0: element-wise kernel
-    int cls, la, lb;      // convolution: variant id (((class * 16 + slots) << 1) |
-                          // per-wave rings) and digits; element-wise: variant id
+    int cls, la, lb;      // convolution: variant id (((class * 16 + slots) << 2) |
+                          // (sparse top tap digit << 1) | per-wave rings) and digits; element-wise: variant id
                           // ((op * 4 + class) * 16 + slots); layout pass: slot class
     const ConvKernel *ck; // convolution kernel variant
     StreamLaunch sk;      // element-wise kernel variant
@@ -62,7 +62,7 @@ static hipError_t plan_prepare(const ne_plan *plan)
 {
     for (const Bucket &b : plan->buckets) {
         if (b.conv <= 0 || b.lds <= 64 * 1024) continue;
-        const hipError_t e = b.ck->prepare[b.cls & 1](b.lds);
+        const hipError_t e = b.ck->prepare[(b.cls >> 1) & 1][b.cls & 1](b.lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -207,7 +207,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // one per wave with a window of 256 + kp each) | raw int32
             // staging of one step (the prefetch, below).
             auto ring_lds = [&](int gw) {
-                return (size_t)4 * lb * conv_tap_plane_bytes(G.nch) +
+                return conv_tap_lds(G.nch, lb) +
                        (size_t)(4 / gw) * nplanes * (la | 1) * (size_t)(256 * gw + G.kp);
             };
             // Blocks of this variant that can share a CU (LDS-bound; at most
@@ -230,14 +230,18 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
             const int kclass = conv_class_of_mode(mode);
-            if (!conv_kernel(kclass, G.nslots, la, lb)) return fail(NE_EUNSUP);
-            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 1) | (gw == 1), la, lb);
+            const ConvKernel *ck = conv_kernel(kclass, G.nslots, la, lb);
+            if (!ck || !ck->launch[dc.sparse][0]) return fail(NE_EUNSUP);
+            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 2) | (dc.sparse << 1) | (gw == 1),
+                                       la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             bucket_lds[key] = std::max(bucket_lds[key], lds);
             const int64_t slots_run = G.nslots - G.lost;
+            // (a sparse top tap digit runs only where the taps need it: that
+            // data-dependent part is not counted)
             st.mfma_macs += slots_run * nstrips * g_conv_steps * (int64_t)kConvTile * 64 * G.nch *
-                            la * lb;
+                            la * (lb - dc.sparse);
         } else {
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = g_stream_steps;
@@ -272,7 +276,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv > 0 ? bucket_lds[kv.first] : 0;
-        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 1) / 16, (b.cls >> 1) % 16, b.la, b.lb) : nullptr;
+        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 2) / 16, (b.cls >> 2) % 16, b.la, b.lb) : nullptr;
         b.sk = b.conv == 0 ? stream_kernel(b.cls / 64, (b.cls / 16) % 4, b.cls % 16) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
@@ -413,7 +417,8 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
         if (b.conv < 0)
             fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
         else if (b.conv)
-            b.ck->launch[b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, b.lds, s);
+            b.ck->launch[(b.cls >> 1) & 1][b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count,
+                                                      plan->d_flags, b.lds, s);
         else
             b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);
     }

@@ -231,3 +231,23 @@ def test_every_convolution_variant(mode, m_lo):
                 assert np.array_equal(dg.result(), ref), (mode, M, bits, lost)
                 ran += 1
     assert ran > 0
+
+
+@pytest.mark.parametrize("ring_waves", [1, 4])
+def test_sparse_top_tap_digit_windows(ring_waves):
+    """16-bit taps need a third balanced digit only above 127 * 257; the
+    kernel runs that digit plane just for the 64-wide chunks whose operand
+    fragments touch such a tap. One large tap at chunk edges, every loss."""
+    g = wl.rng(99)
+    M, n, K = 3, 3000, 200
+    c = wl.uniform_i32(g, -(1 << 15), 1 << 15, (M, n))
+    for pos in (0, 14, 15, 63, 64, 78, 79, 127, 128, 142, 143, 199):
+        k = wl.uniform_i32(g, -30000, 30000, K)
+        k[pos] = 32767 - pos % 7
+        grp = wl.Group("conv", c, k)
+        ref = oracle.apply("conv", grp.c, grp.operand)
+        for lost in (-1, 0, 2):
+            dg = DevGroup(grp, 16, lost, ring_waves=ring_waves)
+            _, flags = run([dg], conv_steps=2)
+            assert flags == 0
+            assert np.array_equal(dg.result(), ref), (pos, lost)
