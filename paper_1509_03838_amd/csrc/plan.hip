@@ -43,6 +43,8 @@ struct ne_plan {
     uint32_t *d_flags = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> branch;  // streams of the graph's parallel branches (capture only)
+    std::vector<hipEvent_t> joins;    // their join events, then the fork event (kBranches + 1)
     ne_plan_stats stats{};
 };
 
@@ -51,6 +53,7 @@ namespace {
 constexpr int kConvStepsDefault = 4;
 constexpr int kStreamStepsDefault = 4;
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr size_t kBranches = 4;  // parallel branches of a captured run
 
 inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -408,19 +411,67 @@ ne_status ne_plan_create_in(const ne_group *groups, int32_t n_groups, int32_t mo
     return NE_OK;
 }
 
+static void launch_bucket(const ne_plan *plan, const Bucket &b, hipStream_t s)
+{
+    if (b.count == 0) return;
+    if (b.conv < 0)
+        fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
+    else if (b.conv)
+        b.ck->launch[(b.cls >> 1) & 1][b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count,
+                                                  plan->d_flags, b.lds, s);
+    else
+        b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);
+}
+
 ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
 {
     if (!plan) return NE_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    for (const Bucket &b : plan->buckets) launch_bucket(plan, b, s);
+    if (plan->n_inner)
+        fused_inner_finalize(plan->d_groups, plan->d_inner, plan->n_inner, plan->d_flags, s);
+    return launch_status();
+}
+
+// The captured form of a run: the permutation layout passes, then every
+// other launch spread over up to kBranches parallel branches of the graph
+// (the launches touch disjoint groups; running them side by side fills the
+// tail of one with the next), then the inner-product recovery.
+static ne_status capture_branches(ne_plan *plan, hipStream_t s)
+{
+    std::vector<const Bucket *> work;
     for (const Bucket &b : plan->buckets) {
         if (b.count == 0) continue;
         if (b.conv < 0)
-            fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
-        else if (b.conv)
-            b.ck->launch[(b.cls >> 1) & 1][b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count,
-                                                      plan->d_flags, b.lds, s);
+            launch_bucket(plan, b, s);
         else
-            b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);
+            work.push_back(&b);
+    }
+    const int nb = (int)std::min<size_t>(plan->branch.size(), work.size());
+    if (nb <= 1) {
+        for (const Bucket *b : work) launch_bucket(plan, *b, s);
+    } else {
+        hipError_t e = hipSuccess;
+        // longest-first onto the least loaded branch (cost ~ items x slots)
+        std::vector<const Bucket *> order = work;
+        auto cost = [](const Bucket *b) { return (double)b->count * (b->conv ? 4.0 : 1.0); };
+        std::sort(order.begin(), order.end(),
+                  [&](const Bucket *x, const Bucket *y) { return cost(x) > cost(y); });
+        std::vector<double> load(nb, 0.0);
+        std::vector<std::vector<const Bucket *>> lanes(nb);
+        for (const Bucket *b : order) {
+            const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            lanes[i].push_back(b);
+            load[i] += cost(b);
+        }
+        e = hipEventRecord(plan->joins[kBranches], s);  // fork
+        for (int i = 0; i < nb && e == hipSuccess; ++i) {
+            e = hipStreamWaitEvent(plan->branch[i], plan->joins[kBranches], 0);
+            for (const Bucket *b : lanes[i]) launch_bucket(plan, *b, plan->branch[i]);
+            if (e == hipSuccess) e = hipEventRecord(plan->joins[i], plan->branch[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->joins[i], 0);  // join
+        }
+        if (e != hipSuccess) return hip_fail(e);
     }
     if (plan->n_inner)
         fused_inner_finalize(plan->d_groups, plan->d_inner, plan->n_inner, plan->d_flags, s);
@@ -439,9 +490,26 @@ ne_status ne_plan_capture(ne_plan *plan, ne_stream stream)
         (void)hipGraphDestroy(plan->graph);
         plan->graph = nullptr;
     }
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    // branch streams and their events, created before the capture begins
+    size_t nwork = 0;
+    for (const Bucket &b : plan->buckets) nwork += b.count > 0 && b.conv >= 0;
+    hipError_t e = hipSuccess;
+    if (nwork > 1) {
+        while (plan->branch.size() < kBranches && e == hipSuccess) {
+            hipStream_t a = nullptr;
+            e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+            if (e == hipSuccess) plan->branch.push_back(a);
+        }
+        while (plan->joins.size() < kBranches + 1 && e == hipSuccess) {
+            hipEvent_t ev = nullptr;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) plan->joins.push_back(ev);
+        }
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e);
-    ne_status st = ne_plan_run(plan, stream);
+    ne_status st = capture_branches(plan, s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (st != NE_OK) {
@@ -492,6 +560,8 @@ ne_status ne_plan_destroy(ne_plan *plan)
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->arena && plan->owns_arena) (void)hipFree(plan->arena);
+    for (hipEvent_t ev : plan->joins) (void)hipEventDestroy(ev);
+    for (hipStream_t a : plan->branch) (void)hipStreamDestroy(a);
     delete plan;
     return NE_OK;
 }

@@ -50,11 +50,11 @@ def _choice(v):
 
 
 class Tuner:
-    def __init__(self, cache_path: str | None = DEFAULT_CACHE, repeats: int = 3,
-                 max_groups: int = 256, min_work: int = 1 << 26):
+    def __init__(self, cache_path: str | None = DEFAULT_CACHE, repeats: int = 5,
+                 max_groups: int = 256, min_work: int = 1 << 26, rounds: int = 2):
         """min_work: input samples the representatives of a class should
         hold (at least one group; at most max_groups)."""
-        self.path, self.repeats = cache_path, repeats
+        self.path, self.repeats, self.rounds = cache_path, repeats, rounds
         self.max_groups, self.min_work = max_groups, min_work
         self.cache: dict[str, tuple[int, int]] = {}
         if cache_path and os.path.exists(cache_path):
@@ -122,7 +122,12 @@ class Tuner:
                 work += len(sp.c) * sp.c[0].numel()
             saved = [(s.steps, s.ring_waves) for s in reps]
             cands = CONV_CANDIDATES if reps[0].op == "conv" else STREAM_CANDIDATES
-            times = {c: self._time(reps, mode, c) for c in cands}
+            # every candidate timed in `rounds` interleaved passes; the best
+            # pass counts (a slow pass is noise, a fast one is not)
+            times = {c: float("inf") for c in cands}
+            for _ in range(self.rounds):
+                for c in cands:
+                    times[c] = min(times[c], self._time(reps, mode, c))
             for s, v in zip(reps, saved):
                 s.steps, s.ring_waves = v
             self.cache[key] = min(times, key=times.get)

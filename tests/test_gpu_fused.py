@@ -135,6 +135,31 @@ def test_uneven_batch_matches_standalone_and_oracle():
         assert np.array_equal(alone.result(), dg.result())
 
 
+def test_uneven_graph_branches_replay():
+    """A captured uneven plan (dozens of launches on parallel graph branches,
+    permutation layout passes first, inner-product recovery last), replayed
+    several times with eager work in between: every replay equals the oracle."""
+    groups = wl.config_uneven(seed=8, groups=60, n_hi=1 << 14)
+    devs = [DevGroup(g, 10) for g in groups]
+    plan = ne.Plan([d.spec for d in devs])
+    assert plan.stats()["launches"] > 8
+    s = torch.cuda.Stream()
+    refs = [d.reference() for d in devs]
+    with torch.cuda.stream(s):
+        plan.capture(s)
+        for rep in range(3):
+            for d in devs:
+                for t in d.out:
+                    t.fill_(POISON)
+            plan.launch(s)
+            s.synchronize()
+            y = torch.ones(4096, device=DEV).cumsum(0)  # unrelated eager work
+            assert float(y[-1]) == 4096.0
+            for d, ref in zip(devs, refs):
+                assert np.array_equal(d.result(), ref), (rep, d.grp.op, d.grp.M)
+    assert plan.flags() == 0
+
+
 def test_graph_replay_matches_eager():
     groups = [make("conv", 3, 20000, 64, 12, 1), make("scale", 4, 9000, 0, 12, 2),
               make("inner", 5, 7777, 0, 12, 3), make("perm", 3, 5000, 0, 12, 4)]
