@@ -226,7 +226,8 @@ typedef enum ne_mode {
 
 /* Device-side error bits (ne_plan_flags). */
 #define NE_FLAG_INPUT_RANGE 1u /* an input or operand value outside in_bits */
-#define NE_FLAG_LIMBS 2u       /* a word needed more digits than planned */
+#define NE_FLAG_LIMBS 2u       /* reserved, never raised: digit counts follow
+                                  in_bits, which every input is checked against */
 #define NE_FLAG_MISMATCH 4u    /* redundant stream disagrees with the outputs */
 
 /* One group: M streams of n int32 samples sharing one operand. */

@@ -32,7 +32,7 @@ enum Mode : int32_t {
 // Error bits reported through the plan's flag word.
 enum Flag : uint32_t {
     kFlagInputRange = 1u,   // an input or operand value outside the declared bits
-    kFlagLimbs = 2u,        // a word did not fit the chosen limb count
+    kFlagLimbs = 2u,        // reserved: digit counts follow the declared (checked) range
     kFlagMismatch = 4u      // the redundant stream disagreed with the recovered outputs
 };
 

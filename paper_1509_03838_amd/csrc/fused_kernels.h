@@ -5,19 +5,19 @@
 // and only the recovered int64 outputs are written. The entangled words and
 // the entangled outputs live in LDS and registers only.
 //
-// Convolution runs on the i8 matrix cores as a Toeplitz product. A block
-// step covers 1024 consecutive outputs; wave w owns the 16x16 tile of
-// outputs y[T + 256w + 16i + j] (row i, column j), and
+// Convolution runs on the i8 matrix cores as a Toeplitz product. Each wave
+// computes 16x16 tiles of outputs y[P + 16i + j] (row i, column j):
 //     y[P + 16i + j] = sum_s A[i][s] B[s][j],
 //     A[i][s] = x[P + 16i - kp + s],  B[s][j] = g[j + kp - s]  (0 outside [0, K)),
 // with s over 64*nch >= K + 15 values and kp = 64*nch - 16, so every row of
-// A is a contiguous window of the stream: the staged window of the block is
-// the whole A operand. Words are split into balanced base-256 digits in
-// [-128, 127] (LA digits for data words, LB for taps); every digit pair is
-// one v_mfma_i32_16x16x64_i8 with exact int32 accumulation, and
-// y = sum 256^(a+b) acc_ab is recombined in 64-bit wrap-around arithmetic,
-// which is exact modulo 2^64 whatever the digit count (a word that needs more
-// digits than chosen is flagged, never silently truncated).
+// A is a contiguous window of the stream, read straight from a staging ring
+// in LDS. Words are split into balanced base-256 digits in [-128, 127] (LA
+// digits for data words, LB for taps); every digit pair is one
+// v_mfma_i32_16x16x64_i8 with exact int32 accumulation (pairs of equal weight
+// a + b share an accumulator), and y = sum 256^s acc_s is recombined in
+// 64-bit wrap-around arithmetic, exact modulo 2^64. The digit counts come
+// from the declared input range, and every input is checked against it
+// (NE_FLAG_INPUT_RANGE), so a word never needs more digits than it gets.
 //
 // Every stream's entangled output depends only on its own entangled input;
 // the stream the plan marks as lost is simply not computed, and recovery
