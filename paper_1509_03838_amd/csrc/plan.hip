@@ -433,41 +433,58 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
     return launch_status();
 }
 
-// The captured form of a run: the permutation layout passes, then every
-// other launch spread over up to kBranches parallel branches of the graph
-// (the launches touch disjoint groups; running them side by side fills the
-// tail of one with the next), then the inner-product recovery.
+// The captured form of a run: the launches spread over up to kBranches
+// parallel branches of the graph (they touch disjoint groups; running them
+// side by side fills the tail of one with the next), then the inner-product
+// recovery. A permutation layout pass and the permutation launches that read
+// its rows form one chain on one branch.
 static ne_status capture_branches(ne_plan *plan, hipStream_t s)
 {
-    std::vector<const Bucket *> work;
-    for (const Bucket &b : plan->buckets) {
+    std::vector<std::vector<const Bucket *>> chains;
+    int chain_of_cls[2] = {-1, -1};
+    for (const Bucket &b : plan->buckets) {  // layout passes sort first
         if (b.count == 0) continue;
-        if (b.conv < 0)
-            launch_bucket(plan, b, s);
-        else
-            work.push_back(&b);
+        if (b.conv < 0) {
+            chain_of_cls[b.cls] = (int)chains.size();
+            chains.push_back({&b});
+        } else if (b.conv == 0 && b.cls / 64 == NE_OP_PERM) {
+            const int c = chain_of_cls[(b.cls % 16) <= 4 ? 0 : 1];
+            if (c >= 0)
+                chains[c].push_back(&b);
+            else
+                chains.push_back({&b});
+        } else {
+            chains.push_back({&b});
+        }
     }
-    const int nb = (int)std::min<size_t>(plan->branch.size(), work.size());
+    const int nb = (int)std::min<size_t>(plan->branch.size(), chains.size());
     if (nb <= 1) {
-        for (const Bucket *b : work) launch_bucket(plan, *b, s);
+        for (const auto &ch : chains)
+            for (const Bucket *b : ch) launch_bucket(plan, *b, s);
     } else {
         hipError_t e = hipSuccess;
-        // longest-first onto the least loaded branch (cost ~ items x slots)
-        std::vector<const Bucket *> order = work;
-        auto cost = [](const Bucket *b) { return (double)b->count * (b->conv ? 4.0 : 1.0); };
+        // longest chain first onto the least loaded branch (cost ~ items)
+        auto cost = [](const std::vector<const Bucket *> &ch) {
+            double c = 0;
+            for (const Bucket *b : ch) c += (double)b->count * (b->conv > 0 ? 4.0 : 1.0);
+            return c;
+        };
+        std::vector<int> order(chains.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
         std::sort(order.begin(), order.end(),
-                  [&](const Bucket *x, const Bucket *y) { return cost(x) > cost(y); });
+                  [&](int x, int y) { return cost(chains[x]) > cost(chains[y]); });
         std::vector<double> load(nb, 0.0);
-        std::vector<std::vector<const Bucket *>> lanes(nb);
-        for (const Bucket *b : order) {
+        std::vector<std::vector<int>> lanes(nb);
+        for (int ci : order) {
             const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            lanes[i].push_back(b);
-            load[i] += cost(b);
+            lanes[i].push_back(ci);
+            load[i] += cost(chains[ci]);
         }
         e = hipEventRecord(plan->joins[kBranches], s);  // fork
         for (int i = 0; i < nb && e == hipSuccess; ++i) {
             e = hipStreamWaitEvent(plan->branch[i], plan->joins[kBranches], 0);
-            for (const Bucket *b : lanes[i]) launch_bucket(plan, *b, plan->branch[i]);
+            for (int ci : lanes[i])
+                for (const Bucket *b : chains[ci]) launch_bucket(plan, *b, plan->branch[i]);
             if (e == hipSuccess) e = hipEventRecord(plan->joins[i], plan->branch[i]);
             if (e == hipSuccess) e = hipStreamWaitEvent(s, plan->joins[i], 0);  // join
         }
@@ -492,7 +509,7 @@ ne_status ne_plan_capture(ne_plan *plan, ne_stream stream)
     }
     // branch streams and their events, created before the capture begins
     size_t nwork = 0;
-    for (const Bucket &b : plan->buckets) nwork += b.count > 0 && b.conv >= 0;
+    for (const Bucket &b : plan->buckets) nwork += b.count > 0;
     hipError_t e = hipSuccess;
     if (nwork > 1) {
         while (plan->branch.size() < kBranches && e == hipSuccess) {
