@@ -248,6 +248,14 @@ typedef struct ne_group {
                             ring per block of 4 waves, two block barriers per
                             step) or 1 (a ring per wave, no barrier in the
                             step loop); 0: the plan's choice */
+    int32_t tap_copies;  /* conv: copies of each tap-digit plane in LDS: 4
+                            (one per byte alignment, every operand fragment
+                            read aligned) or 1 (a quarter of the LDS, each
+                            fragment realigned in registers; block rings
+                            only, for long kernels); 0: the plan's choice (1
+                            only where it fits more blocks per CU than 4, or
+                            4 does not fit at all) */
+    int32_t reserved;    /* must be 0 */
     const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
     const int32_t *operand;           /* device int32 taps / vector /
                                          permutation indices, 16-byte aligned;

@@ -72,18 +72,28 @@ struct GroupDev {
 
 // Bytes of one copy of one tap-digit plane of the convolution kernel: the
 // reversed taps Q[v] = g[kp + 15 - v], v in [0, 64 nch + 16), behind up to
-// 3 bytes of alignment padding, rounded to 16. The kernel keeps 4 copies
-// per digit plane (one per byte alignment) so that every operand fragment
-// read is dword-aligned.
+// 3 bytes of alignment padding, rounded to 16 (an aligned 20-byte read at
+// the last fragment stays inside).
 __host__ __device__ constexpr size_t conv_tap_plane_bytes(int nch)
 {
     return ((size_t)64 * nch + 16 + 3 + 15) & ~(size_t)15;
 }
 
+// LDS layouts of the convolution kernel (a variant axis):
+//   0: one ring per block (4 waves), tap-digit planes in 4 copies (one per
+//      byte alignment: every operand fragment is four aligned words);
+//   1: one ring per wave, tap planes in 4 copies;
+//   2: one ring per block, tap planes in one copy (a quarter of the LDS; each
+//      fragment is realigned from five words in registers), for kernels
+//      whose windows leave no room for 4 copies.
+constexpr int kConvLayouts = 3;
+__host__ __device__ constexpr int conv_layout_waves(int layout) { return layout == 1 ? 1 : 4; }
+__host__ __device__ constexpr int conv_layout_copies(int layout) { return layout == 2 ? 1 : 4; }
+
 // LDS bytes of the convolution kernel's tap planes and chunk mask.
-__host__ __device__ constexpr size_t conv_tap_lds(int nch, int lb)
+__host__ __device__ constexpr size_t conv_tap_lds(int nch, int lb, int copies)
 {
-    return (size_t)4 * lb * conv_tap_plane_bytes(nch) + 16;
+    return (size_t)copies * lb * conv_tap_plane_bytes(nch) + 16;
 }
 
 struct Item {
@@ -96,10 +106,12 @@ struct Item {
 // First index: the taps' top digit is dense (0) or sparse (1); second: one
 // staging ring per block of 4 waves (0) or one per wave (1). Null where no
 // group needs the variant.
+// Indexed [sparse top tap digit][layout].
 struct ConvKernel {
-    void (*launch[2][2])(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
-                         size_t lds, hipStream_t s);
-    hipError_t (*prepare[2][2])(size_t lds);  // raises the kernel's dynamic LDS limit
+    void (*launch[2][kConvLayouts])(const GroupDev *g, const Item *items, uint32_t nitems,
+                                    uint32_t *flags, size_t lds, hipStream_t s);
+    hipError_t (*prepare[2][kConvLayouts])(size_t lds);  // raises the dynamic LDS limit
+    hipError_t (*attributes[2][kConvLayouts])(hipFuncAttributes *a);  // of the loaded kernel
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);

@@ -15,26 +15,42 @@ namespace ne {
 
 namespace {
 
-template <int LA, int LB, int GW, int SP>
+template <int LA, int LB, int L, int SP>
 void launch_one(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
                 size_t lds, hipStream_t s)
 {
     const uint32_t grid = ((nitems + 7u) >> 3) << 3;
-    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW, SP>), dim3(grid),
+    hipLaunchKernelGGL((fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, conv_layout_waves(L), SP,
+                                         conv_layout_copies(L)>),
+                       dim3(grid),
                        dim3(fk::kBlock), lds, s, g, items, nitems, flags);
 }
 
-template <int LA, int LB, int GW, int SP>
+template <int LA, int LB, int L, int SP>
+const void *kernel_of()
+{
+    return reinterpret_cast<const void *>(
+        &fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, conv_layout_waves(L), SP,
+                          conv_layout_copies(L)>);
+}
+
+template <int LA, int LB, int L, int SP>
 hipError_t prepare_one(size_t lds)
 {
-    return hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&fk::k_conv_fused<LA, LB, NE_SLOTS, NE_KCLASS, GW, SP>),
+    return hipFuncSetAttribute(kernel_of<LA, LB, L, SP>(),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int LA, int LB, int L, int SP>
+hipError_t attributes_one(hipFuncAttributes *a)
+{
+    return hipFuncGetAttributes(a, kernel_of<LA, LB, L, SP>());
 }
 
 using LaunchFn = void (*)(const GroupDev *, const Item *, uint32_t, uint32_t *, size_t,
                           hipStream_t);
 using PrepareFn = hipError_t (*)(size_t);
+using AttributesFn = hipError_t (*)(hipFuncAttributes *);
 
 template <int LA, int LB, int SP>
 constexpr bool needed()
@@ -45,20 +61,29 @@ constexpr bool needed()
         return conv_variant_needed(NE_KCLASS, NE_SLOTS, LA, LB, SP);
 }
 
-template <int LA, int LB, int GW, int SP>
+template <int LA, int LB, int L, int SP>
 constexpr LaunchFn launcher()
 {
     if constexpr (needed<LA, LB, SP>())
-        return &launch_one<LA, LB, GW, SP>;
+        return &launch_one<LA, LB, L, SP>;
     else
         return nullptr;
 }
 
-template <int LA, int LB, int GW, int SP>
+template <int LA, int LB, int L, int SP>
 constexpr PrepareFn preparer()
 {
     if constexpr (needed<LA, LB, SP>())
-        return &prepare_one<LA, LB, GW, SP>;
+        return &prepare_one<LA, LB, L, SP>;
+    else
+        return nullptr;
+}
+
+template <int LA, int LB, int L, int SP>
+constexpr AttributesFn attributer()
+{
+    if constexpr (needed<LA, LB, SP>())
+        return &attributes_one<LA, LB, L, SP>;
     else
         return nullptr;
 }
@@ -66,10 +91,13 @@ constexpr PrepareFn preparer()
 template <int LA, int LB>
 constexpr ConvKernel entry()
 {
-    return ConvKernel{{{launcher<LA, LB, 4, 0>(), launcher<LA, LB, 1, 0>()},
-                       {launcher<LA, LB, 4, 1>(), launcher<LA, LB, 1, 1>()}},
-                      {{preparer<LA, LB, 4, 0>(), preparer<LA, LB, 1, 0>()},
-                       {preparer<LA, LB, 4, 1>(), preparer<LA, LB, 1, 1>()}}};
+    return ConvKernel{
+        {{launcher<LA, LB, 0, 0>(), launcher<LA, LB, 1, 0>(), launcher<LA, LB, 2, 0>()},
+         {launcher<LA, LB, 0, 1>(), launcher<LA, LB, 1, 1>(), launcher<LA, LB, 2, 1>()}},
+        {{preparer<LA, LB, 0, 0>(), preparer<LA, LB, 1, 0>(), preparer<LA, LB, 2, 0>()},
+         {preparer<LA, LB, 0, 1>(), preparer<LA, LB, 1, 1>(), preparer<LA, LB, 2, 1>()}},
+        {{attributer<LA, LB, 0, 0>(), attributer<LA, LB, 1, 0>(), attributer<LA, LB, 2, 0>()},
+         {attributer<LA, LB, 0, 1>(), attributer<LA, LB, 1, 1>(), attributer<LA, LB, 2, 1>()}}};
 }
 
 #define NE_ROW(LA) {entry<LA, 1>(), entry<LA, 2>(), entry<LA, 3>(), entry<LA, 4>()}

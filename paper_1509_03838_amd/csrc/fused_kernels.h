@@ -275,6 +275,14 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
 
 // ----------------------------------------------------- convolution kernel
 
+// The LDS words of one tap-operand fragment: 4 aligned words, or the 5
+// aligned words that cover 16 bytes at any byte shift.
+template <int TC>
+struct TapWords {
+    static constexpr int n = TC == 4 ? 4 : 5;
+    uint32_t w[n];
+};
+
 // One variant per kernel class (0 entangled, 1 plain, 2 checksum) and slot
 // count NS, so that the mode, M and the slot loop are compile-time: the
 // descriptor's mode and M must match (the planner picks the variant).
@@ -287,7 +295,8 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
 // own positions; a wave's LDS accesses take effect in program order, so the
 // step loop has no barrier at all, at the price of a window of kp extra
 // positions per wave instead of per block.
-template <int LA, int LB, int NS, int KCLASS, int GW, int SP>
+// TC: copies of each tap-digit plane (4, or 1 with GW = 4, below).
+template <int LA, int LB, int NS, int KCLASS, int GW, int SP, int TC>
 __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
                                                        const Item *__restrict__ items,
                                                        uint32_t nitems, uint32_t *flags)
@@ -298,6 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     static_assert(M >= 1 && M <= kFusedMaxM, "slot count");
     static_assert(GW == 1 || GW == 4, "waves per ring");
     static_assert(SP == 0 || (SP == 1 && LB >= 2), "sparse top tap digit");
+    static_assert(TC == 4 || (TC == 1 && GW == 4), "tap-plane copies");
     constexpr int LBM = LB - SP;     // tap digit planes of the main pass
     constexpr int SPAN = 256 * GW;   // positions a ring advances per step
     constexpr int GT = 64 * GW;      // threads staging one ring
@@ -323,15 +333,16 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     // (each tap would appear 16 times): with the reversed taps
     // Q[v] = g[kp + 15 - v], lane (j, h) of chunk c needs the 16 bytes
     // Q[64c + 16h + 15 - j ...], consecutive but at a byte alignment set by
-    // j. Each digit plane of Q is kept in 4 copies, copy r shifted by
-    // (4 - r) mod 4 bytes, so that the lane reads its fragment as 4
-    // dword-aligned words from the copy matching its alignment.
+    // j. With TC = 4 copies per digit plane, copy r shifted by (4 - r) mod 4
+    // bytes, the lane reads its fragment as 4 dword-aligned words from the
+    // copy matching its alignment; with one copy it reads the 5 aligned
+    // words that cover the fragment and shifts them into place.
     const int tpb = (int)conv_tap_plane_bytes(nch);
     unsigned char *taps = smem;
     // Bit c of tmask: chunk c's top tap-digit plane has a nonzero digit
     // (sparse-top variants; chunks from 64 on always run it).
-    uint32_t *tmask = reinterpret_cast<uint32_t *>(smem + (size_t)4 * LB * tpb);
-    const size_t ring0 = (size_t)4 * LB * tpb + 16;
+    uint32_t *tmask = reinterpret_cast<uint32_t *>(smem + (size_t)TC * LB * tpb);
+    const size_t ring0 = (size_t)TC * LB * tpb + 16;
     unsigned char *planes = smem + ring0 + (size_t)grp * nplanes * lap<LA>() * ring;
     if (SP) {
         if (tid < 2) tmask[tid] = 0;
@@ -348,8 +359,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
 #pragma unroll
             for (int b = 0; b < LB; ++b) {
                 const unsigned char d = (unsigned char)((u >> (8 * b)) & 0xffu) ^ 0x80u;
+                if constexpr (TC == 4) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) taps[(b * 4 + r) * tpb + ((4 - r) & 3) + v] = d;
+                    for (int r = 0; r < 4; ++r) taps[(b * 4 + r) * tpb + ((4 - r) & 3) + v] = d;
+                } else {
+                    taps[b * tpb + v] = d;
+                }
                 if (SP && b == LB - 1 && d != 0) {
                     // the chunks whose fragments read Q[v]: 64c <= v <= 64c + 78
                     for (int c = v >> 6; c >= 0 && 64 * c + 78 >= v; --c)
@@ -358,10 +373,31 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             }
         }
     }
-    // This lane's fragment offset within plane b, chunk c: + (4 b) tpb + 64 c.
+    // This lane's fragment of plane b, chunk c: at tap_lane + TC b tpb + 64 c,
+    // 4 aligned words (TC = 4), or 16 bytes at byte shift tsh from an aligned
+    // word (TC = 1). The words are loaded as they lie and shifted into place
+    // only when the fragment is used, so that a load in flight is not waited
+    // for early.
     const int tj = lane & 15, th = lane >> 4;
     const int tr = (15 - tj) & 3;
-    const int tap_lane = tr * tpb + ((4 - tr) & 3) + 16 * th + 15 - tj;
+    const int tap_lane = TC == 4 ? tr * tpb + ((4 - tr) & 3) + 16 * th + 15 - tj
+                                 : (16 * th + 15 - tj) & ~3;
+    const uint32_t tsh = (uint32_t)(15 - tj) & 3u;
+    auto tap_load = [&](int b, int c, TapWords<TC> &t) {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(taps + tap_lane + TC * b * tpb + 64 * c);
+#pragma unroll
+        for (int i = 0; i < TapWords<TC>::n; ++i) t.w[i] = q[i];
+    };
+    auto tap_frag = [&](const TapWords<TC> &t) -> v4i {
+        if constexpr (TC == 4) {
+            return v4i{(int)t.w[0], (int)t.w[1], (int)t.w[2], (int)t.w[3]};
+        } else {
+            return v4i{(int)__builtin_amdgcn_alignbyte(t.w[1], t.w[0], tsh),
+                       (int)__builtin_amdgcn_alignbyte(t.w[2], t.w[1], tsh),
+                       (int)__builtin_amdgcn_alignbyte(t.w[3], t.w[2], tsh),
+                       (int)__builtin_amdgcn_alignbyte(t.w[4], t.w[3], tsh)};
+        }
+    };
 
     // The digit planes are rings of `ring` bytes (the window SPAN + kp, a
     // multiple of 16, so no 16-byte access wraps): ring offset 0 is position
@@ -444,52 +480,55 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
             v4i acc[S];
             int o = aoff;
-            auto load = [&](int c, v4i(&bf)[LBM], v4i(&af)[LA]) {
+            using TW = TapWords<TC>;
+            auto load = [&](int c, TW(&bf)[LBM], v4i(&af)[LA]) {
                 const unsigned char *pa = pbase + plane_off(o, lap<LA>());
                 o += 64;
                 o = o >= ring ? o - ring : o;
 #pragma unroll
-                for (int b = 0; b < LBM; ++b) {
-                    const uint32_t *q = reinterpret_cast<const uint32_t *>(
-                        taps + tap_lane + 4 * b * tpb + 64 * c);
-                    bf[b] = v4i{(int)q[0], (int)q[1], (int)q[2], (int)q[3]};
-                }
+                for (int b = 0; b < LBM; ++b) tap_load(b, c, bf[b]);
 #pragma unroll
                 for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);
             };
-            auto mma = [&](const v4i(&bf)[LBM], const v4i(&af)[LA]) {
+            auto mma = [&](const TW(&bw)[LBM], const v4i(&af)[LA]) {
 #pragma unroll
-                for (int b = 0; b < LBM; ++b)
+                for (int b = 0; b < LBM; ++b) {
+                    const v4i bf = tap_frag(bw[b]);
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
                         if (a + b < 8)
-                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b],
+                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf,
                                                                               acc[a + b], 0, 0, 0);
+                }
             };
             // chunk 0 starts every weight the main pass reaches (its first pair
             // writes it with a zero accumulator); a weight only the sparse top
             // plane reaches starts at zero
-            auto mma_first = [&](const v4i(&bf)[LBM], const v4i(&af)[LA]) {
+            auto mma_first = [&](const TW(&bw)[LBM], const v4i(&af)[LA]) {
                 if (SP && LA + LB - 2 < 8) acc[LA + LB - 2] = v4i{0, 0, 0, 0};
 #pragma unroll
-                for (int b = 0; b < LBM; ++b)
+                for (int b = 0; b < LBM; ++b) {
+                    const v4i bf = tap_frag(bw[b]);
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
                         if (a + b < 8)
                             acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af[a], bf[b], (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
+                                af[a], bf, (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
                                 0, 0, 0);
+                }
             };
             if constexpr (GW == 1) {
                 // Per-wave rings serve short kernels (few chunks): one
                 // fragment buffer, fewer registers, more waves per SIMD.
                 {
-                    v4i bf[LBM], af[LA];
+                    TW bf[LBM];
+                    v4i af[LA];
                     load(0, bf, af);
                     mma_first(bf, af);
                 }
                 for (int c = 1; c < nch; ++c) {
-                    v4i bf[LBM], af[LA];
+                    TW bf[LBM];
+                    v4i af[LA];
                     load(c, bf, af);
                     mma(bf, af);
                 }
@@ -500,15 +539,16 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                 // every LDS load (only the current buffer's are in flight),
                 // then issues the next chunk's loads, then the current chunk's
                 // products; the scheduling barriers keep that order.
-                auto half = [&](int cn, bool more, v4i(&bfn)[LBM], v4i(&afn)[LA],
-                                const v4i(&bfc)[LBM], const v4i(&afc)[LA]) {
+                auto half = [&](int cn, bool more, TW(&bfn)[LBM], v4i(&afn)[LA],
+                                const TW(&bfc)[LBM], const v4i(&afc)[LA]) {
                     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
                     __builtin_amdgcn_sched_barrier(0);
                     if (more) load(cn, bfn, afn);
                     __builtin_amdgcn_sched_barrier(0);
                     mma(bfc, afc);
                 };
-                v4i bf0[LBM], af0[LA], bf1[LBM], af1[LA];
+                TW bf0[LBM], bf1[LBM];
+                v4i af0[LA], af1[LA];
                 load(0, bf0, af0);
                 __builtin_amdgcn_s_waitcnt(0xc07f);
                 __builtin_amdgcn_sched_barrier(0);
@@ -527,9 +567,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                     int ot = aoff + 64 * c;
                     ot = ot >= ring ? ot - ring : ot;
                     const unsigned char *pa = pbase + plane_off(ot, lap<LA>());
-                    const uint32_t *q = reinterpret_cast<const uint32_t *>(
-                        taps + tap_lane + 4 * (LB - 1) * tpb + 64 * c);
-                    const v4i bt = {(int)q[0], (int)q[1], (int)q[2], (int)q[3]};
+                    TapWords<TC> tw;
+                    tap_load(LB - 1, c, tw);
+                    const v4i bt = tap_frag(tw);
                     v4i af[LA];
 #pragma unroll
                     for (int a = 0; a < LA; ++a) af[a] = *reinterpret_cast<const v4i *>(pa + 16 * a);

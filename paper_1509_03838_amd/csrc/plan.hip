@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <vector>
@@ -16,8 +17,8 @@ using namespace ne;
 
 struct Bucket {
     int conv;             // 1: convolution kernel, 0: element-wise kernel
-    int cls, la, lb;      // convolution: variant id (((class * 16 + slots) << 2) |
-                          // (sparse top tap digit << 1) | per-wave rings) and digits; element-wise: variant id
+    int cls, la, lb;      // convolution: variant id (((class * 16 + slots) << 3) |
+                          // (sparse top tap digit << 2) | LDS layout) and digits; element-wise: variant id
                           // ((op * 4 + class) * 16 + slots); layout pass: slot class
     const ConvKernel *ck; // convolution kernel variant
     StreamLaunch sk;      // element-wise kernel variant
@@ -57,6 +58,29 @@ constexpr size_t kBranches = 4;  // parallel branches of a captured run
 
 inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Blocks of a convolution variant that its registers let share a CU: a
+// block's 4 waves take one wave slot on each SIMD, and a SIMD holds
+// 512 / (VGPRs per lane, in granules of 8) waves. Read from the loaded
+// kernel once per variant; 4 (the plan's cap) where no device can say.
+int register_blocks(const ConvKernel *ck, int sparse, int layout)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const ConvKernel *, int, int>, int> cache;
+    const auto key = std::make_tuple(ck, sparse, layout);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int blocks = 4;
+    hipFuncAttributes a{};
+    if (ck->attributes[sparse][layout] && ck->attributes[sparse][layout](&a) == hipSuccess &&
+        a.numRegs > 0)
+        blocks = std::min(4, 512 / ((a.numRegs + 7) & ~7));
+    else
+        (void)hipGetLastError();
+    cache[key] = blocks;
+    return blocks;
+}
+
 }  // namespace
 
 // Kernel variants whose LDS exceeds the default limit get it raised (once per
@@ -65,7 +89,7 @@ static hipError_t plan_prepare(const ne_plan *plan)
 {
     for (const Bucket &b : plan->buckets) {
         if (b.conv <= 0 || b.lds <= 64 * 1024) continue;
-        const hipError_t e = b.ck->prepare[(b.cls >> 1) & 1][b.cls & 1](b.lds);
+        const hipError_t e = b.ck->prepare[(b.cls >> 2) & 1][b.cls & 3](b.lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -111,6 +135,9 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
         if (u.steps < 0 || u.steps > 4096) return fail(NE_EINVAL);
         if (u.ring_waves != 0 && u.ring_waves != 1 && u.ring_waves != 4) return fail(NE_EINVAL);
+        if (u.tap_copies != 0 && u.tap_copies != 1 && u.tap_copies != 4) return fail(NE_EINVAL);
+        if (u.tap_copies == 1 && u.ring_waves == 1) return fail(NE_EINVAL);
+        if (u.reserved != 0) return fail(NE_EINVAL);
         const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
         const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
         if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
@@ -208,34 +235,54 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
             // LDS: tap-digit planes | digit-plane rings (one per block, or
             // one per wave with a window of 256 + kp each) | raw int32
-            // staging of one step (the prefetch, below).
-            auto ring_lds = [&](int gw) {
-                return conv_tap_lds(G.nch, lb) +
+            // staging of one step (the prefetch, below). Layouts: 0 block
+            // ring, 4 tap copies; 1 per-wave rings, 4 copies; 2 block ring,
+            // one copy.
+            auto ring_lds = [&](int layout) {
+                const int gw = conv_layout_waves(layout);
+                return conv_tap_lds(G.nch, lb, conv_layout_copies(layout)) +
                        (size_t)(4 / gw) * nplanes * (la | 1) * (size_t)(256 * gw + G.kp);
             };
-            // Blocks of this variant that can share a CU (LDS-bound; at most
-            // 4, the register budget), with the raw-input prefetch buffer
-            // (M x 4 KiB) when it costs no block.
-            const size_t raw = (size_t)u.M * 4096;
-            auto fit = [&](int w, bool dma) {
-                const size_t b = ring_lds(w) + (dma ? raw : 0);
-                return b > kMaxLds ? (size_t)0 : std::min<size_t>(4, kMaxLds / b);
-            };
-            auto use_dma = [&](int w) { return g_conv_steps > 1 && fit(w, true) >= fit(w, false); };
-            auto blocks = [&](int w) { return fit(w, use_dma(w)); };
-            int gw = u.ring_waves;
-            if (gw == 0) gw = blocks(1) >= blocks(4) ? 1 : 4;  // per-wave rings: no barriers
-            if (blocks(gw) == 0) return fail(NE_EUNSUP);
-            G.ring_waves = gw;
-            G.ring = 256 * gw + G.kp;
-            G.dma = use_dma(gw);
-            const size_t lds = ring_lds(gw) + (G.dma ? raw : 0);
-            const int64_t strip = (int64_t)g_conv_steps * kConvTile;
-            const int64_t nstrips = (n_out + strip - 1) / strip;
+            // Blocks of this variant that can share a CU (bound by LDS and
+            // by registers), with the raw-input prefetch buffer (M x 4 KiB)
+            // when it costs no block.
             const int kclass = conv_class_of_mode(mode);
             const ConvKernel *ck = conv_kernel(kclass, G.nslots, la, lb);
             if (!ck || !ck->launch[dc.sparse][0]) return fail(NE_EUNSUP);
-            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 2) | (dc.sparse << 1) | (gw == 1),
+            const size_t raw = (size_t)u.M * 4096;
+            auto fit = [&](int layout, bool dma) {
+                const size_t b = ring_lds(layout) + (dma ? raw : 0);
+                if (b > kMaxLds) return (size_t)0;
+                return std::min<size_t>(register_blocks(ck, dc.sparse, layout), kMaxLds / b);
+            };
+            auto use_dma = [&](int layout) {
+                return g_conv_steps > 1 && fit(layout, true) >= fit(layout, false);
+            };
+            auto blocks = [&](int layout) { return fit(layout, use_dma(layout)); };
+            // A block ring keeps 4 tap copies unless one copy fits more
+            // blocks (or is the only fit); per-wave rings (no barriers) win
+            // ties with block rings.
+            auto block_ring = [&]() {
+                if (u.tap_copies == 4) return 0;
+                if (u.tap_copies == 1) return 2;
+                return blocks(2) > blocks(0) ? 2 : 0;
+            };
+            int layout;
+            if (u.ring_waves == 1 || (u.ring_waves == 0 && u.tap_copies != 1)) {
+                layout = 1;
+                if (u.ring_waves == 0 && blocks(block_ring()) > blocks(1)) layout = block_ring();
+            } else {
+                layout = block_ring();
+            }
+            if (blocks(layout) == 0) return fail(NE_EUNSUP);
+            const int gw = conv_layout_waves(layout);
+            G.ring_waves = gw;
+            G.ring = 256 * gw + G.kp;
+            G.dma = use_dma(layout);
+            const size_t lds = ring_lds(layout) + (G.dma ? raw : 0);
+            const int64_t strip = (int64_t)g_conv_steps * kConvTile;
+            const int64_t nstrips = (n_out + strip - 1) / strip;
+            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 3) | (dc.sparse << 2) | layout,
                                        la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
@@ -279,7 +326,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv > 0 ? bucket_lds[kv.first] : 0;
-        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 2) / 16, (b.cls >> 2) % 16, b.la, b.lb) : nullptr;
+        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 3) / 16, (b.cls >> 3) % 16, b.la, b.lb) : nullptr;
         b.sk = b.conv == 0 ? stream_kernel(b.cls / 64, (b.cls / 16) % 4, b.cls % 16) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
@@ -417,7 +464,7 @@ static void launch_bucket(const ne_plan *plan, const Bucket &b, hipStream_t s)
     if (b.conv < 0)
         fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
     else if (b.conv)
-        b.ck->launch[(b.cls >> 1) & 1][b.cls & 1](plan->d_groups, plan->d_items + b.first, b.count,
+        b.ck->launch[(b.cls >> 2) & 1][b.cls & 3](plan->d_groups, plan->d_items + b.first, b.count,
                                                   plan->d_flags, b.lds, s);
     else
         b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);

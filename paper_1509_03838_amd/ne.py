@@ -37,6 +37,7 @@ class GroupC(ctypes.Structure):
                 ("n_operand", ctypes.c_int64), ("scalar", ctypes.c_int64),
                 ("lost", ctypes.c_int32), ("in_bits", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("ring_waves", ctypes.c_int32),
+                ("tap_copies", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("c", ctypes.c_void_p * FUSED_MAX_M), ("operand", ctypes.c_void_p),
                 ("out", ctypes.c_void_p * FUSED_MAX_M)]
 
@@ -249,10 +250,11 @@ class GroupSpec:
     for scale), M int64 output tensors of n_out elements."""
 
     def __init__(self, op: str, c: Sequence, operand, out: Sequence, scalar: int = 0,
-                 lost: int = -1, in_bits: int = 32, steps: int = 0, ring_waves: int = 0):
+                 lost: int = -1, in_bits: int = 32, steps: int = 0, ring_waves: int = 0,
+                 tap_copies: int = 0):
         self.op, self.c, self.operand, self.out = op, list(c), operand, list(out)
         self.scalar, self.lost, self.in_bits = int(scalar), int(lost), int(in_bits)
-        self.steps, self.ring_waves = int(steps), int(ring_waves)
+        self.steps, self.ring_waves, self.tap_copies = int(steps), int(ring_waves), int(tap_copies)
 
     def to_c(self) -> GroupC:
         import torch
@@ -270,6 +272,7 @@ class GroupSpec:
         g.in_bits = self.in_bits
         g.steps = self.steps
         g.ring_waves = self.ring_waves
+        g.tap_copies = self.tap_copies
         for m, t in enumerate(self.c):
             g.c[m] = _ptr(t)
         for m, t in enumerate(self.out):

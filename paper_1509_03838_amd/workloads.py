@@ -129,6 +129,24 @@ def config_long_kernel(seed: int = SEED_BASE + 3, groups: int = 256, n: int = 26
     return [conv_group(g, 3, n, K, -(1 << 15), 1 << 15) for _ in range(groups)]
 
 
+FIG2_M = (3, 8)
+FIG2_TAPS = (100, 250, 500, 1000, 2000, 3000, 4500)
+FIG2_N = 1_000_000
+FIG2_BITS = 15
+
+
+def config_fig2(M: int, K: int, seed: int = SEED_BASE + 5, n: int = FIG2_N) -> Group:
+    """One group shaped as in the paper's experiment (Sec. V, Fig. 2): M
+    streams of 10^6 samples and one K-tap kernel, samples and taps uniform in
+    [-2^14, 2^14) held as int32 -- the widest range whose worst-case output
+    at K = 4500 fits the M = 3 bound at w = 64. The streams depend on M and
+    the seed only, the taps on M, K and the seed."""
+    lo, hi = -(1 << (FIG2_BITS - 1)), 1 << (FIG2_BITS - 1)
+    c = uniform_i32(rng(seed * 16 + M), lo, hi, (M, n))
+    k = uniform_i32(rng((seed * 16 + M) * 8192 + K), lo, hi, K)
+    return Group("conv", c, k, 0, -1)
+
+
 @dataclass
 class Job:
     arrival_s: float

@@ -193,3 +193,34 @@ def test_workspace_holds_permutation_rows(lib):
 def test_ring_waves_values(lib, rw, status):
     g = _group(ring_waves=rw)
     assert _ws(lib, [g])[0] == status
+
+
+@pytest.mark.parametrize("rw,tc,status", [(0, 0, 0), (0, 1, 0), (0, 4, 0), (4, 1, 0), (4, 4, 0),
+                                          (1, 4, 0), (1, 1, -1), (0, 2, -1), (0, -1, -1)])
+def test_tap_copies_values(lib, rw, tc, status):
+    """One tap copy exists only with a block ring."""
+    g = _group(ring_waves=rw, tap_copies=tc)
+    assert _ws(lib, [g])[0] == status
+
+
+def test_reserved_field_must_be_zero(lib):
+    assert _ws(lib, [_group(reserved=1)])[0] == -1
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("M", [3, 8])
+def test_paper_experiment_shapes_plan(lib, mode, M):
+    """The paper's experiment (Sec. V) convolves M in {3, 8} streams of 10^6
+    samples with up to 4500 taps: every mode plans at 15-bit inputs (the
+    widest whose worst case fits D for M = 3 at K = 4500); far longer
+    kernels are refused as unsupported (their windows exceed LDS), not
+    mis-planned."""
+    def grp(K):
+        g = _group(M=M, in_bits=15, n=10**6, n_operand=K)
+        for m in range(M):
+            g.c[m] = FAKE + 256 * m
+            g.out[m] = FAKE + 4096 + 1024 * m
+        return g
+    for K in (100, 1000, 4500):
+        assert _ws(lib, [grp(K)], mode)[0] == 0, K
+    assert _ws(lib, [grp(16000)], mode)[0] in (-2, -4)

@@ -99,3 +99,33 @@ def test_uneven_benchmark_configuration():
             else:
                 ref = oracle.apply("perm", x, g.operand)[pos]
             assert np.array_equal(o[m][idx].cpu().numpy(), ref), (g.op, g.M, g.n, m)
+
+
+@pytest.mark.parametrize("M", [3, 8])
+def test_paper_experiment_longest_kernel(M):
+    """The longest point of the paper's experiment (Sec. V, Fig. 2): M
+    streams of 10^6 samples, 4500 taps, every mode and one lost stream, each
+    replayed twice from one captured plan."""
+    g = wl.config_fig2(M, 4500)
+    c = [torch.from_numpy(np.ascontiguousarray(r)).to(DEV) for r in g.c]
+    k = torch.from_numpy(g.operand).to(DEV)
+    n_out = g.n + g.operand.size - 1
+    rng = wl.rng(14)
+    pos = positions(n_out, rng, 300)
+    idx = torch.from_numpy(pos).to(DEV)
+    ref = [oracle.conv_at(g.c[m], g.operand, pos) for m in range(M)]
+    for mode, lost in (("entangled", -1), ("entangled", M - 1), ("plain", -1),
+                       ("plain_same", -1), ("checksum", -1), ("checksum", 0)):
+        out = [torch.full((n_out,), -1, dtype=torch.int64, device=DEV) for _ in range(M)]
+        spec = ne.GroupSpec("conv", c, k, out, 0, lost, wl.FIG2_BITS)
+        plan = ne.Plan([spec], mode)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            plan.capture(s)
+            plan.launch(s)
+            plan.launch(s)
+            s.synchronize()
+        assert plan.flags() == 0
+        for m in range(M):
+            assert np.array_equal(out[m][idx].cpu().numpy(), ref[m]), (mode, lost, m)
+        plan.close()

@@ -28,7 +28,7 @@ class DevGroup:
     """A workloads.Group on the device with output buffers."""
 
     def __init__(self, grp: wl.Group, in_bits: int, lost: int = -1, mode: str = "entangled",
-                 ring_waves: int = 0):
+                 ring_waves: int = 0, tap_copies: int = 0):
         self.grp = grp
         self.c = [dev32(row) for row in grp.c]
         self.operand = None if grp.op == "scale" else dev32(grp.operand)
@@ -36,7 +36,7 @@ class DevGroup:
         self.out = [torch.full((max(self.n_out, 1),), POISON, dtype=torch.int64, device=DEV)[:self.n_out]
                     for _ in range(grp.M)]
         self.spec = ne.GroupSpec(grp.op, self.c, self.operand, self.out, grp.scalar, lost, in_bits,
-                                 ring_waves=ring_waves)
+                                 ring_waves=ring_waves, tap_copies=tap_copies)
 
     def result(self):
         return host(self.out)
@@ -237,16 +237,18 @@ def test_tuning_steps(steps, ring_waves):
                                        ("checksum", 2)])
 def test_every_convolution_variant(mode, m_lo):
     """Every (M, digit-count) kernel variant the planner can pick for this
-    mode, on a short convolution with a ragged tail, with and without a lost
-    stream: inputs of 1, 2, 8, 9, 16, 17, 24, 25 and 31 bits."""
+    mode, in each LDS layout (block ring with 4 or 1 tap copies, per-wave
+    rings), on a short convolution with a ragged tail, with and without a
+    lost stream: inputs of 1, 2, 8, 9, 16, 17, 24, 25 and 31 bits."""
     ran = 0
     for M in range(m_lo, 9):
         for bits in (1, 2, 8, 9, 16, 17, 24, 25, 31):
             grp = make("conv", M, 1500, 7, bits, seed=7000 + 100 * M + bits)
             ref = oracle.apply("conv", grp.c, grp.operand)
-            for lost, rw in ([(-1, 4), (M - 1, 1)] if mode in ("entangled", "checksum")
-                             else [(-1, 4), (-1, 1)]):
-                dg = DevGroup(grp, bits, lost, mode, ring_waves=rw)
+            for lost, rw, tc in ([(-1, 4, 4), (M - 1, 1, 0), (M - 1, 4, 1)]
+                                 if mode in ("entangled", "checksum")
+                                 else [(-1, 4, 4), (-1, 1, 0), (-1, 4, 1)]):
+                dg = DevGroup(grp, bits, lost, mode, ring_waves=rw, tap_copies=tc)
                 try:
                     _, flags = run([dg], mode)
                 except ne.NeError as e:
@@ -258,8 +260,8 @@ def test_every_convolution_variant(mode, m_lo):
     assert ran > 0
 
 
-@pytest.mark.parametrize("ring_waves", [1, 4])
-def test_sparse_top_tap_digit_windows(ring_waves):
+@pytest.mark.parametrize("ring_waves,tap_copies", [(1, 0), (4, 4), (4, 1)])
+def test_sparse_top_tap_digit_windows(ring_waves, tap_copies):
     """16-bit taps need a third balanced digit only above 127 * 257; the
     kernel runs that digit plane just for the 64-wide chunks whose operand
     fragments touch such a tap. One large tap at chunk edges, every loss."""
@@ -272,7 +274,7 @@ def test_sparse_top_tap_digit_windows(ring_waves):
         grp = wl.Group("conv", c, k)
         ref = oracle.apply("conv", grp.c, grp.operand)
         for lost in (-1, 0, 2):
-            dg = DevGroup(grp, 16, lost, ring_waves=ring_waves)
+            dg = DevGroup(grp, 16, lost, ring_waves=ring_waves, tap_copies=tap_copies)
             _, flags = run([dg], conv_steps=2)
             assert flags == 0
             assert np.array_equal(dg.result(), ref), (pos, lost)
