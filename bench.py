@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="use the default tile steps instead of the autotuner's")
     p.add_argument("--config", default="batched",
-                   choices=("batched", "small", "uneven", "long", "serve", "fig2"),
+                   choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain"),
                    help="workload; the benchmark line is the batched one")
     p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -123,6 +123,8 @@ def main():
         return serve_line(args, wl)
     if args.config == "fig2":
         return fig2_line(args, wl)
+    if args.config == "chain":
+        return chain_line(args, wl)
     t_gen = time.perf_counter()
     cfg = CONFIGS[args.config]
     groups, in_bits, describe = cfg(wl, args)
@@ -363,6 +365,118 @@ def fig2_line(args, wl):
                      "hbm_GBps": round(hbm, 1)},
         "sweep_ms_total": {m: round(v, 4) for m, v in tot.items()},
         "sweep": points,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def chain_line(args, wl):
+    """A series of operations on entangled streams (Sec. II): 3 streams of
+    2^22 samples in [-2^9, 2^9); add a vector, scale, convolve with 64 taps,
+    permute, add another vector (operands in the same range); one
+    entanglement before the series and one extraction after it, against the
+    same series on the raw streams. Per-step kernels, one launch each."""
+    import numpy as np
+    import torch
+    from paper_1509_03838_amd import ne
+
+    dev = torch.device("cuda:0")
+    M, n, bits = 3, 1 << 22, 10
+    c = wl.uniform_i32(wl.rng(wl.SEED_BASE + 6), -(1 << (bits - 1)), 1 << (bits - 1), (M, n))
+    ops = wl.chain_series(wl.rng(wl.SEED_BASE + 7), n, wl.CHAIN_RECIPE, bits=bits, K=64)
+    l = ne.params(M)[0]
+    stream = torch.cuda.Stream()
+
+    def dev_ops(entangled):
+        out = []
+        for op, g, sc in ops:
+            if op == "scale":
+                out.append(ne.ChainOp(op, None, sc))
+                continue
+            dg = torch.from_numpy(np.ascontiguousarray(g)).to(dev)
+            if op == "add":
+                if entangled:
+                    ge = torch.empty(g.size, dtype=torch.int64, device=dev)
+                    ne.entangle_operand(dg, ge, l)
+                    torch.cuda.synchronize()
+                    dg = ge
+                else:
+                    dg = dg if out == [] else dg.to(torch.int64)
+            out.append(ne.ChainOp(op, dg, sc, operand_bits=bits))
+        return out
+
+    ent_ops, plain_ops = dev_ops(True), dev_ops(False)
+    n_out, bound = ne.chain_check(M, bits, n, ent_ops)
+    cd = [torch.from_numpy(row).to(dev) for row in c]
+    eps = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(M)]
+    delta = [torch.empty(n_out, dtype=torch.int64, device=dev) for _ in range(M)]
+    dhat = [torch.empty(n_out, dtype=torch.int64, device=dev) for _ in range(M)]
+    first = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(M)]
+    ws_e = torch.empty(ne.chain_workspace_size(M, n, ent_ops) + 256, dtype=torch.uint8, device=dev)
+    ws_e = ws_e[(-ws_e.data_ptr()) % 256:]
+    ws_p = torch.empty(ne.chain_workspace_size(M, n, plain_ops[1:]) + 256, dtype=torch.uint8,
+                       device=dev)
+    ws_p = ws_p[(-ws_p.data_ptr()) % 256:]
+    full = (1 << M) - 1
+
+    def entangled_step(lost=-1):
+        mask = full & ~(1 << lost) if lost >= 0 else full
+        ne.entangle(cd, eps, l, stream=stream)
+        ne.chain_apply(eps, ent_ops, delta, mask=mask, workspace=ws_e, stream=stream)
+        ne.extract_recover([None if m == lost else delta[m] for m in range(M)], lost, dhat, l,
+                           stream=stream)
+
+    def plain_step():
+        o0 = plain_ops[0]
+        ne.plain_apply(o0.op, cd, o0.operand, first, o0.scalar, stream=stream)
+        ne.chain_apply(first, plain_ops[1:], dhat, workspace=ws_p, stream=stream)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    t_plain = timed(plain_step)
+    ref = torch.stack([t[::4099] for t in dhat]).cpu()
+    t_ent = timed(entangled_step)
+    same = torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref)
+    t_lost = timed(lambda: entangled_step(1))
+    same = same and torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref)
+    if not same:
+        raise SystemExit("chain: entangled and plain results differ")
+    samples = M * n_out
+    # algorithmic HBM bytes of one entangled step: every launch reads its
+    # inputs and operand once and writes its outputs once
+    nb = M * n * (4 + 8)                      # entangle
+    cur = n
+    for op, g, sc in ops:
+        nxt = cur + g.size - 1 if op == "conv" else cur
+        nb += M * (cur + nxt) * 8 + (0 if g is None else g.size * (8 if op == "add" else 4))
+        cur = nxt
+    nb += (M - 1) * n_out * 8 + M * n_out * 8   # extract
+    hbm = nb / (t_ent * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(samples / (t_ent * 1e-3) / 1e9, 3),
+        "unit": "Gout-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_ent, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "series: 3 streams x 2^22 int32 samples in [-2^9,2^9), add -> "
+                               "scale -> conv (64 taps) -> perm -> add, operands in the same range; "
+                               "entangle once, extract once; per-step kernels",
+                   "w": 64, "l": l, "worst_case_bound": bound},
+        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "all launches of the step (entangle, the series, extract)",
+                     "alg_bytes_per_step": nb},
+        "baselines": {"ms_per_step": {"entangled": round(t_ent, 4), "plain": round(t_plain, 4),
+                                      "entangled_one_lost": round(t_lost, 4)},
+                      "overhead_pct_vs_plain": round(100 * (t_ent / t_plain - 1), 2)},
     }
     print(json.dumps(line), flush=True)
 

@@ -38,7 +38,8 @@
  *    every entangled output fits in 64 bits, and wrap-around arithmetic is a
  *    ring homomorphism, so intermediate wrap-around cancels.
  *  - Lengths are element counts (int64). A length of 0 is valid and
- *    enqueues nothing.
+ *    enqueues nothing; a device pointer whose buffer has length 0 is never
+ *    dereferenced and may be NULL (host pointer arrays may not).
  */
 #ifndef NE_H
 #define NE_H
@@ -192,6 +193,74 @@ ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rs
  */
 ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
                               const int64_t *e, int32_t r, int64_t *d_r, ne_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Series of LSB operations (Sec. II: operators applied one after another,
+ * e.g. additions and scalings with fixed operands, then convolutions and
+ * permutations) on the entangled streams, with one extraction at the end.
+ * Every operation is linear, so after each one stream m still holds
+ * d_m + 2^l d_{m-1} of the partial results; recovery needs only the last
+ * stage's outputs, as for a single operation.
+ */
+typedef struct ne_chain_op {
+    int32_t op;           /* ne_op */
+    int32_t operand_bits; /* NE_OP_CONV, NE_OP_ADD, NE_OP_INNER: every value g
+                             of the plain operand satisfies
+                             -2^(b-1) <= g < 2^(b-1), b in [1, 32] (the
+                             range check's promise; not verified on the
+                             device); ignored for NE_OP_SCALE and NE_OP_PERM */
+    const void *operand;  /* device operand, typed as for ne_lsb_apply (for
+                             NE_OP_ADD on entangled streams: the entangled
+                             int64 vector, ne_entangle_operand); may be NULL
+                             for ne_chain_check, which reads no operand */
+    int64_t n_operand;    /* taps (conv); the current length (add, inner,
+                             perm); ignored for scale */
+    int64_t scalar;       /* NE_OP_SCALE: the factor */
+} ne_chain_op;
+
+/*
+ * Shapes and worst-case range of a series on M streams of n_in samples
+ * whose values lie in [-2^(in_bits-1), 2^(in_bits-1)). Stage by stage, the
+ * bound B on |d| becomes K 2^(b-1) B (conv), |s| B (scale), B + 2^(b-1)
+ * (add), n 2^(b-1) B (inner) or B (perm); every stage must satisfy
+ * B <= D of ne_params(M, 64), so that no entangled intermediate leaves the
+ * 64-bit range (wrapping would be harmless for these linear operations,
+ * but the check keeps every intermediate an exact integer). Host-only.
+ * Outputs (either may be NULL): n_out, the last stage's length; bound, the
+ * last stage's B.
+ * Errors: NE_EINVAL (M outside [3, NE_MAX_M], in_bits outside [1, 32],
+ * n_ops outside [1, 64], n_in < 0, NULL ops, operand_bits outside [1, 32]
+ * where used, an operand length that does not match), NE_EUNSUP (unknown
+ * op), NE_ERANGE (a stage's bound above D).
+ */
+ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
+                         int32_t n_ops, int64_t *n_out, int64_t *bound);
+
+/*
+ * Bytes of device workspace ne_chain_apply needs for a series: two buffers
+ * of M int64 streams of the longest intermediate length (0 for one
+ * operation). Host-only; errors as ne_chain_check, without the range.
+ */
+ne_status ne_chain_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                  int32_t n_ops, size_t *bytes);
+
+/*
+ * Run the series on each of M int64 streams independently:
+ *     delta[m] = (...((eps[m] op_0 g_0) op_1 g_1) ...) op_{n_ops-1} g_{n_ops-1}
+ * for every m with bit m of stream_mask set (a cleared bit: a fail-stop
+ * loss of that stream's core for the whole series; delta[m] is neither
+ * read nor written and may be NULL). Intermediates go to the caller's
+ * workspace (ne_chain_workspace_size bytes, 256-byte aligned, device
+ * memory; may be NULL when that size is 0); results wrap modulo 2^64.
+ * n_out must be the series' output length. Launches on `stream` only, no
+ * allocation. delta must not overlap eps, the operands or the workspace.
+ * Errors: as ne_chain_workspace_size, and NE_EINVAL for a missing or small
+ * workspace, a wrong n_out or NULL pointers of computed streams.
+ */
+ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
+                         const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
+                         int64_t n_out, uint32_t stream_mask, void *workspace,
+                         size_t workspace_bytes, ne_stream stream);
 
 /* ------------------------------------------------------------------------
  * Batched executor: many groups (uneven M, length, operation and operand

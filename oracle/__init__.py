@@ -186,3 +186,28 @@ def pipeline(c, op: str, operand=None, scalar: int = 0, r: int = 0, w: int = 64)
         g = entangle_operand(operand, l, w)
     delta = apply(op, eps, g, scalar, w)
     return extract(delta, r, l, w), eps, delta
+
+
+def chain(c, ops, w: int = 64) -> np.ndarray:
+    """A series of LSB operations applied one after another to every stream
+    (Sec. II: operators in series before any extraction), exact. ops: a list
+    of (op, operand, scalar)."""
+    x = _i64(c)
+    for op, operand, scalar in ops:
+        x = apply(op, x, operand, scalar, w)
+    return x
+
+
+def chain_pipeline(c, ops, r: int = 0, w: int = 64):
+    """The method with a series: entangle once (eq. (14)-(15)), run every
+    operation on every entangled stream (an added vector entangled with
+    itself, footnote 3), drop stream r, extract once (eq. (16)-(19)).
+    Returns (d_hat, the last stage's entangled outputs)."""
+    c = _i64(c)
+    M = c.shape[0]
+    l, _, _ = params(M, w)
+    x = entangle(c, l, w)
+    for op, operand, scalar in ops:
+        g = entangle_operand(operand, l, w) if op == "add" else operand
+        x = apply(op, x, g, scalar, w)
+    return extract(x, r, l, w), x

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libne.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "fused.hip", "plan.hip"]
+SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "chain.hip", "fused.hip", "plan.hip"]
 
 # fused_conv.hip is compiled once per (kernel class, slot count), and
 # fused_stream.hip once per kernel class: entangled

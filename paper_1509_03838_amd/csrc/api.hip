@@ -126,6 +126,7 @@ ne_status ne_entangle(int32_t M, int32_t l, int64_t n, const int32_t *const *c,
                       int64_t *const *eps, ne_stream stream)
 {
     if (bad_m(M, 3) || l < 1 || l > 63 || n < 0 || !c || !eps) return NE_EINVAL;
+    if (n == 0) return NE_OK;
     PtrsI32 pc{};
     PtrsI64 pe{};
     for (int m = 0; m < M; ++m) {
@@ -133,7 +134,6 @@ ne_status ne_entangle(int32_t M, int32_t l, int64_t n, const int32_t *const *c,
         pc.p[m] = c[m];
         pe.p[m] = eps[m];
     }
-    if (n == 0) return NE_OK;
     launch_entangle(M, l, n, pc, pe, (hipStream_t)stream);
     return launch_status();
 }
@@ -142,12 +142,12 @@ ne_status ne_entangle_inplace(int32_t M, int32_t l, int64_t n, int64_t *const *x
                               ne_stream stream)
 {
     if (bad_m(M, 3) || l < 1 || l > 63 || n < 0 || !x) return NE_EINVAL;
+    if (n == 0) return NE_OK;
     PtrsI64 px{};
     for (int m = 0; m < M; ++m) {
         if (!x[m]) return NE_EINVAL;
         px.p[m] = x[m];
     }
-    if (n == 0) return NE_OK;
     launch_entangle_inplace(M, l, n, px, (hipStream_t)stream);
     return launch_status();
 }
@@ -176,7 +176,7 @@ ne_status ne_lsb_apply(int32_t op, int32_t M, int64_t n_in, const int64_t *const
     bool nx = false, ny = false;
     const int count = compact(M, eps, stream_mask, px, nx);
     compact(M, delta, stream_mask, py, ny);
-    if (nx || ny) return NE_EINVAL;
+    if ((nx && n_in > 0) || (ny && n_out > 0)) return NE_EINVAL;
     if (count == 0 || n_out == 0) return NE_OK;
     hipStream_t s = (hipStream_t)stream;
     switch (op) {
@@ -197,6 +197,7 @@ ne_status ne_extract_recover(int32_t M, int32_t l, int64_t n_out, const int64_t 
     if (bad_m(M, 3) || l < 1 || l > 63 || (M - 1) * l > 64 || n_out < 0 || !delta || !dhat)
         return NE_EINVAL;
     if (r < -1 || r >= M) return NE_EFAILIDX;
+    if (n_out == 0) return NE_OK;
     if (r < 0) r = 0;
     // Rotate so that the kernel sees delta_{r+1}, ..., delta_{r+M-1} and
     // writes d_{r+1}, ..., d_{r+M-1}, d_r with compile-time indices.
@@ -212,7 +213,6 @@ ne_status ne_extract_recover(int32_t M, int32_t l, int64_t n_out, const int64_t 
         if (!dhat[j]) return NE_EINVAL;
         out.p[t] = dhat[j];
     }
-    if (n_out == 0) return NE_OK;
     launch_extract(M, l, n_out, in, out, (hipStream_t)stream);
     return launch_status();
 }
@@ -230,7 +230,7 @@ ne_status ne_plain_apply(int32_t op, int32_t n_streams, int64_t n_in, const int3
     bool nx = false, ny = false;
     const int count = compact(n_streams, c, all, px, nx);
     compact(n_streams, d, all, py, ny);
-    if (nx || ny) return NE_EINVAL;
+    if ((nx && n_in > 0) || (ny && n_out > 0)) return NE_EINVAL;
     if (n_out == 0) return NE_OK;
     hipStream_t s = (hipStream_t)stream;
     switch (op) {
@@ -248,13 +248,14 @@ ne_status ne_plain_apply(int32_t op, int32_t n_streams, int64_t n_in, const int3
 ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rsum,
                       ne_stream stream)
 {
-    if (bad_m(M, 1) || n < 0 || !c || !rsum) return NE_EINVAL;
+    if (bad_m(M, 1) || n < 0 || !c) return NE_EINVAL;
+    if (n == 0) return NE_OK;
+    if (!rsum) return NE_EINVAL;
     PtrsI32 pc{};
     for (int m = 0; m < M; ++m) {
         if (!c[m]) return NE_EINVAL;
         pc.p[m] = c[m];
     }
-    if (n == 0) return NE_OK;
     launch_checksum(M, n, pc, rsum, (hipStream_t)stream);
     return launch_status();
 }
@@ -262,8 +263,10 @@ ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rs
 ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
                               const int64_t *e, int32_t r, int64_t *d_r, ne_stream stream)
 {
-    if (bad_m(M, 1) || n_out < 0 || !d || !e || !d_r) return NE_EINVAL;
+    if (bad_m(M, 1) || n_out < 0 || !d) return NE_EINVAL;
     if (r < 0 || r >= M) return NE_EFAILIDX;
+    if (n_out == 0) return NE_OK;
+    if (!e || !d_r) return NE_EINVAL;
     PtrsCI64 pd{};
     int count = 0;
     for (int m = 0; m < M; ++m) {
@@ -271,7 +274,6 @@ ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
         if (!d[m]) return NE_EINVAL;
         pd.p[count++] = d[m];
     }
-    if (n_out == 0) return NE_OK;
     launch_checksum_recover(count, n_out, pd, e, d_r, (hipStream_t)stream);
     return launch_status();
 }

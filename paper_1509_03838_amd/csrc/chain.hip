@@ -1,0 +1,184 @@
+// Series of LSB operations on entangled streams (ne_chain_*): the shape and
+// range bookkeeping of the series (host) and its execution as one launch
+// per operation over ping-pong buffers in the caller's workspace. The
+// operations are the per-step kernels of ne_lsb_apply.
+#include <algorithm>
+
+#include "ne_internal.h"
+
+using namespace ne;
+
+namespace {
+
+constexpr int32_t kMaxChainOps = 64;
+constexpr size_t kWsAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kWsAlign - 1) & ~(kWsAlign - 1); }
+
+// Output length of one operation on n_in samples, or -1 for a shape error
+// (-2: unknown operation).
+int64_t stage_out(const ne_chain_op &o, int64_t n_in)
+{
+    switch (o.op) {
+    case NE_OP_CONV:
+        if (o.n_operand < 1) return -1;
+        return n_in == 0 ? 0 : n_in + o.n_operand - 1;
+    case NE_OP_SCALE: return n_in;
+    case NE_OP_ADD:
+    case NE_OP_PERM:
+        if (o.n_operand != n_in) return -1;
+        if (o.op == NE_OP_PERM && n_in > INT32_MAX) return -1;
+        return n_in;
+    case NE_OP_INNER:
+        if (o.n_operand != n_in) return -1;
+        return 1;
+    default: return -2;
+    }
+}
+
+bool uses_operand_bits(int32_t op) { return op == NE_OP_CONV || op == NE_OP_ADD || op == NE_OP_INNER; }
+
+// Walks the series: the output length of every stage, and the longest
+// intermediate (every stage but the last).
+ne_status walk(int64_t n_in, const ne_chain_op *ops, int32_t n_ops, int64_t *n_out,
+               int64_t *longest)
+{
+    if (n_in < 0 || !ops || n_ops < 1 || n_ops > kMaxChainOps) return NE_EINVAL;
+    int64_t n = n_in, lg = 0;
+    for (int32_t i = 0; i < n_ops; ++i) {
+        const ne_chain_op &o = ops[i];
+        if (uses_operand_bits(o.op) && (o.operand_bits < 1 || o.operand_bits > 32))
+            return NE_EINVAL;
+        const int64_t m = stage_out(o, n);
+        if (m == -2) return NE_EUNSUP;
+        if (m < 0) return NE_EINVAL;
+        if (i + 1 < n_ops) lg = std::max(lg, m);
+        n = m;
+    }
+    if (n_out) *n_out = n;
+    if (longest) *longest = lg;
+    return NE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
+                         int32_t n_ops, int64_t *n_out, int64_t *bound)
+{
+    if (M < 3 || M > kMaxM || in_bits < 1 || in_bits > 32) return NE_EINVAL;
+    const ne_status st = walk(n_in, ops, n_ops, n_out, nullptr);
+    if (st != NE_OK) return st;
+    int64_t D = 0;
+    if (ne_params(M, 64, nullptr, nullptr, &D) != NE_OK) return NE_ERANGE;
+    // Worst-case |d| after each stage, in 128 bits; every stage stays <= D
+    // (< 2^62), so no product below can overflow before the comparison.
+    using u128 = unsigned __int128;
+    u128 B = (u128)1 << (in_bits - 1);
+    if (B > (u128)D) return NE_ERANGE;
+    int64_t n = n_in;
+    for (int32_t i = 0; i < n_ops; ++i) {
+        const ne_chain_op &o = ops[i];
+        const u128 G = uses_operand_bits(o.op) ? (u128)1 << (o.operand_bits - 1) : 0;
+        switch (o.op) {
+        case NE_OP_CONV: B = B * G * (u128)o.n_operand; break;
+        case NE_OP_SCALE: {
+            const u128 s = o.scalar < 0 ? (u128)0 - (u128)(__int128)o.scalar : (u128)o.scalar;
+            if (s > ((u128)1 << 62)) return NE_ERANGE;
+            B = B * s;
+            break;
+        }
+        case NE_OP_ADD: B = B + G; break;
+        case NE_OP_INNER: B = B * G * (u128)std::max<int64_t>(n, 1); break;
+        case NE_OP_PERM: break;
+        }
+        if (B > (u128)D) return NE_ERANGE;
+        n = stage_out(o, n);
+    }
+    if (bound) *bound = (int64_t)B;
+    return NE_OK;
+}
+
+ne_status ne_chain_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
+                                  size_t *bytes)
+{
+    if (M < 1 || M > kMaxM || !bytes) return NE_EINVAL;
+    int64_t longest = 0;
+    const ne_status st = walk(n_in, ops, n_ops, nullptr, &longest);
+    if (st != NE_OK) return st;
+    *bytes = n_ops > 1 ? 2 * (size_t)M * align_up((size_t)longest * 8) : 0;
+    return NE_OK;
+}
+
+ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
+                         const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
+                         int64_t n_out, uint32_t stream_mask, void *workspace,
+                         size_t workspace_bytes, ne_stream stream)
+{
+    if (M < 1 || M > kMaxM || !eps || !delta) return NE_EINVAL;
+    int64_t want = 0, longest = 0;
+    ne_status st = walk(n_in, ops, n_ops, &want, &longest);
+    if (st != NE_OK) return st;
+    if (n_out != want) return NE_EINVAL;
+    const size_t plane = align_up((size_t)longest * 8);
+    if (n_ops > 1 && plane > 0) {
+        if (!workspace || workspace_bytes < 2 * (size_t)M * plane) return NE_EINVAL;
+        if ((uintptr_t)workspace % kWsAlign) return NE_EINVAL;
+    }
+    for (int32_t i = 0; i < n_ops; ++i) {
+        const ne_chain_op &o = ops[i];
+        const bool needs = o.op == NE_OP_CONV || (o.op != NE_OP_SCALE && o.n_operand > 0);
+        if (needs && !o.operand) return NE_EINVAL;
+    }
+    if (M < 32) stream_mask &= (1u << M) - 1u;
+    // The computed streams, compacted; stage i reads `cur` and writes the
+    // workspace buffer (i & 1), or delta for the last stage.
+    PtrsCI64 cur{};
+    PtrsI64 fin{};
+    int count = 0;
+    for (int m = 0; m < M; ++m) {
+        if (!((stream_mask >> m) & 1u)) continue;
+        if ((!eps[m] && n_in > 0) || (!delta[m] && n_out > 0)) return NE_EINVAL;
+        cur.p[count] = eps[m];
+        fin.p[count] = delta[m];
+        ++count;
+    }
+    if (count == 0) return NE_OK;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *ws = (unsigned char *)workspace;
+    int64_t n = n_in;
+    for (int32_t i = 0; i < n_ops; ++i) {
+        const ne_chain_op &o = ops[i];
+        const int64_t m = stage_out(o, n);
+        PtrsI64 dst{};
+        if (i + 1 == n_ops) {
+            dst = fin;
+        } else {
+            for (int t = 0; t < count; ++t)
+                dst.p[t] = (int64_t *)(ws + ((size_t)(i & 1) * M + t) * plane);
+        }
+        if (m > 0) {
+            switch (o.op) {
+            case NE_OP_CONV:
+                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
+                break;
+            case NE_OP_SCALE: launch_scale_i64(count, n, cur, o.scalar, dst, s); break;
+            case NE_OP_ADD: launch_add_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
+            case NE_OP_INNER:
+                launch_inner_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
+                break;
+            case NE_OP_PERM:
+                launch_perm_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
+                break;
+            }
+            st = launch_status();
+            if (st != NE_OK) return st;
+        }
+        for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
+        n = m;
+    }
+    return NE_OK;
+}
+
+}  // extern "C"

@@ -24,7 +24,8 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
            "ne_plain_apply", "ne_checksum", "ne_checksum_recover", "ne_plan_create",
            "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
-           "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in")
+           "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in",
+           "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -40,6 +41,13 @@ class GroupC(ctypes.Structure):
                 ("tap_copies", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("c", ctypes.c_void_p * FUSED_MAX_M), ("operand", ctypes.c_void_p),
                 ("out", ctypes.c_void_p * FUSED_MAX_M)]
+
+
+class ChainOpC(ctypes.Structure):
+    """struct ne_chain_op"""
+    _fields_ = [("op", ctypes.c_int32), ("operand_bits", ctypes.c_int32),
+                ("operand", ctypes.c_void_p), ("n_operand", ctypes.c_int64),
+                ("scalar", ctypes.c_int64)]
 
 
 class TuningC(ctypes.Structure):
@@ -96,6 +104,12 @@ def load() -> ctypes.CDLL:
                                           ctypes.POINTER(TuningC), ctypes.POINTER(ctypes.c_size_t)]),
         "ne_plan_create_in": (_i32, [ctypes.POINTER(GroupC), _i32, _i32, ctypes.POINTER(TuningC),
                                      _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_void_p)]),
+        "ne_chain_check": (_i32, [_i32, _i32, _i64, ctypes.POINTER(ChainOpC), _i32,
+                                  ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "ne_chain_workspace_size": (_i32, [_i32, _i64, ctypes.POINTER(ChainOpC), _i32,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
+                                  _P, ctypes.c_size_t, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -346,3 +360,71 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class ChainOp:
+    """One operation of a series: op, its device operand (None for scale;
+    for add on entangled streams the entangled int64 vector), the scale
+    factor, and the bits of the plain operand's values (conv, add, inner)."""
+
+    def __init__(self, op: str, operand=None, scalar: int = 0, operand_bits: int = 32,
+                 n_operand: int | None = None):
+        self.op, self.operand, self.scalar, self.operand_bits = op, operand, int(scalar), operand_bits
+        if n_operand is None:
+            n_operand = 0 if operand is None or isinstance(operand, int) else operand.numel()
+        self.n_operand = int(n_operand)
+
+    def to_c(self) -> ChainOpC:
+        o = ChainOpC()
+        o.op, o.operand_bits = OPS[self.op], int(self.operand_bits)
+        o.operand = _ptr(self.operand) if self.operand is not None else None
+        o.n_operand, o.scalar = self.n_operand, self.scalar
+        return o
+
+
+def _chain_c(ops: Sequence[ChainOp]):
+    return (ChainOpC * max(1, len(ops)))(*[o.to_c() for o in ops])
+
+
+def chain_check(M: int, in_bits: int, n_in: int, ops: Sequence[ChainOp]) -> tuple[int, int]:
+    """(output length, worst-case |d| of the last stage) of a series; raises
+    NeError (status -2) if some stage's bound exceeds D."""
+    no, b = _i64(), _i64()
+    _check("ne_chain_check", load().ne_chain_check(M, in_bits, n_in, _chain_c(ops), len(ops),
+                                                   ctypes.byref(no), ctypes.byref(b)))
+    return no.value, b.value
+
+
+def chain_workspace_size(M: int, n_in: int, ops: Sequence[ChainOp]) -> int:
+    sz = ctypes.c_size_t()
+    _check("ne_chain_workspace_size", load().ne_chain_workspace_size(M, n_in, _chain_c(ops), len(ops),
+                                                                     ctypes.byref(sz)))
+    return sz.value
+
+
+def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: int | None = None,
+                workspace=None, n_in: int | None = None, stream=None):
+    """delta[m] = the series applied to eps[m], for every stream whose mask
+    bit is set. workspace: a uint8 device tensor of chain_workspace_size
+    bytes (allocated here if None)."""
+    import torch
+    _dtype(eps, torch.int64, "eps")
+    _dtype(delta, torch.int64, "delta")
+    M = len(eps)
+    if mask is None:
+        mask = (1 << M) - 1
+    if n_in is None:
+        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    n = n_in
+    for o in ops:
+        n = n_out(o.op, n, o.n_operand)
+    ws_bytes = chain_workspace_size(M, n_in, ops)
+    if workspace is not None and not isinstance(workspace, int) and workspace.numel() < ws_bytes:
+        raise ValueError(f"workspace holds {workspace.numel()} bytes, the series needs {ws_bytes}")
+    if workspace is None and ws_bytes:
+        dev = next(t.device for t in eps if t is not None and not isinstance(t, int))
+        workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+        workspace = workspace[(-workspace.data_ptr()) % 256:]
+    _check("ne_chain_apply", load().ne_chain_apply(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
+                                                   _ptr_array(delta), n, mask & 0xFFFFFFFF,
+                                                   _ptr(workspace), ws_bytes, _stream(stream)))

@@ -147,6 +147,34 @@ def config_fig2(M: int, K: int, seed: int = SEED_BASE + 5, n: int = FIG2_N) -> G
     return Group("conv", c, k, 0, -1)
 
 
+CHAIN_RECIPE = ("add", "scale", "conv", "perm", "add")
+
+
+def chain_series(g: np.random.Generator, n: int, recipe=CHAIN_RECIPE, bits: int = 10,
+                 K: int = 64) -> list[tuple[str, np.ndarray | None, int]]:
+    """Operands of a series of operations on streams of n samples: for each
+    op of the recipe, (op, operand, scalar) with the operand drawn uniform
+    in [-2^(bits-1), 2^(bits-1)) (conv: K taps; add, inner: a vector of the
+    current length), a seeded permutation of the current length, or a scale
+    factor in the same range (nonzero). An inner product makes the length 1
+    for the ops after it."""
+    lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+    out = []
+    for op in recipe:
+        if op == "conv":
+            out.append((op, uniform_i32(g, lo, hi, K), 0))
+            n = n + K - 1 if n else 0
+        elif op in ("add", "inner"):
+            out.append((op, uniform_i32(g, lo, hi, n), 0))
+            n = 1 if op == "inner" else n
+        elif op == "perm":
+            out.append((op, permutation(g, n), 0))
+        else:
+            s = int(g.integers(lo, hi))
+            out.append((op, None, s if s else 1))
+    return out
+
+
 @dataclass
 class Job:
     arrival_s: float

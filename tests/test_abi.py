@@ -224,3 +224,103 @@ def test_paper_experiment_shapes_plan(lib, mode, M):
     for K in (100, 1000, 4500):
         assert _ws(lib, [grp(K)], mode)[0] == 0, K
     assert _ws(lib, [grp(16000)], mode)[0] in (-2, -4)
+
+
+# ------------------------------------------------ series of operations (host)
+
+def _series(*ops):
+    """ChainOp list from (op, n_operand, scalar, operand_bits) tuples, with
+    fake operand addresses (sizing and range checks read no operand)."""
+    return [ne.ChainOp(op, FAKE + 4096 * i, scalar, bits, n_operand=nop)
+            for i, (op, nop, scalar, bits) in enumerate(ops)]
+
+
+def test_series_lengths_and_bound():
+    """Lengths follow each operation (conv grows by K - 1, inner makes 1);
+    the bound composes stage by stage: 2^9 inputs, + 2^9 (add), x 37
+    (scale), x 64 taps x 2^9 (conv), unchanged (perm), then x n x 2^3 for
+    an inner product with 4-bit values."""
+    n = 100
+    ops = _series(("add", n, 0, 10), ("scale", 0, -37, 0), ("conv", 64, 0, 10),
+                  ("perm", n + 63, 0, 0))
+    no, b = ne.chain_check(3, 10, n, ops)
+    assert no == n + 63
+    assert b == (2**9 + 2**9) * 37 * 64 * 2**9
+    ops2 = ops + _series(("inner", n + 63, 0, 4))
+    no2, b2 = ne.chain_check(3, 10, n, ops2)
+    assert no2 == 1 and b2 == b * (n + 63) * 2**3
+
+
+def test_series_bound_against_d():
+    """Every stage must stay within D(M): M = 3 (D = 2^41 - 2^22) accepts a
+    bound of 2^40 and refuses 2^42, even when a later scale by 1 would not
+    change it; M = 8 (D above 2^55) accepts the latter."""
+    ok = _series(("conv", 4, 0, 16), ("scale", 0, 1 << 8, 0))     # 2^15 * 2^15 * 4 * 2^8
+    bad = _series(("conv", 16, 0, 16), ("scale", 0, 1 << 8, 0))   # 2^15 * 2^15 * 16 * 2^8
+    assert ne.chain_check(3, 16, 100, ok)[1] == 1 << 40
+    with pytest.raises(ne.NeError) as e:
+        ne.chain_check(3, 16, 100, bad)
+    assert e.value.status == -2
+    assert ne.chain_check(8, 16, 100, bad)[1] == 1 << 42
+
+
+@pytest.mark.parametrize("ops,status", [
+    ([("add", 99, 0, 10)], -1),                  # operand length differs
+    ([("conv", 0, 0, 10)], -1),                  # no taps
+    ([("conv", 5, 0, 0)], -1),                   # operand bits missing
+    ([("conv", 5, 0, 33)], -1),                  # operand bits above 32
+    ([("perm", 100, 0, 0), ("inner", 100, 0, 8), ("add", 100, 0, 8)], -1),  # length 1 after inner
+    ([(9, 0, 0, 0)], -4),                        # unknown operation
+])
+def test_series_validation(ops, status):
+    L = ne.load()
+    arr = (ne.ChainOpC * len(ops))()
+    for i, (op, nop, sc, bits) in enumerate(ops):
+        arr[i].op = ne.OPS[op] if isinstance(op, str) else op
+        arr[i].n_operand, arr[i].scalar, arr[i].operand_bits = nop, sc, bits
+        arr[i].operand = FAKE
+    no, b = ctypes.c_int64(), ctypes.c_int64()
+    assert L.ne_chain_check(3, 10, 100, arr, len(ops), ctypes.byref(no), ctypes.byref(b)) == status
+
+
+def test_series_argument_checks():
+    L = ne.load()
+    ops = ne._chain_c(_series(("scale", 0, 3, 0)))
+    no = ctypes.c_int64()
+    assert L.ne_chain_check(2, 10, 100, ops, 1, ctypes.byref(no), None) == -1   # M < 3
+    assert L.ne_chain_check(3, 0, 100, ops, 1, ctypes.byref(no), None) == -1   # in_bits
+    assert L.ne_chain_check(3, 10, -1, ops, 1, ctypes.byref(no), None) == -1   # n_in
+    assert L.ne_chain_check(3, 10, 100, ops, 0, ctypes.byref(no), None) == -1  # no ops
+    assert L.ne_chain_check(3, 10, 100, ops, 65, ctypes.byref(no), None) == -1  # too many
+    assert L.ne_chain_check(3, 10, 100, None, 1, ctypes.byref(no), None) == -1
+
+
+def test_series_workspace_size():
+    """Two buffers of M streams of the longest intermediate (256-byte
+    rounded); nothing for a single operation. ne_chain_apply refuses a
+    missing or short workspace before touching the device."""
+    n = 1000
+    one = _series(("conv", 64, 0, 10))
+    assert ne.chain_workspace_size(3, n, one) == 0
+    ops = _series(("conv", 64, 0, 10), ("scale", 0, 3, 0), ("inner", n + 63, 0, 8))
+    up = lambda x: (x + 255) // 256 * 256
+    assert ne.chain_workspace_size(5, n, ops) == 2 * 5 * up(8 * (n + 63))
+    L = ne.load()
+    eps = ne._ptr_array([FAKE + 64 * m for m in range(3)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 64 * m for m in range(3)])
+    arr = ne._chain_c(ops)
+    assert L.ne_chain_apply(3, n, eps, arr, 3, out, 1, 7, None, 0, None) == -1
+    ws = ne.chain_workspace_size(3, n, ops)
+    assert L.ne_chain_apply(3, n, eps, arr, 3, out, 1, 7, FAKE, ws - 1, None) == -1
+    assert L.ne_chain_apply(3, n, eps, arr, 3, out, 2, 7, FAKE, ws, None) == -1   # wrong n_out
+    assert L.ne_chain_apply(3, n, eps, arr, 3, out, 1, 7, FAKE + 8, ws, None) == -1  # misaligned
+
+
+def test_series_of_empty_streams_needs_no_workspace(lib):
+    """Streams of length 0: every stage is empty, the workspace size is 0,
+    NULL stream and workspace pointers are accepted and nothing is
+    launched."""
+    ops = _series(("conv", 5, 0, 8), ("scale", 0, 3, 0))
+    assert ne.chain_workspace_size(3, 0, ops) == 0
+    nulls = ne._ptr_array([None, None, None])
+    assert lib.ne_chain_apply(3, 0, nulls, ne._chain_c(ops), 2, nulls, 0, 7, None, 0, None) == 0

@@ -1,0 +1,122 @@
+"""Series of LSB operations on entangled streams (ne_chain_*): one
+entanglement, the whole series on every stream, one extraction; bit-exact
+against the CPU oracle, with and without a lost stream."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_03838_amd import ne
+from paper_1509_03838_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+POISON = -0x5A5A5A5A5A5A5A5A
+
+SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
+          ("perm", "add", "conv", "inner"), ("add",), ("inner", "conv", "add")]
+
+
+def dev32(a):
+    """An int32 device copy; empty arrays get a zero-length view of a
+    one-element buffer (a device address the library accepts)."""
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    if a.size == 0:
+        return torch.zeros(1, dtype=torch.int32, device=DEV)[:0]
+    return torch.from_numpy(a).to(DEV)
+
+
+def device_ops(ops, l, bits, entangled=True):
+    """ChainOps with device operands; an added vector is entangled with
+    itself for entangled streams (footnote 3), widened to int64 otherwise."""
+    out = []
+    for op, g, s in ops:
+        if op == "scale":
+            out.append(ne.ChainOp(op, None, s))
+            continue
+        dg = dev32(g)
+        if op == "add":
+            if entangled:
+                ge = torch.empty(max(g.size, 1), dtype=torch.int64, device=DEV)[:g.size]
+                ne.entangle_operand(dg, ge, l)
+                dg = ge
+            else:
+                dg = dg.to(torch.int64)
+        out.append(ne.ChainOp(op, dg, s, operand_bits=bits))
+    return out
+
+
+def run_series(c, ops, lost, in_bits, bits):
+    """Entangle, the series on the streams other than `lost`, extract.
+    Returns (recovered outputs, last-stage entangled outputs) on the host."""
+    M, n = c.shape
+    l = ne.params(M)[0]
+    dops = device_ops(ops, l, bits)
+    no, _ = ne.chain_check(M, in_bits, n, dops)
+    cd = [dev32(r) for r in c]
+    eps = [torch.empty(max(n, 1), dtype=torch.int64, device=DEV)[:n] for _ in range(M)]
+    ne.entangle(cd, eps, l)
+    delta = [torch.full((max(no, 1),), POISON, dtype=torch.int64, device=DEV)[:no]
+             for _ in range(M)]
+    mask = ((1 << M) - 1) & ~(1 << lost if lost >= 0 else 0)
+    ne.chain_apply(eps, dops, delta, mask=mask)
+    dhat = [torch.full((max(no, 1),), POISON, dtype=torch.int64, device=DEV)[:no]
+            for _ in range(M)]
+    ne.extract_recover([None if m == lost else delta[m] for m in range(M)], lost, dhat, l, n=no)
+    torch.cuda.synchronize()
+    return (np.stack([t.cpu().numpy() for t in dhat]),
+            np.stack([t.cpu().numpy() for t in delta]))
+
+
+@pytest.mark.parametrize("recipe", SERIES)
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_series_recovers_plain_result(recipe, M):
+    """Every recipe within D(M = 3): 6-bit samples and operands."""
+    n = 3001
+    c = wl.uniform_i32(wl.rng(300 + M), -32, 32, (M, n))
+    ops = wl.chain_series(wl.rng(400 + M), n, recipe, bits=6, K=37)
+    want = oracle.chain(c, ops)
+    _, last = oracle.chain_pipeline(c, ops, r=0)
+    for lost in (-1, 0, M - 1):
+        dhat, delta = run_series(c, ops, lost, 6, 6)
+        assert np.array_equal(dhat, want), (recipe, M, lost)
+        live = [m for m in range(M) if m != lost]
+        assert np.array_equal(delta[live], last[live]), (recipe, M, lost)
+
+
+@pytest.mark.parametrize("recipe,n", [(("conv", "scale"), 0), (("inner", "conv"), 0),
+                                      (("scale",), 1), (("perm", "inner"), 1), (("conv",), 5)])
+def test_series_edge_cases(recipe, n):
+    """Empty and one-sample streams, a single operation (no workspace)."""
+    M = 4
+    c = wl.uniform_i32(wl.rng(500 + n), -100, 100, (M, n))
+    ops = wl.chain_series(wl.rng(600 + n), n, recipe, bits=8, K=3)
+    want = oracle.chain(c, ops)
+    for lost in (-1, 2):
+        dhat, _ = run_series(c, ops, lost, 8, 8)
+        assert np.array_equal(dhat, want), (recipe, n, lost)
+
+
+def test_series_on_plain_streams():
+    """The failure-intolerant baseline of a series: the same launches on raw
+    (not entangled) int64 words."""
+    M, n = 3, 2000
+    c = wl.uniform_i32(wl.rng(700), -512, 512, (M, n))
+    ops = wl.chain_series(wl.rng(701), n, wl.CHAIN_RECIPE, bits=10, K=21)
+    dops = device_ops(ops, 0, 10, entangled=False)
+    x = [dev32(r).to(torch.int64) for r in c]
+    no = n + 20
+    out = [torch.empty(no, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ne.chain_apply(x, dops, out)
+    got = np.stack([t.cpu().numpy() for t in out])
+    assert np.array_equal(got, oracle.chain(c, ops))
+
+
+def test_series_benchmark_size():
+    """The series the benchmark times, at its size (3 streams of 2^22
+    samples, 64-tap convolution), one stream lost, compared in full."""
+    M, n = 3, 1 << 22
+    c = wl.uniform_i32(wl.rng(wl.SEED_BASE + 6), -512, 512, (M, n))
+    ops = wl.chain_series(wl.rng(wl.SEED_BASE + 7), n, wl.CHAIN_RECIPE, bits=10, K=64)
+    dhat, _ = run_series(c, ops, 1, 10, 10)
+    assert np.array_equal(dhat, oracle.chain(c, ops))

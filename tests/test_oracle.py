@@ -342,6 +342,70 @@ def test_add_needs_entangled_operand():
     assert not np.array_equal(bad, c + g)
 
 
+# --------------------------------------------------- series of operations
+
+def _numpy_series(c, ops):
+    """The series by numpy on Python integers (object arrays): each
+    operation restated from its definition, independently of the C oracle."""
+    x = np.array(c, dtype=object)
+    for op, g, s in ops:
+        if op == "conv":
+            x = np.array([np.convolve(row, np.array(g, dtype=object)) if row.size else row
+                          for row in x], dtype=object)
+        elif op == "scale":
+            x = x * s
+        elif op == "add":
+            x = x + np.array(g, dtype=object)
+        elif op == "inner":
+            x = np.array([[sum(int(a) * int(b) for a, b in zip(row, g))] for row in x], dtype=object)
+        else:
+            x = x[:, np.asarray(g, dtype=np.int64)]
+    return x
+
+
+SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
+          ("perm", "add", "conv", "inner"), ("add",)]
+
+
+@pytest.mark.parametrize("recipe", SERIES)
+def test_series_matches_numpy(recipe):
+    """The oracle's series equals numpy's composition of the definitions."""
+    c = _rand(5, -512, 512, (3, 120))
+    ops = wl.chain_series(wl.rng(17), 120, recipe, bits=10, K=9)
+    assert np.array_equal(oracle.chain(c, ops).astype(object), _numpy_series(c, ops))
+
+
+@pytest.mark.parametrize("recipe", SERIES)
+@pytest.mark.parametrize("M", [3, 4, 7])
+def test_series_recovers_plain_result(recipe, M):
+    """One extraction after the whole series recovers the series' plain
+    result from any M-1 streams, and the last stage still holds the
+    closed form d_m + 2^l d_(m-1) (linearity of every operation)."""
+    n = 150
+    c = _rand(M * 3 + len(recipe), -512, 512, (M, n))
+    ops = wl.chain_series(wl.rng(M + 40), n, recipe, bits=10, K=17)
+    plain = oracle.chain(c, ops)
+    l, _, _ = oracle.params(M, 64)
+    for r in range(M):
+        dhat, last = oracle.chain_pipeline(c, ops, r=r)
+        assert np.array_equal(dhat, plain), (recipe, M, r)
+    want = plain.astype(object) + (np.roll(plain.astype(object), 1, axis=0) << l)
+    assert np.array_equal(last.astype(object), want)
+
+
+def test_series_add_needs_entangled_operand():
+    """Footnote 3 holds inside a series too: a plain added vector breaks
+    recovery (planted on the CPU: the pipeline with the plain operand)."""
+    M, n = 3, 60
+    c = _rand(8, -100, 100, (M, n))
+    ops = wl.chain_series(wl.rng(9), n, ("scale", "add", "conv"), bits=8, K=5)
+    l, _, _ = oracle.params(M, 64)
+    x = oracle.entangle(c, l)
+    for op, g, s in ops:
+        x = oracle.apply(op, x, g, s)  # add without entangling its operand
+    assert not np.array_equal(oracle.extract(x, 0, l), oracle.chain(c, ops))
+
+
 @pytest.mark.parametrize("w", [32, 64])
 def test_c_oracle_matches_bigint_twin(w):
     g = np.random.default_rng(w)
