@@ -65,9 +65,11 @@ def lib() -> ctypes.CDLL:
         L.orc_extract_printed_sign.argtypes = [i32, i32, i32, i64, P, i32, P]
         L.orc_checksum.argtypes = [i32, i32, i64, P, P]
         L.orc_checksum_recover.argtypes = [i32, i32, i64, P, P, i32, P]
+        L.orc_gemm.argtypes = [i32, i64, i64, i64, P, P, P]
+        L.orc_gemm_at.argtypes = [i32, i64, i64, i64, P, P, i64, P, P, P]
         for f in ("orc_params", "orc_entangle", "orc_entangle_operand", "orc_op", "orc_conv_at",
                   "orc_extract", "orc_extract_printed_sign", "orc_checksum",
-                  "orc_checksum_recover"):
+                  "orc_checksum_recover", "orc_gemm", "orc_gemm_at"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -211,3 +213,45 @@ def chain_pipeline(c, ops, r: int = 0, w: int = 64):
         g = entangle_operand(operand, l, w) if op == "add" else operand
         x = apply(op, x, g, scalar, w)
     return extract(x, r, l, w), x
+
+
+def gemm(c, g, w: int = 64) -> np.ndarray:
+    """Integer matrix product of every block: c (M, N, P) or (N, P), g (P, Q);
+    exact (the multiplication operator of eq. (2) on matrix blocks)."""
+    c, g = _i64(c), _i64(g)
+    if c.ndim == 3:
+        return np.stack([gemm(blk, g, w) for blk in c]) if c.shape[0] else \
+            np.zeros((0, c.shape[1], g.shape[1]), np.int64)
+    N, P = c.shape
+    Q = g.shape[1]
+    if g.shape[0] != P:
+        raise ValueError("inner dimensions differ")
+    out = np.empty((N, Q), np.int64)
+    _check(lib().orc_gemm(w, N, P, Q, _p(np.ascontiguousarray(c)), _p(np.ascontiguousarray(g)),
+                          _p(out)), "gemm")
+    return out
+
+
+def gemm_at(c, g, rows, cols, w: int = 64) -> np.ndarray:
+    """Entries (rows[q], cols[q]) of c @ g for one block c (N, P)."""
+    c, g = np.ascontiguousarray(_i64(c)), np.ascontiguousarray(_i64(g))
+    rows, cols = _i64(rows), _i64(cols)
+    out = np.empty(rows.size, np.int64)
+    N, P = c.shape
+    _check(lib().orc_gemm_at(w, N, P, g.shape[1], _p(c), _p(g), rows.size, _p(rows), _p(cols),
+                             _p(out)), "gemm_at")
+    return out
+
+
+def gemm_pipeline(c, g, r: int = 0, w: int = 64):
+    """The method on M matrix blocks: entangle the blocks element by element
+    (eq. (14)-(15)), multiply every entangled block by g, drop block r,
+    extract element by element (eq. (16)-(19)). Returns (d_hat, delta)."""
+    c = _i64(c)
+    M, N, P = c.shape
+    l, _, _ = params(M, w)
+    eps = entangle(c.reshape(M, N * P), l, w).reshape(M, N, P)
+    delta = gemm(eps, g, w)
+    Q = delta.shape[2]
+    dhat = extract(delta.reshape(M, N * Q), r, l, w).reshape(M, N, Q)
+    return dhat, delta

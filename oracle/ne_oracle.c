@@ -366,3 +366,49 @@ int orc_checksum_recover(int M, int w, int64_t n, const int64_t *d, const int64_
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------ matrix product */
+
+/* One entry of the integer matrix product D = C G (C: N x P, G: P x Q,
+ * row-major): D[i][j] = sum_k C[i][k] G[k][j], exact in 128 bits. The matrix
+ * product is the multiplication operator of eq. (2) applied to blocks of a
+ * stream: each of the M streams is an N x P block and G the shared kernel
+ * matrix (Sec. IV's GEMM case). */
+static int gemm_one(const int64_t *c, const int64_t *g, int64_t P, int64_t Q, int64_t i,
+                    int64_t j, i128 *out)
+{
+    i128 acc = 0, t;
+    for (int64_t k = 0; k < P; ++k) {
+        if (!mul_ok((i128)c[i * P + k], (i128)g[k * Q + j], &t) || !add_ok(acc, t, &acc))
+            return 0;
+    }
+    *out = acc;
+    return 1;
+}
+
+int orc_gemm(int w, int64_t N, int64_t P, int64_t Q, const int64_t *c, const int64_t *g,
+             int64_t *out)
+{
+    if (w < 2 || w > 64 || N < 0 || P < 0 || Q < 0) return ORC_EINVAL;
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < Q; ++j) {
+            i128 v;
+            if (!gemm_one(c, g, P, Q, i, j, &v) || !fits(v, w)) return ORC_EOVERFLOW;
+            out[i * Q + j] = (int64_t)v;
+        }
+    return ORC_OK;
+}
+
+/* Selected entries (rows[q], cols[q]) of the same product. */
+int orc_gemm_at(int w, int64_t N, int64_t P, int64_t Q, const int64_t *c, const int64_t *g,
+                int64_t count, const int64_t *rows, const int64_t *cols, int64_t *out)
+{
+    if (w < 2 || w > 64 || N < 0 || P < 0 || Q < 0 || count < 0) return ORC_EINVAL;
+    for (int64_t q = 0; q < count; ++q) {
+        if (rows[q] < 0 || rows[q] >= N || cols[q] < 0 || cols[q] >= Q) return ORC_EINVAL;
+        i128 v;
+        if (!gemm_one(c, g, P, Q, rows[q], cols[q], &v) || !fits(v, w)) return ORC_EOVERFLOW;
+        out[q] = (int64_t)v;
+    }
+    return ORC_OK;
+}

@@ -406,6 +406,51 @@ def test_series_add_needs_entangled_operand():
     assert not np.array_equal(oracle.extract(x, 0, l), oracle.chain(c, ops))
 
 
+# ------------------------------------------------------- matrix product
+
+@pytest.mark.parametrize("N,P,Q", [(1, 1, 1), (7, 5, 4), (16, 64, 16), (33, 70, 17), (0, 3, 2),
+                                   (3, 0, 2), (2, 3, 0)])
+def test_gemm_matches_numpy(N, P, Q):
+    """Block matrix product against numpy's matmul on Python integers."""
+    c = _rand(N + 3 * P, -2048, 2048, (2, N, P))
+    g = _rand(P + 5 * Q, -2048, 2048, (P, Q))
+    want = np.stack([blk.astype(object) @ g.astype(object) for blk in c]) if N * Q else \
+        np.zeros((2, N, Q), dtype=object)
+    assert np.array_equal(oracle.gemm(c, g).astype(object), want)
+
+
+def test_gemm_at_matches_full():
+    c = _rand(3, -2048, 2048, (40, 70))
+    g = _rand(4, -2048, 2048, (70, 30))
+    rows, cols = np.array([0, 39, 17, 5]), np.array([29, 0, 13, 5])
+    assert np.array_equal(oracle.gemm_at(c, g, rows, cols), oracle.gemm(c, g)[rows, cols])
+
+
+def test_gemm_exact_beyond_int64_intermediates():
+    """Products near 2^62 that cancel: the sum is exact, and a sum that does
+    not fit 64 bits is refused."""
+    c = np.array([[1 << 40, -(1 << 40)]], np.int64)
+    g = np.array([[1 << 21], [1 << 21]], np.int64)
+    assert oracle.gemm(c, g)[0, 0] == 0
+    with pytest.raises(oracle.OracleError):
+        oracle.gemm(c, np.array([[1 << 23], [0]], np.int64))
+
+
+@pytest.mark.parametrize("M", [3, 4, 8])
+def test_gemm_entangled_closed_form_and_recovery(M):
+    """Entangled blocks times G hold D_m + 2^l D_(m-1) (linearity of the
+    product), and every block is recovered from any M-1 of them."""
+    l, _, _ = oracle.params(M, 64)
+    c = _rand(M + 60, -2048, 2048, (M, 9, 33))
+    g = _rand(M + 61, -2048, 2048, (33, 11))
+    plain = np.stack([blk.astype(object) @ g.astype(object) for blk in c])
+    for r in range(M):
+        dhat, delta = oracle.gemm_pipeline(c, g, r=r)
+        assert np.array_equal(dhat.astype(object), plain), (M, r)
+    want = plain + (np.roll(plain, 1, axis=0) << l)
+    assert np.array_equal(delta.astype(object), want)
+
+
 @pytest.mark.parametrize("w", [32, 64])
 def test_c_oracle_matches_bigint_twin(w):
     g = np.random.default_rng(w)
