@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="use the default tile steps instead of the autotuner's")
     p.add_argument("--config", default="batched",
-                   choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain"),
+                   choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain", "gemm"),
                    help="workload; the benchmark line is the batched one")
     p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -125,6 +125,8 @@ def main():
         return fig2_line(args, wl)
     if args.config == "chain":
         return chain_line(args, wl)
+    if args.config == "gemm":
+        return gemm_line(args, wl)
     t_gen = time.perf_counter()
     cfg = CONFIGS[args.config]
     groups, in_bits, describe = cfg(wl, args)
@@ -477,6 +479,95 @@ def chain_line(args, wl):
         "baselines": {"ms_per_step": {"entangled": round(t_ent, 4), "plain": round(t_plain, 4),
                                       "entangled_one_lost": round(t_lost, 4)},
                       "overhead_pct_vs_plain": round(100 * (t_ent / t_plain - 1), 2)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _digits(neg: int, pos: int) -> int:
+    """Fewest balanced base-256 digits covering [-neg, pos] (the kernels'
+    digit rule, restated here to count the matrix-core work)."""
+    R, p = 0, 1
+    for L in range(1, 17):
+        R += p
+        p *= 256
+        if 128 * R >= neg and 127 * R >= pos:
+            return L
+    return 17
+
+
+def gemm_line(args, wl):
+    """Entangled integer matrix product (Sec. IV's GEMM case): 3 blocks of
+    4096 x 1024 int32 values times one 1024 x 4096 kernel matrix, values in
+    [-2^11, 2^11); entangle on load, product on the i8 matrix cores, recover
+    in registers, one launch; against the plain product (narrow and on the
+    same datapath), the checksum method and one lost block."""
+    import numpy as np
+    import torch
+    from paper_1509_03838_amd import ne
+
+    dev = torch.device("cuda:0")
+    c, g = wl.config_gemm()
+    M, N, P = c.shape
+    Q = g.shape[1]
+    bits = wl.GEMM_BITS
+    cd = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for b in c]
+    gd = torch.from_numpy(g).to(dev)
+    out = [torch.empty((N, Q), dtype=torch.int64, device=dev) for _ in range(M)]
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.Stream()
+
+    def timed(mode, lost=-1):
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                ne.gemm(cd, gd, out, mode, lost, bits, flags=flags, stream=stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                ne.gemm(cd, gd, out, mode, lost, bits, flags=flags, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms = {}
+    ref = None
+    for mode in ("entangled", "plain", "plain_same", "checksum"):
+        ms[mode] = timed(mode)
+        snap = torch.stack([o[::97, ::89] for o in out]).cpu()
+        if int(flags.item()) or (ref is not None and not torch.equal(snap, ref)):
+            raise SystemExit(f"gemm: {mode} results differ or flagged")
+        ref = snap
+    ms["entangled_one_lost"] = timed("entangled", 1)
+    B = 1 << (bits - 1)
+    l = ne.params(M)[0]
+    la = _digits(B * ((1 << l) + 1), (B - 1) * ((1 << l) + 1))
+    lb = _digits(B, B - 1)
+    pairs = sum(1 for a in range(la) for b in range(lb) if a + b < 8)
+    pad = lambda x, t: (x + t - 1) // t * t
+    mfma_ops = 2 * M * pad(N, 32) * pad(Q, 32) * pad(P, 64) * pairs
+    useful_ops = 2 * M * N * P * Q
+    e = ms["entangled"]
+    tops = mfma_ops / (e * 1e-3) / 1e12
+    samples = M * N * Q
+    alg_bytes = M * N * P * 4 + P * Q * 4 + M * N * Q * 8
+    line = {
+        "metric": METRIC, "value": round(samples / (e * 1e-3) / 1e9, 3),
+        "unit": "Gout-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(e, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"gemm: {M} blocks of {N}x{P} int32 values in [-2^11,2^11) times "
+                               f"one {P}x{Q} kernel matrix, entangled (l={l}), one launch",
+                   "w": 64, "digits": [la, lb]},
+        "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "k_gemm_fused (i8 ops issued: digit pairs x padded tiles)",
+                     "useful_int_tops": round(useful_ops / (e * 1e-3) / 1e12, 2),
+                     "hbm_GBps": round(alg_bytes / (e * 1e-3) / 1e9, 1)},
+        "baselines": {"ms_per_step": {k: round(v, 4) for k, v in ms.items()},
+                      "overhead_pct_vs_plain_same": round(100 * (e / ms["plain_same"] - 1), 2),
+                      "overhead_pct_vs_plain": round(100 * (e / ms["plain"] - 1), 2),
+                      "checksum_overhead_pct_vs_plain_same":
+                          round(100 * (ms["checksum"] / ms["plain_same"] - 1), 2)},
     }
     print(json.dumps(line), flush=True)
 

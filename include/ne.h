@@ -263,6 +263,35 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
                          size_t workspace_bytes, ne_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Entangled integer matrix product: the multiplication operator of eq. (2)
+ * applied to M blocks of the streams and one shared kernel matrix (the GEMM
+ * case of Sec. IV, eq. (20)): D_m = C_m G for every block m, computed by the
+ * method of `mode` in one fused pass -- blocks entangled on load
+ * (eq. (14)-(15)), each entangled block multiplied by G on the i8 matrix
+ * cores, every output recovered from the M-1 blocks other than `lost`
+ * (eq. (16)-(19)) -- or plain, plain on the same datapath, or with a
+ * checksum block (eq. (3)-(5)).
+ *
+ * c: host array of M device pointers to N x P int32 matrices (row-major);
+ * g: device P x Q int32 matrix (row-major); out: host array of M device
+ * pointers to N x Q int64 matrices (row-major, disjoint from the inputs).
+ * Every value of c and g must lie in [-2^(in_bits-1), 2^(in_bits-1)),
+ * in_bits in [1, 16]; values outside are flagged (NE_FLAG_INPUT_RANGE).
+ * lost: -1, or the block whose product is not computed (its output is
+ * recovered; plain modes leave it unwritten). flags: device word OR-ed with
+ * NE_FLAG_* bits (NULL: not reported). One launch on `stream`, no
+ * allocation.
+ * Errors: NE_EINVAL (mode, M, negative sizes, NULL pointers of non-empty
+ * matrices), NE_EFAILIDX (lost), NE_ERANGE (P 2^(2 in_bits - 2) above D of
+ * ne_params(M, 64) for the method, above 2^63 - 1 otherwise), NE_EUNSUP
+ * (in_bits above 16, N above 32 * 65535, Q above 2^26, P above 2^24, or an
+ * inner dimension too long for exact 32-bit digit sums).
+ */
+ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q,
+                  const int32_t *const *c, const int32_t *g, int64_t *const *out, int32_t lost,
+                  int32_t in_bits, uint32_t *flags, ne_stream stream);
+
+/* ------------------------------------------------------------------------
  * Batched executor: many groups (uneven M, length, operation and operand
  * size) in a fixed set of fused launches, optionally as one hipGraph.
  *

@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "libne.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "chain.hip", "fused.hip", "plan.hip"]
+SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "chain.hip", "fused.hip", "plan.hip",
+           "gemm.hip"]
 
 # fused_conv.hip is compiled once per (kernel class, slot count), and
 # fused_stream.hip once per kernel class: entangled
@@ -36,6 +37,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     units += [("fused_conv.hip", f"fused_conv_{k}_{n}.o", [f"-DNE_KCLASS={k}", f"-DNE_SLOTS={n}"])
               for k, n in CONV_VARIANTS]
     units += [("fused_stream.hip", f"fused_stream_{k}.o", [f"-DNE_KCLASS={k}"]) for k in range(3)]
+    units += [("gemm_kernels.hip", f"gemm_kernels_{k}.o", [f"-DNE_KCLASS={k}"]) for k in range(3)]
     objs = []
     pending = list(units)
     running = []

@@ -105,4 +105,20 @@ constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb, int sp
     return false;
 }
 
+// Whether some group of this kernel class and slot count, with inputs of
+// 1..max_bits bits, uses digit counts (la, lb) (any top-digit sparsity).
+constexpr bool digits_needed(int kclass, int slots, int la, int lb, int max_bits)
+{
+    for (int mode = 0; mode < 4; ++mode) {
+        if (conv_class_of_mode(mode) != kclass) continue;
+        const int M = mode == 3 ? slots - 1 : slots;
+        if (M < (mode == 0 ? 3 : (mode == 3 ? 2 : 1)) || M > 8) continue;
+        for (int b = 1; b <= max_bits; ++b) {
+            const DigitCounts d = conv_digits(mode, M, b);
+            if (d.la == la && d.lb == lb) return true;
+        }
+    }
+    return false;
+}
+
 }  // namespace ne

@@ -25,7 +25,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_plain_apply", "ne_checksum", "ne_checksum_recover", "ne_plan_create",
            "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
            "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in",
-           "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply")
+           "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
+        "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -428,3 +429,25 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
     _check("ne_chain_apply", load().ne_chain_apply(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
                                                    _ptr_array(delta), n, mask & 0xFFFFFFFF,
                                                    _ptr(workspace), ws_bytes, _stream(stream)))
+
+
+def gemm(c: Sequence, g, out: Sequence, mode: str = "entangled", lost: int = -1,
+         in_bits: int = 16, flags=None, stream=None):
+    """out[m] = c[m] @ g for M int32 blocks c[m] (N x P) and an int32 kernel
+    matrix g (P x Q), int64 outputs (N x Q), by the method of `mode`."""
+    import torch
+    _dtype(c, torch.int32, "c")
+    _dtype([g], torch.int32, "g")
+    _dtype(out, torch.int64, "out")
+    if g.dim() != 2:
+        raise ValueError("g must be a matrix")
+    P, Q = g.shape
+    N = out[0].shape[0] if out[0].dim() == 2 else 0
+    for t in c:
+        if t.dim() != 2 or t.shape[1] != P or t.shape[0] != N:
+            raise ValueError("every block must be N x P")
+    for t in out:
+        if t.dim() != 2 or tuple(t.shape) != (N, Q):
+            raise ValueError("every output must be N x Q")
+    _check("ne_gemm", load().ne_gemm(MODES[mode], len(c), N, P, Q, _ptr_array(c), _ptr(g),
+                                     _ptr_array(out), lost, in_bits, _ptr(flags), _stream(stream)))

@@ -175,6 +175,18 @@ def chain_series(g: np.random.Generator, n: int, recipe=CHAIN_RECIPE, bits: int 
     return out
 
 
+GEMM_BITS = 12
+
+
+def config_gemm(seed: int = SEED_BASE + 8, M: int = 3, N: int = 4096, P: int = 1024,
+                Q: int = 4096) -> tuple[np.ndarray, np.ndarray]:
+    """M blocks of N x P int32 values and one P x Q kernel matrix, all
+    uniform in [-2^11, 2^11) (the batched configuration's range)."""
+    g = rng(seed)
+    lo, hi = -(1 << (GEMM_BITS - 1)), 1 << (GEMM_BITS - 1)
+    return uniform_i32(g, lo, hi, (M, N, P)), uniform_i32(g, lo, hi, (P, Q))
+
+
 @dataclass
 class Job:
     arrival_s: float

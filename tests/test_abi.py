@@ -324,3 +324,34 @@ def test_series_of_empty_streams_needs_no_workspace(lib):
     assert ne.chain_workspace_size(3, 0, ops) == 0
     nulls = ne._ptr_array([None, None, None])
     assert lib.ne_chain_apply(3, 0, nulls, ne._chain_c(ops), 2, nulls, 0, 7, None, 0, None) == 0
+
+
+# ---------------------------------------------------- matrix product (host)
+
+@pytest.mark.parametrize("args,status", [
+    (dict(mode=4), -1),                      # unknown mode
+    (dict(M=2), -1),                         # the method needs M >= 3
+    (dict(M=9), -1),                         # above the fused limit
+    (dict(N=-1), -1),
+    (dict(lost=3), -3),                      # lost block out of range
+    (dict(in_bits=0), -1),
+    (dict(in_bits=17), -4),                  # beyond the supported values
+    (dict(P=1 << 20, in_bits=16), -2),       # worst case above D
+    (dict(Q=(1 << 26) + 1), -4),
+    (dict(N=0), 0),                          # no outputs: nothing to do
+    (dict(Q=0), 0),
+])
+def test_gemm_validation(lib, args, status):
+    a = dict(mode=0, M=3, N=8, P=8, Q=8, lost=-1, in_bits=12)
+    a.update(args)
+    c = ne._ptr_array([FAKE + 4096 * m for m in range(8)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 4096 * m for m in range(8)])
+    assert lib.ne_gemm(a["mode"], a["M"], a["N"], a["P"], a["Q"], c, FAKE, out, a["lost"],
+                       a["in_bits"], None, None) == status
+
+
+def test_gemm_null_blocks_refused(lib):
+    c = ne._ptr_array([FAKE, 0, FAKE])
+    out = ne._ptr_array([FAKE, FAKE, FAKE])
+    assert lib.ne_gemm(0, 3, 8, 8, 8, c, FAKE, out, -1, 12, None, None) == -1
+    assert lib.ne_gemm(0, 3, 8, 8, 8, out, 0, out, -1, 12, None, None) == -1
