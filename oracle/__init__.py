@@ -11,7 +11,9 @@ integers for tiny inputs.
 
 Conventions: a group of M streams of n samples is an int64 array of shape
 (M, n). Integer op codes follow the paper's eq. (2): CONV (full linear
-convolution), SCALE, ADD, INNER (inner product), PERM (fixed permutation).
+convolution), SCALE, ADD, INNER (inner product), PERM (fixed permutation),
+SUB, MUL (element by element), CIRC (circular convolution), XCORR (full
+cross-correlation), OUTER (outer product).
 """
 from __future__ import annotations
 
@@ -26,7 +28,12 @@ _SRC = os.path.join(_HERE, "ne_oracle.c")
 _LIB = os.path.join(_HERE, "libne_oracle.so")
 
 CONV, SCALE, ADD, INNER, PERM = 0, 1, 2, 3, 4
-OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM}
+SUB, MUL, CIRC, XCORR, OUTER = 5, 6, 7, 8, 9
+OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM,
+       "sub": SUB, "mul": MUL, "circ": CIRC, "xcorr": XCORR, "outer": OUTER}
+# operations whose vector operand is added or subtracted: on entangled data it
+# is entangled with itself first (footnote 3)
+ADDITIVE = ("add", "sub")
 
 OK, EINVAL, EOVERFLOW, EINEXACT = 0, 1, 2, 3
 
@@ -117,10 +124,12 @@ def entangle_operand(g, l: int, w: int = 64) -> np.ndarray:
 
 
 def n_out(op: str, n_in: int, n_operand: int) -> int:
-    if op == "conv":
+    if op in ("conv", "xcorr"):
         return 0 if n_in == 0 or n_operand == 0 else n_in + n_operand - 1
     if op == "inner":
         return 1
+    if op == "outer":
+        return n_in * n_operand
     return n_in
 
 
@@ -184,7 +193,7 @@ def pipeline(c, op: str, operand=None, scalar: int = 0, r: int = 0, w: int = 64)
     l, _, _ = params(M, w)
     eps = entangle(c, l, w)
     g = operand
-    if op == "add":
+    if op in ADDITIVE:
         g = entangle_operand(operand, l, w)
     delta = apply(op, eps, g, scalar, w)
     return extract(delta, r, l, w), eps, delta
@@ -210,7 +219,7 @@ def chain_pipeline(c, ops, r: int = 0, w: int = 64):
     l, _, _ = params(M, w)
     x = entangle(c, l, w)
     for op, operand, scalar in ops:
-        g = entangle_operand(operand, l, w) if op == "add" else operand
+        g = entangle_operand(operand, l, w) if op in ADDITIVE else operand
         x = apply(op, x, g, scalar, w)
     return extract(x, r, l, w), x
 

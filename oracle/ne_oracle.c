@@ -37,7 +37,10 @@ enum {
     ORC_EINEXACT = 3  /* a shift that the method says is exact dropped bits */
 };
 
-enum { ORC_CONV = 0, ORC_SCALE = 1, ORC_ADD = 2, ORC_INNER = 3, ORC_PERM = 4 };
+enum {
+    ORC_CONV = 0, ORC_SCALE = 1, ORC_ADD = 2, ORC_INNER = 3, ORC_PERM = 4,
+    ORC_SUB = 5, ORC_MUL = 6, ORC_CIRC = 7, ORC_XCORR = 8, ORC_OUTER = 9
+};
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -187,6 +190,17 @@ static int conv_one(const int64_t *x, int64_t n, const int64_t *g, int64_t K, in
  *   ORC_INNER: d[0] = sum_i x[i] * operand[i], n_out = 1, n_operand = n_in
  *   ORC_PERM : d[i] = x[operand[i]], a fixed bijection of [0, n_in)
  *              (footnote 2), n_out = n_in = n_operand
+ * and the other operators eq. (2) lists:
+ *   ORC_SUB  : d[i] = x[i] - operand[i] (entangled operand on entangled
+ *              data, as for addition)
+ *   ORC_MUL  : d[i] = x[i] * operand[i] (element-by-element product)
+ *   ORC_CIRC : circular convolution of length n_in,
+ *              d[t] = sum_j operand[j] x[(t - j) mod n_in], n_out = n_in
+ *   ORC_XCORR: full cross-correlation,
+ *              d[t] = sum_j operand[j] x[t + j - (n_operand - 1)],
+ *              n_out = n_in + n_operand - 1 (0 when either length is 0)
+ *   ORC_OUTER: outer product, d[i n_operand + j] = x[i] operand[j],
+ *              n_out = n_in n_operand
  * Every output must fit in w bits, else ORC_EOVERFLOW. */
 int orc_op(int op, int w, int64_t n_in, const int64_t *x, const int64_t *operand,
            int64_t n_operand, int64_t scalar, int64_t *out, int64_t n_out)
@@ -241,6 +255,61 @@ int orc_op(int op, int w, int64_t n_in, const int64_t *x, const int64_t *operand
             if (s < 0 || s >= n_in) return ORC_EINVAL;
             out[i] = x[s];
         }
+        return ORC_OK;
+    }
+    case ORC_SUB:
+    case ORC_MUL: {
+        if (n_out != n_in || n_operand != n_in) return ORC_EINVAL;
+        for (int64_t i = 0; i < n_in; ++i) {
+            i128 v;
+            if (op == ORC_SUB)
+                v = (i128)x[i] - (i128)operand[i];
+            else if (!mul_ok((i128)x[i], (i128)operand[i], &v))
+                return ORC_EOVERFLOW;
+            if (!fits(v, w)) return ORC_EOVERFLOW;
+            out[i] = (int64_t)v;
+        }
+        return ORC_OK;
+    }
+    case ORC_CIRC: {
+        if (n_out != n_in || (n_in > 0 && n_operand < 1)) return ORC_EINVAL;
+        for (int64_t t = 0; t < n_out; ++t) {
+            i128 acc = 0, p;
+            for (int64_t j = 0; j < n_operand; ++j) {
+                int64_t src = (t - j) % n_in;
+                if (src < 0) src += n_in;
+                if (!mul_ok((i128)operand[j], (i128)x[src], &p) || !add_ok(acc, p, &acc))
+                    return ORC_EOVERFLOW;
+            }
+            if (!fits(acc, w)) return ORC_EOVERFLOW;
+            out[t] = (int64_t)acc;
+        }
+        return ORC_OK;
+    }
+    case ORC_XCORR: {
+        int64_t want = (n_in == 0 || n_operand == 0) ? 0 : n_in + n_operand - 1;
+        if (n_out != want) return ORC_EINVAL;
+        for (int64_t t = 0; t < n_out; ++t) {
+            i128 acc = 0, p;
+            for (int64_t j = 0; j < n_operand; ++j) {
+                int64_t src = t + j - (n_operand - 1);
+                if (src < 0 || src >= n_in) continue;
+                if (!mul_ok((i128)operand[j], (i128)x[src], &p) || !add_ok(acc, p, &acc))
+                    return ORC_EOVERFLOW;
+            }
+            if (!fits(acc, w)) return ORC_EOVERFLOW;
+            out[t] = (int64_t)acc;
+        }
+        return ORC_OK;
+    }
+    case ORC_OUTER: {
+        if (n_out != n_in * n_operand) return ORC_EINVAL;
+        for (int64_t i = 0; i < n_in; ++i)
+            for (int64_t j = 0; j < n_operand; ++j) {
+                i128 v;
+                if (!mul_ok((i128)x[i], (i128)operand[j], &v) || !fits(v, w)) return ORC_EOVERFLOW;
+                out[i * n_operand + j] = (int64_t)v;
+            }
         return ORC_OK;
     }
     default:

@@ -342,6 +342,56 @@ def test_add_needs_entangled_operand():
     assert not np.array_equal(bad, c + g)
 
 
+# ------------------------------------------- the other operators of eq. (2)
+
+@pytest.mark.parametrize("n,K", [(1, 1), (7, 3), (100, 17), (40, 64), (257, 257)])
+def test_more_operators_match_numpy(n, K):
+    """Subtraction, element-by-element product, circular convolution,
+    cross-correlation and outer product against numpy on Python integers."""
+    x = _rand(n + K, -3000, 3000, n)
+    v = _rand(n + K + 1, -3000, 3000, n)
+    g = _rand(n + K + 2, -3000, 3000, K)
+    xo, vo, go = x.astype(object), v.astype(object), g.astype(object)
+    assert np.array_equal(oracle.apply("sub", x, v).astype(object), xo - vo)
+    assert np.array_equal(oracle.apply("mul", x, v).astype(object), xo * vo)
+    circ = [sum(go[j] * xo[(t - j) % n] for j in range(K)) for t in range(n)]
+    assert oracle.apply("circ", x, g).tolist() == circ
+    assert np.array_equal(oracle.apply("xcorr", x, g).astype(object),
+                          np.correlate(xo, go, "full"))
+    assert np.array_equal(oracle.apply("outer", x, g).astype(object), np.outer(xo, go).ravel())
+
+
+def test_circular_convolution_is_folded_linear_convolution():
+    """Circular convolution of length n = the linear convolution with its
+    tail folded back (indices mod n), an identity independent of the
+    definition above."""
+    x = _rand(1, -500, 500, 50)
+    g = _rand(2, -500, 500, 120)  # longer than the stream: folds twice
+    lin = np.convolve(x, g).astype(object)
+    fold = np.zeros(50, dtype=object)
+    for t, v in enumerate(lin):
+        fold[t % 50] += v
+    assert np.array_equal(oracle.apply("circ", x, g).astype(object), fold)
+
+
+@pytest.mark.parametrize("op", ["sub", "mul", "circ", "xcorr", "outer"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_more_operators_recover(op, M):
+    """The method recovers each of them from any M-1 streams, and the
+    entangled outputs hold d_m + 2^l d_(m-1) (all are linear in the
+    stream; subtraction entangles its operand like addition)."""
+    n = 90
+    c = _rand(M + 5 * len(op), -2048, 2048, (M, n))
+    g = _rand(M + 6 * len(op), -2048, 2048, 23 if op in ("circ", "xcorr", "outer") else n)
+    plain = oracle.apply(op, c, g)
+    l, _, _ = oracle.params(M, 64)
+    for r in range(M):
+        dhat, _, delta = oracle.pipeline(c, op, g, r=r)
+        assert np.array_equal(dhat, plain), (op, M, r)
+    want = plain.astype(object) + (np.roll(plain.astype(object), 1, axis=0) << l)
+    assert np.array_equal(delta.astype(object), want)
+
+
 # --------------------------------------------------- series of operations
 
 def _numpy_series(c, ops):
