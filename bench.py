@@ -53,7 +53,8 @@ def parse():
     p.add_argument("--no-autotune", action="store_true",
                    help="use the default tile steps instead of the autotuner's")
     p.add_argument("--config", default="batched",
-                   choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain", "gemm"),
+                   choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain", "gemm",
+                            "ops"),
                    help="workload; the benchmark line is the batched one")
     p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -127,6 +128,8 @@ def main():
         return chain_line(args, wl)
     if args.config == "gemm":
         return gemm_line(args, wl)
+    if args.config == "ops":
+        return ops_line(args, wl)
     t_gen = time.perf_counter()
     cfg = CONFIGS[args.config]
     groups, in_bits, describe = cfg(wl, args)
@@ -568,6 +571,97 @@ def gemm_line(args, wl):
                       "overhead_pct_vs_plain": round(100 * (e / ms["plain"] - 1), 2),
                       "checksum_overhead_pct_vs_plain_same":
                           round(100 * (ms["checksum"] / ms["plain_same"] - 1), 2)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def ops_line(args, wl):
+    """The other operators of eq. (2) on the per-step path: for each of
+    subtraction, element-by-element product, circular convolution (64 taps),
+    cross-correlation (64 taps) and outer product (8 values), 3 streams of
+    2^22 samples in [-2^9, 2^9) through entangle -> op -> extract, against
+    the plain op on the raw streams."""
+    import numpy as np
+    import torch
+    from paper_1509_03838_amd import ne
+
+    dev = torch.device("cuda:0")
+    M, n, bits = 3, 1 << 22, 10
+    rng = wl.rng(wl.SEED_BASE + 9)
+    lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+    c = wl.uniform_i32(rng, lo, hi, (M, n))
+    l = ne.params(M)[0]
+    stream = torch.cuda.Stream()
+    cd = [torch.from_numpy(row).to(dev) for row in c]
+    eps = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(M)]
+    sizes = {"sub": n, "mul": n, "circ": 64, "xcorr": 64, "outer": 8}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    rows, tot_samples, tot_ms, tot_bytes = {}, 0, 0.0, 0
+    for op, K in sizes.items():
+        g = wl.uniform_i32(rng, lo, hi, K)
+        g32 = torch.from_numpy(g).to(dev)
+        operand = g32
+        if op == "sub":
+            operand = torch.empty(n, dtype=torch.int64, device=dev)
+            ne.entangle_operand(g32, operand, l, stream=stream)
+        no = ne.n_out(op, n, K)
+        delta = [torch.empty(no, dtype=torch.int64, device=dev) for _ in range(M)]
+        dhat = [torch.empty(no, dtype=torch.int64, device=dev) for _ in range(M)]
+
+        def ent():
+            ne.entangle(cd, eps, l, stream=stream)
+            ne.lsb_apply(op, eps, operand, delta, n_in=n, stream=stream)
+            ne.extract_recover(delta, -1, dhat, l, stream=stream)
+
+        def plain():
+            ne.plain_apply(op, cd, g32, dhat, stream=stream)
+
+        t_plain = timed(plain)
+        ref = torch.stack([t[::4099] for t in dhat]).cpu()
+        t_ent = timed(ent)
+        if not torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref):
+            raise SystemExit(f"ops: {op} entangled and plain results differ")
+        # algorithmic HBM bytes of the three launches: entangle, op, extract
+        nb = (M * n * 12 + M * (n + no) * 8 + operand.numel() * operand.element_size() +
+              (2 * M - 1) * no * 8)
+        rows[op] = {"K": K, "n_out": no, "ms": {"entangled": round(t_ent, 4), "plain": round(t_plain, 4)},
+                    "gout_per_s": round(M * no / (t_ent * 1e-3) / 1e9, 3),
+                    "hbm_GBps": round(nb / (t_ent * 1e-3) / 1e9, 1),
+                    "overhead_pct_vs_plain": round(100 * (t_ent / t_plain - 1), 2)}
+        tot_samples += M * no
+        tot_ms += t_ent
+        tot_bytes += nb
+        print(f"# ops {op}: entangled {t_ent:.4f} ms, plain {t_plain:.4f} ms", file=sys.stderr,
+              flush=True)
+        del delta, dhat
+    line = {
+        "metric": METRIC, "value": round(tot_samples / (tot_ms * 1e-3) / 1e9, 3),
+        "unit": "Gout-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(tot_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "operators: 3 streams x 2^22 int32 samples in [-2^9,2^9); sub, mul, "
+                               "circ (64 taps), xcorr (64 taps), outer (8 values); entangle -> op -> "
+                               "extract per-step kernels; value = all outputs / the sum of times",
+                   "w": 64, "l": l},
+        "roofline": {"bound": "hbm", "achieved": round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(tot_bytes / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": "all launches of the five pipelines (per-operator rows below; the "
+                               "convolution-like ones are bound by the vector ALUs)"},
+        "ops": rows,
     }
     print(json.dumps(line), flush=True)
 

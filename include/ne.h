@@ -70,7 +70,17 @@ typedef enum ne_op {
     NE_OP_SCALE = 1, /* y[i] = s * x[i] (scalar multiplication) */
     NE_OP_ADD = 2,   /* y[i] = x[i] + g[i] (element-wise addition) */
     NE_OP_INNER = 3, /* y[0] = sum_i x[i] g[i] (inner product) */
-    NE_OP_PERM = 4   /* y[i] = x[p[i]] for a fixed bijection p (footnote 2) */
+    NE_OP_PERM = 4,  /* y[i] = x[p[i]] for a fixed bijection p (footnote 2) */
+    /* The other operators eq. (2) lists (per-step calls and series; the
+       batched executor runs NE_OP_CONV .. NE_OP_PERM): */
+    NE_OP_SUB = 5,   /* y[i] = x[i] - g[i] (element-wise subtraction) */
+    NE_OP_MUL = 6,   /* y[i] = x[i] g[i] (element-by-element product) */
+    NE_OP_CIRC = 7,  /* circular convolution of length n with K taps:
+                        y[t] = sum_{j<K} g[j] x[(t-j) mod n], 0 <= t < n */
+    NE_OP_XCORR = 8, /* full cross-correlation with K taps:
+                        y[t] = sum_{j<K} g[j] x[t+j-(K-1)], 0 <= t < n+K-1 */
+    NE_OP_OUTER = 9  /* outer product with a vector of K values:
+                        y[i K + j] = x[i] g[j], 0 <= i < n, 0 <= j < K */
 } ne_op;
 
 typedef void *ne_stream; /* a hipStream_t */
@@ -115,8 +125,8 @@ ne_status ne_entangle_inplace(int32_t M, int32_t l, int64_t n, int64_t *const *x
                               ne_stream stream);
 
 /*
- * Entangle an operand with itself (footnote 3), needed for NE_OP_ADD on
- * entangled streams: g_ent[i] = g[i] + 2^l g[i]. g: n int32; g_ent: n int64.
+ * Entangle an operand with itself (footnote 3), needed for NE_OP_ADD and
+ * NE_OP_SUB on entangled streams: g_ent[i] = g[i] + 2^l g[i]. g: n int32; g_ent: n int64.
  */
 ne_status ne_entangle_operand(int32_t l, int64_t n, const int32_t *g, int64_t *g_ent,
                               ne_stream stream);
@@ -139,6 +149,13 @@ ne_status ne_entangle_operand(int32_t l, int64_t n, const int32_t *g, int64_t *g
  *   NE_OP_PERM : operand = int32 indices p of n_operand = n_in, a
  *                permutation of [0, n_in) (not checked; an index outside
  *                the range is clamped into it); n_out = n_in
+ *   NE_OP_SUB  : as NE_OP_ADD (the operand entangled likewise)
+ *   NE_OP_MUL  : operand = int32 vector of n_operand = n_in; n_out = n_in
+ *   NE_OP_CIRC : operand = int32 kernel of K >= 1 taps (K may exceed
+ *                n_in: the taps wrap); n_out = n_in
+ *   NE_OP_XCORR: operand = int32 kernel of K >= 1 taps;
+ *                n_out = n_in + K - 1 (0 when n_in = 0)
+ *   NE_OP_OUTER: operand = int32 vector of K >= 0 values; n_out = n_in K
  * M in [1, NE_MAX_M] (the operation itself does not depend on
  * entanglement, so this also runs the checksum stream of the checksum
  * method). delta must not overlap eps or the operand.
@@ -167,8 +184,8 @@ ne_status ne_extract_recover(int32_t M, int32_t l, int64_t n_out, const int64_t 
 /*
  * Failure-intolerant baseline: the same LSB operations on n_streams raw
  * int32 streams, int64 outputs, computed exactly (no entanglement). The
- * operand types are those of ne_lsb_apply except NE_OP_ADD, whose operand
- * is an int32 vector here.
+ * operand types are those of ne_lsb_apply except NE_OP_ADD and NE_OP_SUB,
+ * whose operand is an int32 vector here.
  */
 ne_status ne_plain_apply(int32_t op, int32_t n_streams, int64_t n_in, const int32_t *const *c,
                          const void *operand, int64_t n_operand, int64_t scalar,
@@ -204,25 +221,28 @@ ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
  */
 typedef struct ne_chain_op {
     int32_t op;           /* ne_op */
-    int32_t operand_bits; /* NE_OP_CONV, NE_OP_ADD, NE_OP_INNER: every value g
+    int32_t operand_bits; /* every op but NE_OP_SCALE and NE_OP_PERM: every value g
                              of the plain operand satisfies
                              -2^(b-1) <= g < 2^(b-1), b in [1, 32] (the
                              range check's promise; not verified on the
                              device); ignored for NE_OP_SCALE and NE_OP_PERM */
     const void *operand;  /* device operand, typed as for ne_lsb_apply (for
-                             NE_OP_ADD on entangled streams: the entangled
-                             int64 vector, ne_entangle_operand); may be NULL
+                             NE_OP_ADD and NE_OP_SUB on entangled streams:
+                             the entangled int64 vector,
+                             ne_entangle_operand); may be NULL
                              for ne_chain_check, which reads no operand */
-    int64_t n_operand;    /* taps (conv); the current length (add, inner,
-                             perm); ignored for scale */
+    int64_t n_operand;    /* taps (conv, circ, xcorr), values (outer); the
+                             current length (add, sub, mul, inner, perm);
+                             ignored for scale */
     int64_t scalar;       /* NE_OP_SCALE: the factor */
 } ne_chain_op;
 
 /*
  * Shapes and worst-case range of a series on M streams of n_in samples
  * whose values lie in [-2^(in_bits-1), 2^(in_bits-1)). Stage by stage, the
- * bound B on |d| becomes K 2^(b-1) B (conv), |s| B (scale), B + 2^(b-1)
- * (add), n 2^(b-1) B (inner) or B (perm); every stage must satisfy
+ * bound B on |d| becomes K 2^(b-1) B (conv, circ, xcorr), |s| B (scale),
+ * B + 2^(b-1) (add, sub), n 2^(b-1) B (inner), 2^(b-1) B (mul, outer) or
+ * B (perm); every stage must satisfy
  * B <= D of ne_params(M, 64), so that no entangled intermediate leaves the
  * 64-bit range (wrapping would be harmless for these linear operations,
  * but the check keeps every intermediate an exact integer). Host-only.

@@ -52,12 +52,23 @@ ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t 
     if (n_in < 0 || n_operand < 0 || n_out < 0) return NE_EINVAL;
     switch (op) {
     case NE_OP_CONV:
+    case NE_OP_XCORR:
         if (n_operand < 1 || !operand) return NE_EINVAL;
         if (n_out != (n_in == 0 ? 0 : n_in + n_operand - 1)) return NE_EINVAL;
+        return NE_OK;
+    case NE_OP_CIRC:
+        if (n_operand < 1 || !operand || n_out != n_in) return NE_EINVAL;
+        return NE_OK;
+    case NE_OP_OUTER:
+        if (n_operand > 0 && n_in > INT64_MAX / n_operand) return NE_EUNSUP;
+        if (n_out != n_in * n_operand) return NE_EINVAL;
+        if (n_operand > 0 && !operand) return NE_EINVAL;
         return NE_OK;
     case NE_OP_SCALE:
         return n_out == n_in ? NE_OK : NE_EINVAL;
     case NE_OP_ADD:
+    case NE_OP_SUB:
+    case NE_OP_MUL:
     case NE_OP_PERM:
         if (n_operand != n_in || n_out != n_in) return NE_EINVAL;
         if (n_in > 0 && !operand) return NE_EINVAL;
@@ -187,6 +198,17 @@ ne_status ne_lsb_apply(int32_t op, int32_t M, int64_t n_in, const int64_t *const
     case NE_OP_ADD: launch_add_i64(count, n_in, px, (const int64_t *)operand, py, s); break;
     case NE_OP_INNER: launch_inner_i64(count, n_in, px, (const int32_t *)operand, py, s); break;
     case NE_OP_PERM: launch_perm_i64(count, n_in, px, (const int32_t *)operand, py, s); break;
+    case NE_OP_SUB: launch_sub_i64(count, n_in, px, (const int64_t *)operand, py, s); break;
+    case NE_OP_MUL: launch_mul_i64(count, n_in, px, (const int32_t *)operand, py, s); break;
+    case NE_OP_CIRC:
+        launch_conv_i64(count, n_in, px, (const int32_t *)operand, n_operand, py, s, kConvCircular);
+        break;
+    case NE_OP_XCORR:
+        launch_conv_i64(count, n_in, px, (const int32_t *)operand, n_operand, py, s, kConvXcorr);
+        break;
+    case NE_OP_OUTER:
+        launch_outer_i64(count, n_in, px, (const int32_t *)operand, n_operand, py, s);
+        break;
     }
     return launch_status();
 }
@@ -241,6 +263,17 @@ ne_status ne_plain_apply(int32_t op, int32_t n_streams, int64_t n_in, const int3
     case NE_OP_ADD: launch_add_i32(count, n_in, px, (const int32_t *)operand, py, s); break;
     case NE_OP_INNER: launch_inner_i32(count, n_in, px, (const int32_t *)operand, py, s); break;
     case NE_OP_PERM: launch_perm_i32(count, n_in, px, (const int32_t *)operand, py, s); break;
+    case NE_OP_SUB: launch_sub_i32(count, n_in, px, (const int32_t *)operand, py, s); break;
+    case NE_OP_MUL: launch_mul_i32(count, n_in, px, (const int32_t *)operand, py, s); break;
+    case NE_OP_CIRC:
+        launch_conv_i32(count, n_in, px, (const int32_t *)operand, n_operand, py, s, kConvCircular);
+        break;
+    case NE_OP_XCORR:
+        launch_conv_i32(count, n_in, px, (const int32_t *)operand, n_operand, py, s, kConvXcorr);
+        break;
+    case NE_OP_OUTER:
+        launch_outer_i32(count, n_in, px, (const int32_t *)operand, n_operand, py, s);
+        break;
     }
     return launch_status();
 }

@@ -21,10 +21,19 @@ int64_t stage_out(const ne_chain_op &o, int64_t n_in)
 {
     switch (o.op) {
     case NE_OP_CONV:
+    case NE_OP_XCORR:
         if (o.n_operand < 1) return -1;
         return n_in == 0 ? 0 : n_in + o.n_operand - 1;
+    case NE_OP_CIRC:
+        if (o.n_operand < 1) return -1;
+        return n_in;
+    case NE_OP_OUTER:
+        if (o.n_operand < 0 || (o.n_operand > 0 && n_in > INT64_MAX / 8 / o.n_operand)) return -1;
+        return n_in * o.n_operand;
     case NE_OP_SCALE: return n_in;
     case NE_OP_ADD:
+    case NE_OP_SUB:
+    case NE_OP_MUL:
     case NE_OP_PERM:
         if (o.n_operand != n_in) return -1;
         if (o.op == NE_OP_PERM && n_in > INT32_MAX) return -1;
@@ -36,7 +45,7 @@ int64_t stage_out(const ne_chain_op &o, int64_t n_in)
     }
 }
 
-bool uses_operand_bits(int32_t op) { return op == NE_OP_CONV || op == NE_OP_ADD || op == NE_OP_INNER; }
+bool uses_operand_bits(int32_t op) { return op != NE_OP_SCALE && op != NE_OP_PERM; }
 
 // Walks the series: the output length of every stage, and the longest
 // intermediate (every stage but the last).
@@ -47,11 +56,11 @@ ne_status walk(int64_t n_in, const ne_chain_op *ops, int32_t n_ops, int64_t *n_o
     int64_t n = n_in, lg = 0;
     for (int32_t i = 0; i < n_ops; ++i) {
         const ne_chain_op &o = ops[i];
-        if (uses_operand_bits(o.op) && (o.operand_bits < 1 || o.operand_bits > 32))
-            return NE_EINVAL;
         const int64_t m = stage_out(o, n);
         if (m == -2) return NE_EUNSUP;
         if (m < 0) return NE_EINVAL;
+        if (uses_operand_bits(o.op) && (o.operand_bits < 1 || o.operand_bits > 32))
+            return NE_EINVAL;
         if (i + 1 < n_ops) lg = std::max(lg, m);
         n = m;
     }
@@ -82,14 +91,19 @@ ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chai
         const ne_chain_op &o = ops[i];
         const u128 G = uses_operand_bits(o.op) ? (u128)1 << (o.operand_bits - 1) : 0;
         switch (o.op) {
-        case NE_OP_CONV: B = B * G * (u128)o.n_operand; break;
+        case NE_OP_CONV:
+        case NE_OP_CIRC:
+        case NE_OP_XCORR: B = B * G * (u128)o.n_operand; break;
+        case NE_OP_MUL:
+        case NE_OP_OUTER: B = B * G; break;
         case NE_OP_SCALE: {
             const u128 s = o.scalar < 0 ? (u128)0 - (u128)(__int128)o.scalar : (u128)o.scalar;
             if (s > ((u128)1 << 62)) return NE_ERANGE;
             B = B * s;
             break;
         }
-        case NE_OP_ADD: B = B + G; break;
+        case NE_OP_ADD:
+        case NE_OP_SUB: B = B + G; break;
         case NE_OP_INNER: B = B * G * (u128)std::max<int64_t>(n, 1); break;
         case NE_OP_PERM: break;
         }
@@ -170,6 +184,19 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
                 break;
             case NE_OP_PERM:
                 launch_perm_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
+                break;
+            case NE_OP_SUB: launch_sub_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
+            case NE_OP_MUL: launch_mul_i64(count, n, cur, (const int32_t *)o.operand, dst, s); break;
+            case NE_OP_CIRC:
+                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
+                                kConvCircular);
+                break;
+            case NE_OP_XCORR:
+                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
+                                kConvXcorr);
+                break;
+            case NE_OP_OUTER:
+                launch_outer_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
                 break;
             }
             st = launch_status();

@@ -1,6 +1,9 @@
 // Full linear convolution y[t] = sum_{j<K} g[j] x[t-j] on the vector ALUs,
 // one stream per blockIdx.y, for int64 words (entangled or widened plain
 // streams, modulo 2^64) and for raw int32 streams (exact int64 results).
+// The same kernels run the circular convolution (the window read modulo
+// n, n outputs) and the full cross-correlation (the taps read reversed:
+// sum_j g[j] x[t+j-(K-1)] = sum_j g[K-1-j] x[t-j]).
 //
 // A block owns kTile consecutive outputs. For each chunk of up to kKC taps
 // it stages the input window the chunk touches, zero-padded outside
@@ -29,6 +32,7 @@ struct ConvArgsI64 {
     PtrsI64 y;
     const int32_t *g;
     int64_t n, K, n_out;
+    int32_t kind, pad_;  // ConvKind
 };
 
 struct ConvArgsI32 {
@@ -36,7 +40,24 @@ struct ConvArgsI32 {
     PtrsI64 y;
     const int32_t *g;
     int64_t n, K, n_out;
+    int32_t kind, pad_;
 };
+
+// Input index of window position idx: zero outside [0, n) (linear), or
+// wrapped modulo n (circular, n > 0); -1 marks a zero.
+__device__ __forceinline__ int64_t window_index(int64_t idx, int64_t n, int kind)
+{
+    if (kind == kConvCircular) {
+        int64_t r = idx % n;
+        return r < 0 ? r + n : r;
+    }
+    return (idx >= 0 && idx < n) ? idx : -1;
+}
+
+__device__ __forceinline__ int32_t tap(const int32_t *g, int64_t j, int64_t K, int kind)
+{
+    return g[kind == kConvXcorr ? K - 1 - j : j];
+}
 
 __global__ __launch_bounds__(kBlock) void k_conv_i64(ConvArgsI64 a)
 {
@@ -59,12 +80,12 @@ __global__ __launch_bounds__(kBlock) void k_conv_i64(ConvArgsI64 a)
         const int wlen = kTile + kc - 1;
         __syncthreads();
         for (int w = tid; w < wlen; w += kBlock) {
-            const int64_t idx = wbase + w;
-            const uint64_t v = (idx >= 0 && idx < a.n) ? (uint64_t)x[idx] : 0;
+            const int64_t idx = window_index(wbase + w, a.n, a.kind);
+            const uint64_t v = idx >= 0 ? (uint64_t)x[idx] : 0;
             sxl[w] = (uint32_t)v;
             sxh[w] = (uint32_t)(v >> 32);
         }
-        for (int j = tid; j < kc; j += kBlock) sg[j] = a.g[j0 + j];
+        for (int j = tid; j < kc; j += kBlock) sg[j] = tap(a.g, j0 + j, a.K, a.kind);
         __syncthreads();
         for (int j = 0; j < kc; ++j) {
             const int32_t gj = sg[j];
@@ -104,10 +125,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_i32(ConvArgsI32 a)
         const int wlen = kTile + kc - 1;
         __syncthreads();
         for (int w = tid; w < wlen; w += kBlock) {
-            const int64_t idx = wbase + w;
-            sx[w] = (idx >= 0 && idx < a.n) ? x[idx] : 0;
+            const int64_t idx = window_index(wbase + w, a.n, a.kind);
+            sx[w] = idx >= 0 ? x[idx] : 0;
         }
-        for (int j = tid; j < kc; j += kBlock) sg[j] = a.g[j0 + j];
+        for (int j = tid; j < kc; j += kBlock) sg[j] = tap(a.g, j0 + j, a.K, a.kind);
         __syncthreads();
         for (int j = 0; j < kc; ++j) {
             const int64_t gj = sg[j];
@@ -127,17 +148,17 @@ __global__ __launch_bounds__(kBlock) void k_conv_i32(ConvArgsI32 a)
 }  // namespace
 
 void launch_conv_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
-                     const PtrsI64 &y, hipStream_t s)
+                     const PtrsI64 &y, hipStream_t s, int kind)
 {
-    ConvArgsI64 a{x, y, g, n, K, n + K - 1};
+    ConvArgsI64 a{x, y, g, n, K, kind == kConvCircular ? n : n + K - 1, kind, 0};
     const int64_t tiles = (a.n_out + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_conv_i64, dim3((unsigned)tiles, count), dim3(kBlock), 0, s, a);
 }
 
 void launch_conv_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
-                     const PtrsI64 &y, hipStream_t s)
+                     const PtrsI64 &y, hipStream_t s, int kind)
 {
-    ConvArgsI32 a{x, y, g, n, K, n + K - 1};
+    ConvArgsI32 a{x, y, g, n, K, kind == kConvCircular ? n : n + K - 1, kind, 0};
     const int64_t tiles = (a.n_out + kTile - 1) / kTile;
     hipLaunchKernelGGL(k_conv_i32, dim3((unsigned)tiles, count), dim3(kBlock), 0, s, a);
 }

@@ -55,8 +55,16 @@ void launch_perm_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *p, 
                      hipStream_t s);
 void launch_inner_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,
                       hipStream_t s);
+// Convolution kinds: full linear, circular of length n, full cross-correlation.
+constexpr int kConvLinear = 0, kConvCircular = 1, kConvXcorr = 2;
 void launch_conv_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
-                     const PtrsI64 &y, hipStream_t s);
+                     const PtrsI64 &y, hipStream_t s, int kind = kConvLinear);
+void launch_sub_i64(int count, int64_t n, const PtrsCI64 &x, const int64_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_mul_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_outer_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
+                      const PtrsI64 &y, hipStream_t s);
 
 // The same operations on raw int32 streams with int64 results.
 void launch_scale_i32(int count, int64_t n, const PtrsI32 &x, int64_t s_val, const PtrsI64 &y,
@@ -68,7 +76,13 @@ void launch_perm_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *p, c
 void launch_inner_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
                       hipStream_t s);
 void launch_conv_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
-                     const PtrsI64 &y, hipStream_t s);
+                     const PtrsI64 &y, hipStream_t s, int kind = kConvLinear);
+void launch_sub_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_mul_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s);
+void launch_outer_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
+                      const PtrsI64 &y, hipStream_t s);
 
 // Checksum method.
 void launch_checksum(int M, int64_t n, const PtrsI32 &c, int64_t *rsum, hipStream_t s);

@@ -202,15 +202,49 @@ __global__ __launch_bounds__(kBlock) void k_scale(Ptrs x, PtrsI64 y, int64_t n, 
         ys[i] = (int64_t)((uint64_t)widen(xs[i]) * (uint64_t)sv);
 }
 
-// y = x + g (mod 2^64)
-template <typename Ptrs, typename G>
+// y = x + g, or x - g with SUB (mod 2^64)
+template <typename Ptrs, typename G, bool SUB = false>
 __global__ __launch_bounds__(kBlock) void k_add(Ptrs x, const G *g, PtrsI64 y, int64_t n)
 {
     const auto *xs = x.p[blockIdx.y];
     int64_t *ys = y.p[blockIdx.y];
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const uint64_t gv = (uint64_t)widen(g[i]);
+        ys[i] = (int64_t)((uint64_t)widen(xs[i]) + (SUB ? (uint64_t)0 - gv : gv));
+    }
+}
+
+// y = x * g element by element (mod 2^64)
+template <typename Ptrs>
+__global__ __launch_bounds__(kBlock) void k_mul(Ptrs x, const int32_t *g, PtrsI64 y, int64_t n)
+{
+    const auto *xs = x.p[blockIdx.y];
+    int64_t *ys = y.p[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock)
-        ys[i] = (int64_t)((uint64_t)widen(xs[i]) + (uint64_t)widen(g[i]));
+        ys[i] = (int64_t)((uint64_t)widen(xs[i]) * (uint64_t)(int64_t)g[i]);
+}
+
+// y[i K + j] = x[i] g[j] (mod 2^64): block rows of kOuterRows inputs, the
+// lanes of a block walk j, so the stores of one row are consecutive.
+constexpr int kOuterRows = 16;
+
+template <typename Ptrs>
+__global__ __launch_bounds__(kBlock) void k_outer(Ptrs x, const int32_t *g, PtrsI64 y, int64_t n,
+                                                  int64_t K)
+{
+    const auto *xs = x.p[blockIdx.y];
+    int64_t *ys = y.p[blockIdx.y];
+    for (int64_t i0 = (int64_t)blockIdx.x * kOuterRows; i0 < n;
+         i0 += (int64_t)gridDim.x * kOuterRows) {
+        const int64_t i1 = i0 + kOuterRows < n ? i0 + kOuterRows : n;
+        for (int64_t i = i0; i < i1; ++i) {
+            const uint64_t xi = (uint64_t)widen(xs[i]);
+            for (int64_t j = threadIdx.x; j < K; j += kBlock)
+                ys[i * K + j] = (int64_t)(xi * (uint64_t)(int64_t)g[j]);
+        }
+    }
 }
 
 // y[i] = x[p[i]] (gather); an index outside [0, n) is clamped so that a bad
@@ -373,6 +407,27 @@ void launch_add_i64(int count, int64_t n, const PtrsCI64 &x, const int64_t *g, c
                        dim3(kBlock), 0, s, x, g, y, n);
 }
 
+void launch_sub_i64(int count, int64_t n, const PtrsCI64 &x, const int64_t *g, const PtrsI64 &y,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL((k_add<PtrsCI64, int64_t, true>), dim3(grid_for(n, kBlock, 4096), count),
+                       dim3(kBlock), 0, s, x, g, y, n);
+}
+
+void launch_mul_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mul<PtrsCI64>, dim3(grid_for(n, kBlock, 4096), count), dim3(kBlock), 0, s,
+                       x, g, y, n);
+}
+
+void launch_outer_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
+                      const PtrsI64 &y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_outer<PtrsCI64>, dim3(grid_for(n, kOuterRows, 4096), count), dim3(kBlock),
+                       0, s, x, g, y, n, K);
+}
+
 void launch_perm_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *p, const PtrsI64 &y,
                      hipStream_t s)
 {
@@ -400,6 +455,27 @@ void launch_add_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, co
 {
     hipLaunchKernelGGL((k_add<PtrsI32, int32_t>), dim3(grid_for(n, kBlock, 4096), count),
                        dim3(kBlock), 0, s, x, g, y, n);
+}
+
+void launch_sub_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL((k_add<PtrsI32, int32_t, true>), dim3(grid_for(n, kBlock, 4096), count),
+                       dim3(kBlock), 0, s, x, g, y, n);
+}
+
+void launch_mul_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mul<PtrsI32>, dim3(grid_for(n, kBlock, 4096), count), dim3(kBlock), 0, s,
+                       x, g, y, n);
+}
+
+void launch_outer_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
+                      const PtrsI64 &y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_outer<PtrsI32>, dim3(grid_for(n, kOuterRows, 4096), count), dim3(kBlock),
+                       0, s, x, g, y, n, K);
 }
 
 void launch_perm_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *p, const PtrsI64 &y,

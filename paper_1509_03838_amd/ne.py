@@ -17,7 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("NE_LIB") or os.path.join(HERE, "libne.so")
 
 CONV, SCALE, ADD, INNER, PERM = 0, 1, 2, 3, 4
-OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM}
+SUB, MUL, CIRC, XCORR, OUTER = 5, 6, 7, 8, 9
+OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM,
+       "sub": SUB, "mul": MUL, "circ": CIRC, "xcorr": XCORR, "outer": OUTER}
 MAX_M = 32
 
 EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_entangle",
@@ -192,10 +194,12 @@ def entangle_operand(g, g_ent, l: int, stream=None):
 
 
 def n_out(op: str, n_in: int, n_operand: int) -> int:
-    if op == "conv":
+    if op in ("conv", "xcorr"):
         return 0 if n_in == 0 else n_in + n_operand - 1
     if op == "inner":
         return 1
+    if op == "outer":
+        return n_in * n_operand
     return n_in
 
 

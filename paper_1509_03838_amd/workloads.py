@@ -154,17 +154,20 @@ def chain_series(g: np.random.Generator, n: int, recipe=CHAIN_RECIPE, bits: int 
                  K: int = 64) -> list[tuple[str, np.ndarray | None, int]]:
     """Operands of a series of operations on streams of n samples: for each
     op of the recipe, (op, operand, scalar) with the operand drawn uniform
-    in [-2^(bits-1), 2^(bits-1)) (conv: K taps; add, inner: a vector of the
-    current length), a seeded permutation of the current length, or a scale
-    factor in the same range (nonzero). An inner product makes the length 1
-    for the ops after it."""
+    in [-2^(bits-1), 2^(bits-1)) (conv, circ, xcorr: K taps; outer: K
+    values; add, sub, mul, inner: a vector of the current length), a seeded
+    permutation of the current length, or a scale factor in the same range
+    (nonzero). The length after each op follows it (inner: 1; outer: n K)."""
     lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
     out = []
     for op in recipe:
-        if op == "conv":
+        if op in ("conv", "xcorr"):
             out.append((op, uniform_i32(g, lo, hi, K), 0))
             n = n + K - 1 if n else 0
-        elif op in ("add", "inner"):
+        elif op in ("circ", "outer"):
+            out.append((op, uniform_i32(g, lo, hi, K), 0))
+            n = n * K if op == "outer" else n
+        elif op in ("add", "inner", "sub", "mul"):
             out.append((op, uniform_i32(g, lo, hi, n), 0))
             n = 1 if op == "inner" else n
         elif op == "perm":

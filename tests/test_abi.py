@@ -95,7 +95,7 @@ def test_validation_before_launch(lib):
     # inner: n_out must be 1
     assert lib.ne_lsb_apply(3, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -1
     # unknown op
-    assert lib.ne_lsb_apply(9, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -4
+    assert lib.ne_lsb_apply(10, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -4
     # a NULL output for a stream that is computed
     assert lib.ne_lsb_apply(1, 3, 10, p3, 0, 0, 2, _ptrs([FAKE, 0, FAKE]), 10, 7, None) == -1
     # checksum recovery: bad index
@@ -270,7 +270,7 @@ def test_series_bound_against_d():
     ([("conv", 5, 0, 0)], -1),                   # operand bits missing
     ([("conv", 5, 0, 33)], -1),                  # operand bits above 32
     ([("perm", 100, 0, 0), ("inner", 100, 0, 8), ("add", 100, 0, 8)], -1),  # length 1 after inner
-    ([(9, 0, 0, 0)], -4),                        # unknown operation
+    ([(10, 0, 0, 0)], -4),                       # unknown operation
 ])
 def test_series_validation(ops, status):
     L = ne.load()

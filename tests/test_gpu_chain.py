@@ -14,7 +14,8 @@ DEV = "cuda:0"
 POISON = -0x5A5A5A5A5A5A5A5A
 
 SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
-          ("perm", "add", "conv", "inner"), ("add",), ("inner", "conv", "add")]
+          ("perm", "add", "conv", "inner"), ("add",), ("inner", "conv", "add"),
+          ("sub", "mul", "circ", "xcorr"), ("outer", "sub", "perm")]
 
 
 def dev32(a):
@@ -35,7 +36,7 @@ def device_ops(ops, l, bits, entangled=True):
             out.append(ne.ChainOp(op, None, s))
             continue
         dg = dev32(g)
-        if op == "add":
+        if op in ("add", "sub"):
             if entangled:
                 ge = torch.empty(max(g.size, 1), dtype=torch.int64, device=DEV)[:g.size]
                 ne.entangle_operand(dg, ge, l)

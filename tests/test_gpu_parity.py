@@ -43,9 +43,9 @@ def gpu_pipeline(grp, r=-1, poison=True, inplace=False):
     eps = empty64(M, n)
     ne.entangle(c, eps, l)
     operand = None
-    if grp.op in ("conv", "inner", "perm"):
+    if grp.op in ("conv", "inner", "perm", "mul", "circ", "xcorr", "outer"):
         operand = dev(grp.operand, torch.int32)
-    elif grp.op == "add":
+    elif grp.op in ("add", "sub"):
         g32 = dev(grp.operand, torch.int32)
         operand = torch.empty(n, dtype=torch.int64, device=DEV)
         ne.entangle_operand(g32, operand, l)
@@ -295,3 +295,45 @@ def test_checksum_method_matches_oracle():
         dr = torch.empty(n + K - 1, dtype=torch.int64, device=DEV)
         ne.checksum_recover([None if j == r else t for j, t in enumerate(d)], e[0], r, dr)
         assert np.array_equal(host(dr), plain[r])
+
+
+# ------------------------------------------- the other operators of eq. (2)
+
+@pytest.mark.parametrize("op", ["sub", "mul", "circ", "xcorr", "outer"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_pipeline_more_ops(op, M):
+    """Subtraction (operand entangled like addition), element-by-element
+    product, circular convolution (taps longer than the stream: they wrap),
+    cross-correlation and outer product through entangle -> op -> extract,
+    every loss, bit-exact against the oracle."""
+    g = wl.rng(M * 57 + len(op))
+    n = 301 + M if op == "outer" else 3001 + M
+    c = wl.uniform_i32(g, -(1 << 9), 1 << 9, (M, n))
+    if op in ("sub", "mul"):
+        operand = wl.uniform_i32(g, -(1 << 9), 1 << 9, n)
+    elif op == "circ":
+        operand = wl.uniform_i32(g, -(1 << 9), 1 << 9, n + 77)
+    else:
+        operand = wl.uniform_i32(g, -(1 << 9), 1 << 9, 37)
+    grp = wl.Group(op, c, operand, 0)
+    plain = oracle.apply(op, c, operand)
+    for r in range(-1, M):
+        dhat, _ = gpu_pipeline(grp, r, inplace=(r % 2 == 1))
+        assert np.array_equal(dhat, plain), (op, M, r)
+
+
+@pytest.mark.parametrize("op", ["sub", "mul", "circ", "xcorr", "outer"])
+@pytest.mark.parametrize("n", [1, 5, 1000, 4097])
+def test_plain_more_ops(op, n):
+    """The failure-intolerant per-step calls of the same operators on raw
+    int32 streams (int32 operands throughout)."""
+    g = wl.rng(n + 13 * len(op))
+    M = 3
+    c = wl.uniform_i32(g, -(1 << 20), 1 << 20, (M, n))
+    K = 1 if n == 1 else 19
+    operand = wl.uniform_i32(g, -(1 << 10), 1 << 10, n if op in ("sub", "mul") else K)
+    no = ne.n_out(op, n, operand.size)
+    d = empty64(M, no, fill=POISON)
+    ne.plain_apply(op, streams(c, torch.int32), dev(operand, torch.int32), d)
+    got = np.stack([host(t) for t in d])
+    assert np.array_equal(got, oracle.apply(op, c, operand)), (op, n)
