@@ -72,7 +72,7 @@ typedef enum ne_op {
     NE_OP_INNER = 3, /* y[0] = sum_i x[i] g[i] (inner product) */
     NE_OP_PERM = 4,  /* y[i] = x[p[i]] for a fixed bijection p (footnote 2) */
     /* The other operators eq. (2) lists (per-step calls and series; the
-       batched executor runs NE_OP_CONV .. NE_OP_PERM): */
+       batched executor runs all of them but NE_OP_OUTER): */
     NE_OP_SUB = 5,   /* y[i] = x[i] - g[i] (element-wise subtraction) */
     NE_OP_MUL = 6,   /* y[i] = x[i] g[i] (element-by-element product) */
     NE_OP_CIRC = 7,  /* circular convolution of length n with K taps:
@@ -350,13 +350,14 @@ typedef enum ne_mode {
 
 /* One group: M streams of n int32 samples sharing one operand. */
 typedef struct ne_group {
-    int32_t op;          /* ne_op */
+    int32_t op;          /* ne_op: any but NE_OP_OUTER */
     int32_t M;           /* streams: 3..8 (entangled), 2..8 (checksum), 1..8 */
     int64_t n;           /* samples per stream (>= 0) */
-    int64_t n_operand;   /* K taps (conv), n (add, inner, perm), 0 (scale) */
+    int64_t n_operand;   /* K taps (conv, circ, xcorr), n (add, sub, mul, inner,
+                            perm), 0 (scale) */
     int64_t scalar;      /* scale factor (NE_OP_SCALE) */
     int32_t lost;        /* -1, or the stream whose operation is dropped */
-    int32_t in_bits;     /* 1..31 (conv) or 1..32: every sample and operand
+    int32_t in_bits;     /* 1..31 (conv, circ, xcorr) or 1..32: every sample and operand
                             value v satisfies -2^(in_bits-1) <= v < 2^(in_bits-1);
                             violations are flagged (NE_FLAG_INPUT_RANGE) */
     int32_t steps;       /* tile steps per block for this group (conv: 1024
@@ -378,9 +379,9 @@ typedef struct ne_group {
     const int32_t *operand;           /* device int32 taps / vector /
                                          permutation indices, 16-byte aligned;
                                          NULL for scale.
-                                         For add, the plain vector g (the
-                                         entangled mode entangles it itself,
-                                         footnote 3). */
+                                         For add and sub, the plain vector g
+                                         (the entangled mode entangles it
+                                         itself, footnote 3). */
     int64_t *out[NE_FUSED_MAX_M];     /* device outputs, n_out int64 each,
                                          16-byte aligned, disjoint */
 } ne_group;

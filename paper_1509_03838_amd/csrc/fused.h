@@ -54,7 +54,7 @@ struct GroupDev {
     int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv)
     int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
     int32_t skip;     // slot whose operation is not run (the lost stream), or -1
-    int32_t pad_;
+    int32_t kind;     // convolution kernel: 0 linear, 1 circular (length n), 2 cross-correlation
     int64_t n, K, n_out;
     int64_t scalar;
     // Inputs and outputs in slot order. Slot t of an entangled group is

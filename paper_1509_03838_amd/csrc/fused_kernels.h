@@ -213,18 +213,38 @@ struct Raw4 {
 template <int DM>
 __device__ __forceinline__ void load4(const GroupDev *G, int64_t p, int64_t n, Raw4<DM> &raw)
 {
-    const bool full = p >= 0 && p + 4 <= n;
+    if (p >= 0 && p + 4 <= n) {
 #pragma unroll
-    for (int m = 0; m < DM; ++m) {
-        if (full) {
+        for (int m = 0; m < DM; ++m) {
             const v4i v = load_in4(G->c[m] + p);
             raw.cv[m][0] = v.x; raw.cv[m][1] = v.y; raw.cv[m][2] = v.z; raw.cv[m][3] = v.w;
-        } else {
+        }
+        return;
+    }
+    // Edges of the stream: zeros outside [0, n), or, for a circular
+    // convolution, the window wrapped modulo n (one division per call).
+    int64_t idx[4];
+    bool ok[4];
+    if (G->kind == kConvCircular) {
+        int64_t i = p % n;
+        i = i < 0 ? i + n : i;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                raw.cv[m][q] = (p + q >= 0 && p + q < n) ? load_in1(G->c[m] + p + q) : 0;
+        for (int q = 0; q < 4; ++q) {
+            idx[q] = i;
+            ok[q] = true;
+            i = i + 1 == n ? 0 : i + 1;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            idx[q] = p + q;
+            ok[q] = p + q >= 0 && p + q < n;
         }
     }
+#pragma unroll
+    for (int m = 0; m < DM; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) raw.cv[m][q] = ok[q] ? load_in1(G->c[m] + idx[q]) : 0;
 }
 
 // Converts raw inputs of 4 positions into the LA digit planes (one per slot,
@@ -351,9 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     {
         constexpr uint64_t CB = digit_offset<LB>();
         const int vlen = 64 * nch + 16;
+        const bool xcorr = G->kind == kConvXcorr;  // cross-correlation: the taps reversed
         for (int v = tid; v < vlen; v += kBlock) {
             const int64_t idx = (int64_t)kp + 15 - v;
-            const int32_t gv = (idx >= 0 && idx < K) ? g[idx] : 0;
+            const int32_t gv = (idx >= 0 && idx < K) ? g[xcorr ? K - 1 - idx : idx] : 0;
             bd.add(gv);
             const uint64_t u = (uint64_t)(int64_t)gv + CB;
 #pragma unroll
@@ -878,7 +899,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
                     for (int v = 0; v < V; ++v) prev0[v] = cv[t][v];
         }
-        if (op == NE_OP_ADD || op == NE_OP_INNER) {
+        if (op == NE_OP_ADD || op == NE_OP_SUB || op == NE_OP_MUL || op == NE_OP_INNER) {
             if (full) {
                 load_vec<V>(opd + p, gv);
             } else {
@@ -909,6 +930,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
                 switch (op) {
                 case NE_OP_SCALE: y = (uint64_t)x * (uint64_t)sv; break;
                 case NE_OP_ADD: y = (uint64_t)x + (uint64_t)gs; break;
+                case NE_OP_SUB: y = (uint64_t)x - (uint64_t)gs; break;
+                case NE_OP_MUL: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
                 case NE_OP_INNER: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
                 default: y = (uint64_t)x; break;  // permutation: the gather above
                 }

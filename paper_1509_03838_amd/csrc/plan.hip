@@ -140,7 +140,9 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         if (u.reserved != 0) return fail(NE_EINVAL);
         const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
         const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
-        if (u.op < NE_OP_CONV || u.op > NE_OP_PERM) return fail(NE_EUNSUP);
+        // every operator but the outer product (whose output is n K long)
+        if (u.op < NE_OP_CONV || u.op > NE_OP_XCORR) return fail(NE_EUNSUP);
+        const bool convlike = u.op == NE_OP_CONV || u.op == NE_OP_CIRC || u.op == NE_OP_XCORR;
         for (int m = 0; m < u.M; ++m) {
             if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 16))
                 return fail(NE_EINVAL);
@@ -148,14 +150,17 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         int64_t n_out;
         switch (u.op) {
         case NE_OP_CONV:
+        case NE_OP_XCORR:
+        case NE_OP_CIRC:
             if (u.n_operand < 1 || !u.operand || u.in_bits > 31) return fail(NE_EINVAL);
-            n_out = u.n == 0 ? 0 : u.n + u.n_operand - 1;
+            n_out = u.op == NE_OP_CIRC ? u.n : (u.n == 0 ? 0 : u.n + u.n_operand - 1);
             break;
         case NE_OP_SCALE: n_out = u.n; break;
         case NE_OP_INNER: n_out = 1; break;
         default: n_out = u.n; break;
         }
-        if (u.op == NE_OP_ADD || u.op == NE_OP_INNER || u.op == NE_OP_PERM) {
+        if (u.op == NE_OP_ADD || u.op == NE_OP_SUB || u.op == NE_OP_MUL || u.op == NE_OP_INNER ||
+            u.op == NE_OP_PERM) {
             if (u.n_operand != u.n || (u.n > 0 && !u.operand)) return fail(NE_EINVAL);
         }
         if (u.operand && !aligned(u.operand, 16)) return fail(NE_EINVAL);
@@ -167,9 +172,13 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         const unsigned __int128 s_abs =
             (unsigned __int128)(u.scalar < 0 ? -(__int128)u.scalar : (__int128)u.scalar);
         switch (u.op) {
-        case NE_OP_CONV: bound = B * B * (unsigned __int128)u.n_operand; break;
+        case NE_OP_CONV:
+        case NE_OP_CIRC:
+        case NE_OP_XCORR: bound = B * B * (unsigned __int128)u.n_operand; break;
         case NE_OP_SCALE: bound = B * s_abs; break;
-        case NE_OP_ADD: bound = 2 * B; break;
+        case NE_OP_ADD:
+        case NE_OP_SUB: bound = 2 * B; break;
+        case NE_OP_MUL: bound = B * B; break;
         case NE_OP_INNER: bound = B * B * (unsigned __int128)(u.n > 0 ? u.n : 1); break;
         case NE_OP_PERM: bound = B; break;
         }
@@ -196,7 +205,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         G.in_lo = u.in_bits == 32 ? INT32_MIN : -(int32_t)((int64_t)1 << (u.in_bits - 1));
         G.in_hi = u.in_bits == 32 ? INT32_MAX : (int32_t)(((int64_t)1 << (u.in_bits - 1)) - 1);
         G.n = u.n;
-        G.K = u.op == NE_OP_CONV ? u.n_operand : 0;
+        G.K = convlike ? u.n_operand : 0;
+        G.kind = u.op == NE_OP_CIRC ? kConvCircular : (u.op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
         G.n_out = n_out;
         G.scalar = u.scalar;
         G.skip = G.lost ? (mode == kEntangled ? u.M - 1 : G.r) : -1;
@@ -212,11 +222,12 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         st.in_bytes += (int64_t)u.M * u.n * 4 + (u.op == NE_OP_SCALE ? 0 : u.n_operand * 4);
         st.out_bytes += (int64_t)u.M * n_out * 8;
         st.out_samples += (int64_t)u.M * n_out;
-        if (u.op == NE_OP_CONV) st.macs += (int64_t)u.M * u.n * u.n_operand;
+        if (convlike) st.macs += (int64_t)u.M * (u.op == NE_OP_CIRC ? n_out : u.n) * u.n_operand;
+        if (u.op == NE_OP_MUL) st.macs += (int64_t)u.M * u.n;
         if (u.op == NE_OP_INNER) st.macs += (int64_t)u.M * u.n;
 
         if (n_out == 0) continue;
-        if (u.op == NE_OP_CONV) {
+        if (convlike) {
             const DigitCounts dc = conv_digits(mode, u.M, u.in_bits);
             const int la = dc.la, lb = dc.lb;
             if (la > kLimbsA || lb > kLimbsB) return fail(NE_EUNSUP);

@@ -226,23 +226,28 @@ __global__ __launch_bounds__(kBlock) void k_mul(Ptrs x, const int32_t *g, PtrsI6
         ys[i] = (int64_t)((uint64_t)widen(xs[i]) * (uint64_t)(int64_t)g[i]);
 }
 
-// y[i K + j] = x[i] g[j] (mod 2^64): block rows of kOuterRows inputs, the
-// lanes of a block walk j, so the stores of one row are consecutive.
-constexpr int kOuterRows = 16;
-
+// y[i K + j] = x[i] g[j] (mod 2^64). Every lane owns one output index at a
+// time (consecutive lanes, consecutive outputs: coalesced stores); the row
+// i = idx / K and column j advance incrementally, so the loop divides only
+// once per lane.
 template <typename Ptrs>
 __global__ __launch_bounds__(kBlock) void k_outer(Ptrs x, const int32_t *g, PtrsI64 y, int64_t n,
                                                   int64_t K)
 {
     const auto *xs = x.p[blockIdx.y];
     int64_t *ys = y.p[blockIdx.y];
-    for (int64_t i0 = (int64_t)blockIdx.x * kOuterRows; i0 < n;
-         i0 += (int64_t)gridDim.x * kOuterRows) {
-        const int64_t i1 = i0 + kOuterRows < n ? i0 + kOuterRows : n;
-        for (int64_t i = i0; i < i1; ++i) {
-            const uint64_t xi = (uint64_t)widen(xs[i]);
-            for (int64_t j = threadIdx.x; j < K; j += kBlock)
-                ys[i * K + j] = (int64_t)(xi * (uint64_t)(int64_t)g[j]);
+    const int64_t total = n * K, step = (int64_t)gridDim.x * kBlock;
+    int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= total) return;
+    int64_t i = idx / K, j = idx - i * K;
+    const int64_t di = step / K, dj = step - di * K;
+    for (; idx < total; idx += step) {
+        ys[idx] = (int64_t)((uint64_t)widen(xs[i]) * (uint64_t)(int64_t)g[j]);
+        i += di;
+        j += dj;
+        if (j >= K) {
+            j -= K;
+            ++i;
         }
     }
 }
@@ -424,7 +429,7 @@ void launch_mul_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, c
 void launch_outer_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
                       const PtrsI64 &y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_outer<PtrsCI64>, dim3(grid_for(n, kOuterRows, 4096), count), dim3(kBlock),
+    hipLaunchKernelGGL(k_outer<PtrsCI64>, dim3(grid_for(n * K, kBlock, 4096), count), dim3(kBlock),
                        0, s, x, g, y, n, K);
 }
 
@@ -474,7 +479,7 @@ void launch_mul_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, co
 void launch_outer_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
                       const PtrsI64 &y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_outer<PtrsI32>, dim3(grid_for(n, kOuterRows, 4096), count), dim3(kBlock),
+    hipLaunchKernelGGL(k_outer<PtrsI32>, dim3(grid_for(n * K, kBlock, 4096), count), dim3(kBlock),
                        0, s, x, g, y, n, K);
 }
 

@@ -24,6 +24,7 @@ from typing import Sequence
 
 from . import ne
 
+CONV_LIKE = ("conv", "circ", "xcorr")  # operations that run on the convolution kernel
 CONV_CANDIDATES = tuple((st, rw) for st in (1, 2, 4, 8, 16) for rw in (4, 1))
 STREAM_CANDIDATES = tuple((st, 0) for st in (1, 2, 4, 8))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ne_tune.json")
@@ -36,7 +37,7 @@ def _bucket(x: int) -> int:
 def class_key(spec: ne.GroupSpec, mode: str) -> str:
     n = spec.c[0].numel() if spec.c else 0
     nb = _bucket(n) // 2
-    if spec.op == "conv":
+    if spec.op in CONV_LIKE:
         K = spec.operand.numel() if spec.operand is not None else 0
         return f"{mode}|conv|M{len(spec.c)}|b{spec.in_bits}|K{_bucket(K)}|n{nb}"
     return f"{mode}|{spec.op}|M{'<=4' if len(spec.c) <= 4 else '>4'}|n{nb}"
@@ -121,7 +122,7 @@ class Tuner:
                 reps.append(sp)
                 work += len(sp.c) * sp.c[0].numel()
             saved = [(s.steps, s.ring_waves) for s in reps]
-            cands = CONV_CANDIDATES if reps[0].op == "conv" else STREAM_CANDIDATES
+            cands = CONV_CANDIDATES if reps[0].op in CONV_LIKE else STREAM_CANDIDATES
             # every candidate timed in `rounds` interleaved passes; the best
             # pass counts (a slow pass is noise, a fast one is not)
             times = {c: float("inf") for c in cands}

@@ -127,7 +127,8 @@ def _group(**kw):
     ({"M": 2}, -1),                      # entangled needs M >= 3
     ({"M": 9}, -1),                      # above the fused limit
     ({"lost": 3}, -3),                   # failed index out of range
-    ({"op": 7}, -4),                     # unknown operation
+    ({"op": 9}, -4),                     # the outer product: per-step calls only
+    ({"op": 10}, -4),                    # unknown operation
     ({"n_operand": 0}, -1),              # convolution without taps
     ({"in_bits": 32}, -1),               # 32-bit convolution operands
     ({"in_bits": 31, "n_operand": 1 << 20}, -2),  # worst case above D

@@ -278,3 +278,91 @@ def test_sparse_top_tap_digit_windows(ring_waves, tap_copies):
             _, flags = run([dg], conv_steps=2)
             assert flags == 0
             assert np.array_equal(dg.result(), ref), (pos, lost)
+
+
+# ------------------------------------- the other operators in the fused path
+
+def make_more(op, M, n, K, bits, seed):
+    """Subtraction and product take a vector of n values, circular
+    convolution and cross-correlation K taps."""
+    g = wl.rng(seed)
+    lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+    c = wl.uniform_i32(g, lo, hi, (M, n))
+    operand = wl.uniform_i32(g, lo, hi, K if op in ("circ", "xcorr") else n)
+    return wl.Group(op, c, operand, 0)
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("op", ["sub", "mul"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_more_streaming_ops_fused(mode, op, M):
+    """Subtraction (operand entangled on the fly, footnote 3; M g for the
+    checksum stream) and element-by-element product in the element-wise
+    fused kernel, ragged lengths, every mode and loss position."""
+    for n in (1, 255, 4097, 70001):
+        grp = make_more(op, M, n, 0, 10, seed=n * 17 + M + len(op))
+        ref = oracle.apply(op, grp.c, grp.operand)
+        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+        for lost in losses:
+            dg = DevGroup(grp, 10, lost, mode)
+            _, flags = run([dg], mode)
+            assert flags == 0
+            assert np.array_equal(dg.result(), ref), (mode, op, M, n, lost)
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("op", ["circ", "xcorr"])
+@pytest.mark.parametrize("M", [3, 8])
+@pytest.mark.parametrize("n,K,bits", [(1, 1, 8), (5, 3, 12), (3001, 37, 12), (700, 1500, 10),
+                                      (2049, 1024, 16)])
+def test_circular_and_cross_correlation_fused(mode, op, M, n, K, bits):
+    """The convolution kernel with the window wrapped modulo n (taps longer
+    than the stream wrap more than once) or with the taps reversed, in every
+    LDS layout, every mode and loss position."""
+    grp = make_more(op, M, n, K, bits, seed=M * 1000 + n + K + len(op))
+    ref = oracle.apply(op, grp.c, grp.operand)
+    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+    for lost in losses:
+        for rw, tc in ((4, 4), (1, 0), (4, 1)):
+            dg = DevGroup(grp, bits, lost, mode, ring_waves=rw, tap_copies=tc)
+            try:
+                _, flags = run([dg], mode, conv_steps=3)
+            except ne.NeError as e:
+                assert e.status == -4 and rw == 1, (mode, M, K, rw, e)  # windows too large for LDS
+                continue
+            assert flags == 0, (mode, op, lost, flags, rw, tc)
+            assert np.array_equal(dg.result(), ref), (mode, op, M, n, K, lost, rw, tc)
+
+
+def test_all_fused_operators_in_one_captured_plan():
+    """Groups of all nine fused operators with uneven M, lengths and losses
+    in one plan, captured as a graph and replayed twice with eager work in
+    between: every replay matches the oracle."""
+    rng = wl.rng(4242)
+    specs = []
+    for i, op in enumerate(["conv", "scale", "add", "inner", "perm", "sub", "mul", "circ",
+                            "xcorr"] * 3):
+        M = int(rng.integers(3, 9))
+        n = int(rng.integers(1, 20000))
+        if op in ("conv", "circ", "xcorr"):
+            grp = make_more("circ", M, n, int(rng.integers(1, 300)), 10, seed=5000 + i)
+            grp = wl.Group(op, grp.c, grp.operand, 0)
+        elif op in ("sub", "mul"):
+            grp = make_more(op, M, n, 0, 10, seed=5000 + i)
+        else:
+            grp = make(op, M, n, 0, 10, seed=5000 + i)
+        specs.append((grp, DevGroup(grp, 10, int(rng.integers(-1, M)))))
+    plan = ne.Plan([d.spec for _, d in specs], "entangled")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(s)
+        for rep in range(2):
+            for _, d in specs:
+                for o in d.out:
+                    o.fill_(POISON)
+            plan.launch(s)
+            s.synchronize()
+            assert plan.flags() == 0
+            for grp, d in specs:
+                assert np.array_equal(d.result(), d.reference()), (grp.op, grp.M, grp.n, rep)
+    plan.close()
