@@ -580,7 +580,8 @@ def ops_line(args, wl):
     subtraction, element-by-element product, circular convolution (64 taps),
     cross-correlation (64 taps) and outer product (8 values), 3 streams of
     2^22 samples in [-2^9, 2^9) through entangle -> op -> extract, against
-    the plain op on the raw streams."""
+    the plain op on the raw streams; and, for all but the outer product, the
+    same operation in the fused executor (one pass, one captured launch)."""
     import numpy as np
     import torch
     from paper_1509_03838_amd import ne
@@ -633,6 +634,18 @@ def ops_line(args, wl):
         t_ent = timed(ent)
         if not torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref):
             raise SystemExit(f"ops: {op} entangled and plain results differ")
+        fused = {}
+        if op != "outer":
+            # the same operation in the fused executor: one pass, one captured launch
+            for mode in ("entangled", "plain"):
+                spec = ne.GroupSpec(op, cd, g32, dhat, 0, -1, bits)
+                plan = ne.Plan([spec], mode)
+                plan.capture(stream)
+                fused[mode], _ = time_captured(torch, plan, stream, args.steps, args.warmup)
+                same = torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref)
+                if plan.flags() or not same:
+                    raise SystemExit(f"ops: fused {op} ({mode}) differs from the per-step result")
+                plan.close()
         # algorithmic HBM bytes of the three launches: entangle, op, extract
         nb = (M * n * 12 + M * (n + no) * 8 + operand.numel() * operand.element_size() +
               (2 * M - 1) * no * 8)
@@ -640,11 +653,16 @@ def ops_line(args, wl):
                     "gout_per_s": round(M * no / (t_ent * 1e-3) / 1e9, 3),
                     "hbm_GBps": round(nb / (t_ent * 1e-3) / 1e9, 1),
                     "overhead_pct_vs_plain": round(100 * (t_ent / t_plain - 1), 2)}
+        if fused:
+            fb = M * n * 4 + g32.numel() * 4 + M * no * 8  # one pass: inputs in, outputs out
+            rows[op]["fused_ms"] = {k: round(v, 4) for k, v in fused.items()}
+            rows[op]["fused_gout_per_s"] = round(M * no / (fused["entangled"] * 1e-3) / 1e9, 3)
+            rows[op]["fused_hbm_GBps"] = round(fb / (fused["entangled"] * 1e-3) / 1e9, 1)
         tot_samples += M * no
         tot_ms += t_ent
         tot_bytes += nb
-        print(f"# ops {op}: entangled {t_ent:.4f} ms, plain {t_plain:.4f} ms", file=sys.stderr,
-              flush=True)
+        print(f"# ops {op}: per-step entangled {t_ent:.4f} ms, plain {t_plain:.4f} ms; fused "
+              + ", ".join(f"{k} {v:.4f} ms" for k, v in fused.items()), file=sys.stderr, flush=True)
         del delta, dhat
     line = {
         "metric": METRIC, "value": round(tot_samples / (tot_ms * 1e-3) / 1e9, 3),
