@@ -299,17 +299,31 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
  * in_bits in [1, 16]; values outside are flagged (NE_FLAG_INPUT_RANGE).
  * lost: -1, or the block whose product is not computed (its output is
  * recovered; plain modes leave it unwritten). flags: device word OR-ed with
- * NE_FLAG_* bits (NULL: not reported). One launch on `stream`, no
- * allocation.
+ * NE_FLAG_* bits (NULL: not reported). No allocation; launches on `stream`
+ * only.
+ * workspace: NULL runs one fused launch (digits split in LDS inside the
+ * product kernel); otherwise device memory of ne_gemm_workspace_size bytes,
+ * 256-byte aligned, owned by the caller: the digit planes of every block's
+ * (entangled) values and of G are written there once, then the product
+ * kernel reads its matrix-core fragments straight from them (three
+ * launches, no staging in the product loop; faster for large products).
  * Errors: NE_EINVAL (mode, M, negative sizes, NULL pointers of non-empty
- * matrices), NE_EFAILIDX (lost), NE_ERANGE (P 2^(2 in_bits - 2) above D of
+ * matrices, a short or misaligned workspace), NE_EFAILIDX (lost), NE_ERANGE (P 2^(2 in_bits - 2) above D of
  * ne_params(M, 64) for the method, above 2^63 - 1 otherwise), NE_EUNSUP
  * (in_bits above 16, N above 32 * 65535, Q above 2^26, P above 2^24, or an
  * inner dimension too long for exact 32-bit digit sums).
  */
 ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q,
                   const int32_t *const *c, const int32_t *g, int64_t *const *out, int32_t lost,
-                  int32_t in_bits, uint32_t *flags, ne_stream stream);
+                  int32_t in_bits, void *workspace, size_t workspace_bytes, uint32_t *flags,
+                  ne_stream stream);
+
+/*
+ * Workspace bytes of ne_gemm's two-phase form for these arguments (0 when
+ * there is no output). Host-only; errors as ne_gemm's argument checks.
+ */
+ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q,
+                                 int32_t in_bits, size_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Batched executor: many groups (uneven M, length, operation and operand

@@ -25,8 +25,35 @@ __host__ __device__ constexpr size_t gemm_lds(int slots, int la, int lb)
     return (size_t)(slots * la + lb) * kGemmTile * kGemmRow;
 }
 
+// Two-phase path: the digit planes of every slot's C values and of G are
+// written once to caller workspace, then a matrix-core kernel reads its
+// fragments straight from them (no staging, no barriers). Each wave owns
+// 16 rows x 32 columns; a block (2 x 2 waves) 32 rows x 64 columns.
+constexpr int kGemmSplitRows = 32, kGemmSplitCols = 64;
+
+struct GemmSplit {
+    int64_t Np, Pp, Qp;  // N, P, Q rounded up to the block rows, 64 and the block columns
+    unsigned char *a;    // slots x LA planes of Np x Pp digit bytes ([slot][digit][row][k])
+    unsigned char *b;    // LB planes of Qp x Pp digit bytes ([digit][column][k])
+};
+
+inline int64_t gemm_round(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Workspace bytes of the two-phase path (256-byte aligned pieces).
+inline size_t gemm_split_bytes(int slots, int la, int lb, int64_t N, int64_t P, int64_t Q)
+{
+    const size_t Np = gemm_round(N, kGemmSplitRows), Pp = gemm_round(P, kGemmK),
+                 Qp = gemm_round(Q, kGemmSplitCols);
+    return (size_t)gemm_round((int64_t)(slots * la * Np * Pp), 256) + (size_t)lb * Qp * Pp;
+}
+
 using GemmLaunch = hipError_t (*)(const GemmArgs &a, hipStream_t s);
+using GemmSplitLaunch = hipError_t (*)(const GemmArgs &a, const GemmSplit &w, hipStream_t s);
+struct GemmKernel {
+    GemmLaunch fused;       // one pass, digits staged in LDS
+    GemmSplitLaunch split;  // two phases through workspace
+};
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
-GemmLaunch gemm_kernel(int kclass, int slots, int la, int lb);
+const GemmKernel *gemm_kernel(int kclass, int slots, int la, int lb);
 
 }  // namespace ne

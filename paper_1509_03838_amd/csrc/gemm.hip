@@ -8,11 +8,11 @@
 #include "ne_internal.h"
 
 namespace ne {
-GemmLaunch gemm_kernel_0(int slots, int la, int lb);
-GemmLaunch gemm_kernel_1(int slots, int la, int lb);
-GemmLaunch gemm_kernel_2(int slots, int la, int lb);
+const GemmKernel *gemm_kernel_0(int slots, int la, int lb);
+const GemmKernel *gemm_kernel_1(int slots, int la, int lb);
+const GemmKernel *gemm_kernel_2(int slots, int la, int lb);
 
-GemmLaunch gemm_kernel(int kclass, int slots, int la, int lb)
+const GemmKernel *gemm_kernel(int kclass, int slots, int la, int lb)
 {
     switch (kclass) {
     case 0: return gemm_kernel_0(slots, la, lb);
@@ -25,18 +25,47 @@ GemmLaunch gemm_kernel(int kclass, int slots, int la, int lb)
 
 using namespace ne;
 
-extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q,
-                             const int32_t *const *c, const int32_t *g, int64_t *const *out,
-                             int32_t lost, int32_t in_bits, uint32_t *flags, ne_stream stream)
+namespace {
+
+// Argument checks and digit counts shared by the size query and the call.
+ne_status gemm_shape(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q, int32_t in_bits,
+                     DigitCounts *dc)
 {
     if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
     const int minM = mode == kEntangled ? 3 : (mode == kChecksum ? 2 : 1);
-    if (M < minM || M > kFusedMaxM || N < 0 || P < 0 || Q < 0 || !c || !out) return NE_EINVAL;
+    if (M < minM || M > kFusedMaxM || N < 0 || P < 0 || Q < 0) return NE_EINVAL;
     if (in_bits < 1 || in_bits > 32) return NE_EINVAL;
-    if (lost < -1 || lost >= M) return NE_EFAILIDX;
     if (in_bits > kGemmMaxBits) return NE_EUNSUP;
     if (N > (int64_t)kGemmTile * 65535 || Q > ((int64_t)1 << 26) || P > ((int64_t)1 << 24))
         return NE_EUNSUP;
+    *dc = conv_digits(mode, M, in_bits);
+    return NE_OK;
+}
+
+}  // namespace
+
+extern "C" ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, int64_t P,
+                                            int64_t Q, int32_t in_bits, size_t *bytes)
+{
+    if (!bytes) return NE_EINVAL;
+    DigitCounts dc{};
+    const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc);
+    if (st != NE_OK) return st;
+    const int nslots = mode == kChecksum ? M + 1 : M;
+    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q);
+    return NE_OK;
+}
+
+extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q,
+                             const int32_t *const *c, const int32_t *g, int64_t *const *out,
+                             int32_t lost, int32_t in_bits, void *workspace,
+                             size_t workspace_bytes, uint32_t *flags, ne_stream stream)
+{
+    DigitCounts dc0{};
+    const ne_status st0 = gemm_shape(mode, M, N, P, Q, in_bits, &dc0);
+    if (st0 != NE_OK) return st0;
+    if (!c || !out) return NE_EINVAL;
+    if (lost < -1 || lost >= M) return NE_EFAILIDX;
     if (N == 0 || Q == 0) return NE_OK;
     for (int m = 0; m < M; ++m)
         if ((!c[m] && P > 0) || !out[m]) return NE_EINVAL;
@@ -57,14 +86,16 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)M : bound;
         if (chk > (((unsigned __int128)1 << 63) - 1)) return NE_ERANGE;
     }
-    const DigitCounts dc = conv_digits(mode, M, in_bits);
+    const DigitCounts dc = dc0;
     // int32 accumulation: a digit product is at most 2^14, summed over the
     // padded inner dimension and at most min(la, lb) pairs per weight.
     const int64_t pp = (P + kGemmK - 1) / kGemmK * kGemmK;
     if (pp * std::min(dc.la, dc.lb) * 16384 >= ((int64_t)1 << 31)) return NE_EUNSUP;
     const int nslots = mode == kChecksum ? M + 1 : M;
-    const GemmLaunch launch = gemm_kernel(conv_class_of_mode(mode), nslots, dc.la, dc.lb);
-    if (!launch) return NE_EUNSUP;
+    const GemmKernel *kern = gemm_kernel(conv_class_of_mode(mode), nslots, dc.la, dc.lb);
+    if (!kern) return NE_EUNSUP;
+    const size_t need = gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q);
+    if (workspace && (workspace_bytes < need || (uintptr_t)workspace % 256)) return NE_EINVAL;
 
     GemmArgs a{};
     GroupDev &G = a.g;
@@ -93,6 +124,18 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
     a.Q = Q;
     a.flags = flags;
     a.vec = vec ? 1 : 0;
-    const hipError_t e = launch(a, (hipStream_t)stream);
+    hipError_t e;
+    if (workspace) {
+        GemmSplit w{};
+        w.Np = gemm_round(N, kGemmSplitRows);
+        w.Pp = gemm_round(P, kGemmK);
+        w.Qp = gemm_round(Q, kGemmSplitCols);
+        w.a = (unsigned char *)workspace;
+        w.b = w.a + gemm_round((int64_t)(nslots * dc.la * (size_t)w.Np * w.Pp), 256);
+        if (w.Qp / kGemmSplitCols > 0x7fffffff || w.Np / kGemmSplitRows > 65535) return NE_EUNSUP;
+        e = kern->split(a, w, (hipStream_t)stream);
+    } else {
+        e = kern->fused(a, (hipStream_t)stream);
+    }
     return e == hipSuccess ? NE_OK : hip_fail(e);
 }

@@ -52,7 +52,7 @@ __device__ __forceinline__ void load_row8(const int32_t *src, bool full, bool ve
 // 8 values into L digit planes: plane a receives the 8 digit bytes of
 // weight 256^a at dst + a * stride (two aligned words).
 template <int L>
-__device__ __forceinline__ void put_digits8(const int64_t (&x)[8], unsigned char *dst, int stride)
+__device__ __forceinline__ void put_digits8(const int64_t (&x)[8], unsigned char *dst, size_t stride)
 {
     constexpr uint64_t C = digit_offset<L>();
     uint32_t lo[8], hi[8];
@@ -217,9 +217,186 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
     if (flag && args.flags) atomicOr(args.flags, flag);
 }
 
+// ---------------------------------------------------------- two phases
+
+// Phase 1: the digit planes of every slot's value (entangled, plain, or the
+// checksum sum) for all Np x Pp positions (zero outside the matrix); the
+// lost slot's planes are not written (never read).
+template <int LA, int NS, int KCLASS>
+__global__ __launch_bounds__(kBlock) void k_gemm_split_a(const GemmArgs args, GemmSplit w)
+{
+    constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
+    constexpr int M = KCLASS == 2 ? NS - 1 : NS;
+    const GroupDev *G = &args.g;
+    const int64_t N = args.N, P = args.P, Pp = w.Pp;
+    const int skip = G->skip, l = G->l;
+    const bool vec = args.vec != 0;
+    const size_t plane = (size_t)w.Np * Pp;
+    const int64_t kgs = Pp / 8, total = w.Np * kgs;
+    Bounds bd;
+    for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * kBlock) {
+        const int64_t row = it / kgs, k0 = (it - row * kgs) * 8;
+        const bool row_ok = row < N;
+        const int64_t kleft = P - k0;
+        const bool full = kleft >= 8;
+        int32_t prev[8], cur[8], sum[8];
+        if (mode == kEntangled) load_row8(G->c[M - 1] + row * P + k0, full, vec, row_ok, kleft, prev);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sum[i] = 0;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            load_row8(G->c[t] + row * P + k0, full, vec, row_ok, kleft, cur);
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) bd.add2(cur[i], cur[i + 1]);
+            if (t != skip) {
+                int64_t x[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[i] = mode == kEntangled ? ent(cur[i], prev[i], l) : cur[i];
+                put_digits8<LA>(x, w.a + (size_t)t * LA * plane + row * Pp + k0, plane);
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sum[i] += cur[i];
+                prev[i] = cur[i];
+            }
+        }
+        if (mode == kChecksum) {
+            int64_t x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = sum[i];
+            put_digits8<LA>(x, w.a + (size_t)M * LA * plane + row * Pp + k0, plane);
+        }
+    }
+    if ((bd.lo < G->in_lo || bd.hi > G->in_hi) && args.flags) atomicOr(args.flags, kFlagInputRange);
+}
+
+// Phase 1: the digit planes of G, transposed ([digit][column][k]); lanes
+// take consecutive columns so that the reads of a row of G coalesce.
+template <int LB>
+__global__ __launch_bounds__(kBlock) void k_gemm_split_b(const GemmArgs args, GemmSplit w)
+{
+    const GroupDev *G = &args.g;
+    const int64_t P = args.P, Q = args.Q, Pp = w.Pp, Qp = w.Qp;
+    const size_t plane = (size_t)Qp * Pp;
+    const int64_t total = Qp * (Pp / 8);
+    Bounds bd;
+    for (int64_t it = (int64_t)blockIdx.x * kBlock + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * kBlock) {
+        const int64_t k0 = (it / Qp) * 8, col = it - (it / Qp) * Qp;
+        int64_t x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int32_t v = (col < Q && k0 + i < P) ? load_in1(G->operand + (k0 + i) * Q + col) : 0;
+            bd.add(v);
+            x[i] = v;
+        }
+        put_digits8<LB>(x, w.b + col * Pp + k0, plane);
+    }
+    if ((bd.lo < G->in_lo || bd.hi > G->in_hi) && args.flags) atomicOr(args.flags, kFlagInputRange);
+}
+
+typedef __attribute__((address_space(1))) const v4i gcv4i_t;
+
+// Phase 2: slot by slot, every digit pair of 16 x 64 A and 64 x 16 B
+// fragments read from the planes (16-byte global loads) into the
+// accumulator of its weight; each slot's tiles are recombined into 64-bit
+// words, kept until every slot is done, then recovered and stored.
+template <int LA, int LB, int NS, int KCLASS>
+__global__ __launch_bounds__(kBlock) void k_gemm_mma(const GemmArgs args, GemmSplit w)
+{
+    constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
+    constexpr int M = KCLASS == 2 ? NS - 1 : NS;
+    constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+    constexpr int CT = 2;  // 16-column tiles per wave
+    const GroupDev *G = &args.g;
+    const int64_t N = args.N, Q = args.Q, Pp = w.Pp;
+    const int skip = G->skip, l = G->l;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fi = lane & 15, fh = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.y * kGemmSplitRows + (wave >> 1) * 16;
+    const int64_t c0 = (int64_t)blockIdx.x * kGemmSplitCols + (wave & 1) * 16 * CT;
+    const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
+    const unsigned char *brow = w.b + (c0 + fi) * Pp + 16 * fh;
+    uint32_t flag = 0;
+    int64_t dl[CT][NS][4];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        if (t == skip) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) dl[ct][t][v] = 0;
+            continue;
+        }
+        const unsigned char *arow = w.a + (size_t)t * LA * aplane + (r0 + fi) * Pp + 16 * fh;
+        v4i acc[CT][S];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[ct][s] = v4i{0, 0, 0, 0};
+        for (int64_t kc = 0; kc < Pp; kc += kGemmK) {
+            v4i af[LA], bf[CT][LB];
+#pragma unroll
+            for (int a = 0; a < LA; ++a) af[a] = *(gcv4i_t *)(arow + a * aplane + kc);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+                    bf[ct][b] = *(gcv4i_t *)(brow + b * bplane + (size_t)16 * ct * Pp + kc);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[ct][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bf[ct][b], acc[ct][a + b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uint64_t y = (uint64_t)(int64_t)acc[ct][S - 1][v];
+#pragma unroll
+                for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[ct][s][v];
+                dl[ct][t][v] = (int64_t)y;
+            }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int64_t orow = r0 + 4 * fh, ocol = c0 + 16 * ct + fi;
+        int loc[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            loc[v] = (orow + v < N && ocol < Q) ? (int)((4 * fh + v) * Q + fi) : INT_MAX;
+        epilogue<NS, 4>(G, mode, M, skip, l, r0 * Q + c0 + 16 * ct, INT_MAX, loc, dl[ct], flag);
+    }
+    if (flag && args.flags) atomicOr(args.flags, flag);
+}
+
 }  // namespace fk
 
 namespace {
+
+unsigned grid_of(int64_t items)
+{
+    const int64_t g = (items + fk::kBlock - 1) / fk::kBlock;
+    return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+template <int LA, int LB, int NS>
+hipError_t launch_split(const GemmArgs &a, const GemmSplit &w, hipStream_t s)
+{
+    hipLaunchKernelGGL((fk::k_gemm_split_a<LA, NS, NE_KCLASS>), dim3(grid_of(w.Np * (w.Pp / 8))),
+                       dim3(fk::kBlock), 0, s, a, w);
+    hipLaunchKernelGGL((fk::k_gemm_split_b<LB>), dim3(grid_of(w.Qp * (w.Pp / 8))), dim3(fk::kBlock),
+                       0, s, a, w);
+    const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows));
+    hipLaunchKernelGGL((fk::k_gemm_mma<LA, LB, NS, NE_KCLASS>), grid, dim3(fk::kBlock), 0, s, a, w);
+    return hipGetLastError();
+}
 
 template <int LA, int LB, int NS>
 hipError_t launch_one(const GemmArgs &a, hipStream_t s)
@@ -238,18 +415,18 @@ hipError_t launch_one(const GemmArgs &a, hipStream_t s)
 }
 
 template <int LA, int LB, int NS>
-constexpr GemmLaunch launcher()
+constexpr GemmKernel launcher()
 {
     if constexpr (digits_needed(NE_KCLASS, NS, LA, LB, kGemmMaxBits) &&
                   gemm_lds(NS, LA, LB) <= 160 * 1024)
-        return &launch_one<LA, LB, NS>;
+        return GemmKernel{&launch_one<LA, LB, NS>, &launch_split<LA, LB, NS>};
     else
-        return nullptr;
+        return GemmKernel{nullptr, nullptr};
 }
 
 template <int NS>
 struct Row {
-    GemmLaunch f[kLimbsA][3];
+    GemmKernel f[kLimbsA][3];
 };
 
 template <int NS, int LA>
@@ -276,15 +453,16 @@ constexpr Row<NS> row()
 }
 
 template <int NS>
-GemmLaunch pick(int la, int lb)
+const GemmKernel *pick(int la, int lb)
 {
     static constexpr Row<NS> r = row<NS>();
-    return r.f[la - 1][lb - 1];
+    const GemmKernel *k = &r.f[la - 1][lb - 1];
+    return k->fused ? k : nullptr;
 }
 
 }  // namespace
 
-GemmLaunch NE_NAME(gemm_kernel_, NE_KCLASS)(int slots, int la, int lb)
+const GemmKernel *NE_NAME(gemm_kernel_, NE_KCLASS)(int slots, int la, int lb)
 {
     if (la < 1 || la > kLimbsA || lb < 1 || lb > 3) return nullptr;
     switch (slots) {

@@ -27,7 +27,8 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_plain_apply", "ne_checksum", "ne_checksum_recover", "ne_plan_create",
            "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
            "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in",
-           "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm")
+           "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
+           "ne_gemm_workspace_size")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -112,7 +113,10 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
-        "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P, _P]),
+        "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P,
+                           ctypes.c_size_t, _P, _P]),
+        "ne_gemm_workspace_size": (_i32, [_i32, _i32, _i64, _i64, _i64, _i32,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -435,10 +439,19 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
                                                    _ptr(workspace), ws_bytes, _stream(stream)))
 
 
+def gemm_workspace_size(mode: str, M: int, N: int, P: int, Q: int, in_bits: int) -> int:
+    sz = ctypes.c_size_t()
+    _check("ne_gemm_workspace_size", load().ne_gemm_workspace_size(MODES[mode], M, N, P, Q, in_bits,
+                                                                   ctypes.byref(sz)))
+    return sz.value
+
+
 def gemm(c: Sequence, g, out: Sequence, mode: str = "entangled", lost: int = -1,
-         in_bits: int = 16, flags=None, stream=None):
+         in_bits: int = 16, flags=None, stream=None, workspace=None):
     """out[m] = c[m] @ g for M int32 blocks c[m] (N x P) and an int32 kernel
-    matrix g (P x Q), int64 outputs (N x Q), by the method of `mode`."""
+    matrix g (P x Q), int64 outputs (N x Q), by the method of `mode`.
+    workspace: None (one fused launch) or a 256-byte aligned uint8 device
+    tensor of gemm_workspace_size bytes (two-phase form)."""
     import torch
     _dtype(c, torch.int32, "c")
     _dtype([g], torch.int32, "g")
@@ -453,5 +466,7 @@ def gemm(c: Sequence, g, out: Sequence, mode: str = "entangled", lost: int = -1,
     for t in out:
         if t.dim() != 2 or tuple(t.shape) != (N, Q):
             raise ValueError("every output must be N x Q")
+    ws_bytes = 0 if workspace is None else workspace.numel()
     _check("ne_gemm", load().ne_gemm(MODES[mode], len(c), N, P, Q, _ptr_array(c), _ptr(g),
-                                     _ptr_array(out), lost, in_bits, _ptr(flags), _stream(stream)))
+                                     _ptr_array(out), lost, in_bits, _ptr(workspace), ws_bytes,
+                                     _ptr(flags), _stream(stream)))

@@ -348,11 +348,26 @@ def test_gemm_validation(lib, args, status):
     c = ne._ptr_array([FAKE + 4096 * m for m in range(8)])
     out = ne._ptr_array([FAKE + (1 << 20) + 4096 * m for m in range(8)])
     assert lib.ne_gemm(a["mode"], a["M"], a["N"], a["P"], a["Q"], c, FAKE, out, a["lost"],
-                       a["in_bits"], None, None) == status
+                       a["in_bits"], None, 0, None, None) == status
 
 
 def test_gemm_null_blocks_refused(lib):
     c = ne._ptr_array([FAKE, 0, FAKE])
     out = ne._ptr_array([FAKE, FAKE, FAKE])
-    assert lib.ne_gemm(0, 3, 8, 8, 8, c, FAKE, out, -1, 12, None, None) == -1
-    assert lib.ne_gemm(0, 3, 8, 8, 8, out, 0, out, -1, 12, None, None) == -1
+    assert lib.ne_gemm(0, 3, 8, 8, 8, c, FAKE, out, -1, 12, None, 0, None, None) == -1
+    assert lib.ne_gemm(0, 3, 8, 8, 8, out, 0, out, -1, 12, None, 0, None, None) == -1
+
+
+def test_gemm_workspace_size_and_checks(lib):
+    """Digit planes of every slot (rows padded to 32, the inner dimension to
+    64) and of G (columns padded to 64); a short or misaligned workspace is
+    refused before anything is launched."""
+    # entangled M = 3, 12-bit values: 5 digits per word, 2 per kernel value
+    size = ne.gemm_workspace_size("entangled", 3, 100, 70, 90, 12)
+    up = lambda x, m: (x + m - 1) // m * m
+    assert size == up(3 * 5 * 128 * 128, 256) + 2 * 128 * 128
+    assert ne.gemm_workspace_size("entangled", 3, 0, 70, 90, 12) == 0
+    c = ne._ptr_array([FAKE + 4096 * m for m in range(3)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 4096 * m for m in range(3)])
+    assert lib.ne_gemm(0, 3, 100, 70, 90, c, FAKE, out, -1, 12, FAKE, size - 1, None, None) == -1
+    assert lib.ne_gemm(0, 3, 100, 70, 90, c, FAKE, out, -1, 12, FAKE + 16, size, None, None) == -1

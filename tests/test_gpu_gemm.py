@@ -14,7 +14,10 @@ DEV = "cuda:0"
 POISON = -0x5A5A5A5A5A5A5A5A
 
 
-def run(c, g, mode="entangled", lost=-1, in_bits=12):
+SPLIT = [False, True]  # one fused launch / the two-phase form through workspace
+
+
+def run(c, g, mode="entangled", lost=-1, in_bits=12, split=False):
     """c: (M, N, P) int32, g: (P, Q) int32 -> (outputs (M, N, Q), flags)."""
     M, N, P = c.shape
     Q = g.shape[1]
@@ -22,7 +25,12 @@ def run(c, g, mode="entangled", lost=-1, in_bits=12):
     gd = torch.from_numpy(np.ascontiguousarray(g)).to(DEV)
     out = [torch.full((N, Q), POISON, dtype=torch.int64, device=DEV) for _ in range(M)]
     flags = torch.zeros(1, dtype=torch.int32, device=DEV)
-    ne.gemm(cd, gd, out, mode, lost, in_bits, flags=flags)
+    ws = None
+    if split:
+        nb = ne.gemm_workspace_size(mode, M, N, P, Q, in_bits)
+        ws = torch.full((nb + 256,), 0x5A, dtype=torch.uint8, device=DEV)  # stale bytes
+        ws = ws[(-ws.data_ptr()) % 256:][:nb]
+    ne.gemm(cd, gd, out, mode, lost, in_bits, flags=flags, workspace=ws)
     torch.cuda.synchronize()
     return np.stack([o.cpu().numpy() for o in out]), int(flags.item())
 
@@ -36,15 +44,16 @@ def draw(seed, M, N, P, Q, bits):
 MODES = [("entangled", 3), ("plain", 1), ("plain_same", 1), ("checksum", 2)]
 
 
+@pytest.mark.parametrize("split", SPLIT)
 @pytest.mark.parametrize("mode,m_lo", MODES)
 @pytest.mark.parametrize("M", [3, 4, 8])
-def test_gemm_modes_and_losses(mode, m_lo, M):
+def test_gemm_modes_and_losses(mode, m_lo, M, split):
     """Ragged tiles in every dimension (N, Q not multiples of 32, P not a
     multiple of 64 nor of 4), every loss position."""
     c, g = draw(1000 + M, M, 37, 70, 45, 12)
     want = oracle.gemm(c, g)
     for lost in (-1, 0, M - 1):
-        got, flags = run(c, g, mode, lost)
+        got, flags = run(c, g, mode, lost, split=split)
         assert flags == 0, (mode, M, lost, flags)
         if mode in ("plain", "plain_same") and lost >= 0:
             keep = [m for m in range(M) if m != lost]
@@ -54,8 +63,9 @@ def test_gemm_modes_and_losses(mode, m_lo, M):
             assert np.array_equal(got, want), (mode, M, lost)
 
 
+@pytest.mark.parametrize("split", SPLIT)
 @pytest.mark.parametrize("mode,m_lo", MODES)
-def test_gemm_every_variant(mode, m_lo):
+def test_gemm_every_variant(mode, m_lo, split):
     """Every (M, digit counts) variant the call can pick: inputs of 1 to 16
     bits at a small shape, one lost block where the mode recovers it."""
     ran = 0
@@ -65,7 +75,7 @@ def test_gemm_every_variant(mode, m_lo):
             want = oracle.gemm(c, g)
             lost = M - 1 if mode in ("entangled", "checksum") else -1
             try:
-                got, flags = run(c, g, mode, lost, bits)
+                got, flags = run(c, g, mode, lost, bits, split=split)
             except ne.NeError as e:
                 assert e.status == -2, (mode, M, bits, e)  # only the range check may refuse
                 continue
@@ -75,7 +85,8 @@ def test_gemm_every_variant(mode, m_lo):
     assert ran > 0
 
 
-def test_gemm_vector_loads_and_extremes():
+@pytest.mark.parametrize("split", SPLIT)
+def test_gemm_vector_loads_and_extremes(split):
     """P a multiple of 4 (16-byte row loads), values at both ends of the
     declared 16-bit range, several chunks of the inner dimension."""
     M, N, P, Q = 3, 64, 256, 64
@@ -84,32 +95,35 @@ def test_gemm_vector_loads_and_extremes():
     g = np.full((P, Q), -(1 << 15), np.int32)
     g[::3] = (1 << 15) - 1
     for lost in (-1, 1):
-        got, flags = run(c, g, "entangled", lost, 16)
+        got, flags = run(c, g, "entangled", lost, 16, split=split)
         assert flags == 0
         assert np.array_equal(got, oracle.gemm(c, g))
 
 
-def test_gemm_empty_inner_dimension_gives_zeros():
+@pytest.mark.parametrize("split", SPLIT)
+def test_gemm_empty_inner_dimension_gives_zeros(split):
     c = np.zeros((3, 5, 0), np.int32)
     g = np.zeros((0, 7), np.int32)
-    got, flags = run(c, g, "entangled", 1)
+    got, flags = run(c, g, "entangled", 1, split=split)
     assert flags == 0 and (got == 0).all()
 
 
-def test_gemm_declared_range_violation_is_flagged():
+@pytest.mark.parametrize("split", SPLIT)
+def test_gemm_declared_range_violation_is_flagged(split):
     c, g = draw(5, 3, 16, 64, 16, 8)
     c[2, 3, 5] = 200  # outside 8 bits
-    _, flags = run(c, g, "entangled", -1, 8)
+    _, flags = run(c, g, "entangled", -1, 8, split=split)
     assert flags & ne.FLAG_INPUT_RANGE
 
 
-def test_gemm_benchmark_size():
+@pytest.mark.parametrize("split", SPLIT)
+def test_gemm_benchmark_size(split):
     """The product the benchmark times (3 blocks of 4096 x 1024 times
     1024 x 4096, 12-bit values), one block lost, sampled against the oracle
     entry by entry, edges included."""
     M, N, P, Q = 3, 4096, 1024, 4096
     c, g = wl.config_gemm()
-    got, flags = run(c, g, "entangled", 1, wl.GEMM_BITS)
+    got, flags = run(c, g, "entangled", 1, wl.GEMM_BITS, split=split)
     assert flags == 0
     rng = wl.rng(77)
     rows = np.concatenate([[0, N - 1, 31, 32], rng.integers(0, N, 400)])
