@@ -571,7 +571,7 @@ def gemm_line(args, wl):
                    "w": 64, "digits": [la, lb]},
         "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS,
                      "unit": "TOP/s", "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "digit split + k_gemm_mma, whole call (i8 ops issued: digit "
+                     "kernel": "digit split + k_gemm_digits + recovery, whole call (i8 ops issued: digit "
                                "pairs x padded tiles)",
                      "useful_int_tops": round(useful_ops / (e * 1e-3) / 1e12, 2),
                      "hbm_GBps": round(alg_bytes / (e * 1e-3) / 1e9, 1)},

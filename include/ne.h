@@ -302,11 +302,15 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
  * NE_FLAG_* bits (NULL: not reported). No allocation; launches on `stream`
  * only.
  * workspace: NULL runs one fused launch (digits split in LDS inside the
- * product kernel); otherwise device memory of ne_gemm_workspace_size bytes,
- * 256-byte aligned, owned by the caller: the digit planes of every block's
- * (entangled) values and of G are written there once, then the product
- * kernel reads its matrix-core fragments straight from them (three
- * launches, no staging in the product loop; faster for large products).
+ * product kernel, recovery in registers; with no loss the redundant block
+ * is checked, NE_FLAG_MISMATCH). Otherwise device memory of
+ * ne_gemm_workspace_size bytes, 256-byte aligned, owned by the caller: the
+ * digit planes of every block's (entangled) values and of G are written
+ * there once; every computed block's product is then an independent slice
+ * of one launch reading its matrix-core fragments straight from the planes
+ * and writing its entangled outputs into that block's output buffer (the
+ * checksum block's into the workspace); recovery follows in place (no
+ * redundancy check). Faster for large products.
  * Errors: NE_EINVAL (mode, M, negative sizes, NULL pointers of non-empty
  * matrices, a short or misaligned workspace), NE_EFAILIDX (lost), NE_ERANGE (P 2^(2 in_bits - 2) above D of
  * ne_params(M, 64) for the method, above 2^63 - 1 otherwise), NE_EUNSUP

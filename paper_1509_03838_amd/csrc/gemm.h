@@ -26,25 +26,31 @@ __host__ __device__ constexpr size_t gemm_lds(int slots, int la, int lb)
 }
 
 // Two-phase path: the digit planes of every slot's C values and of G are
-// written once to caller workspace, then a matrix-core kernel reads its
-// fragments straight from them (no staging, no barriers). Each wave owns
-// 16 rows x 32 columns; a block (2 x 2 waves) 32 rows x 64 columns.
-constexpr int kGemmSplitRows = 32, kGemmSplitCols = 64;
+// written once to caller workspace; then every computed slot's product is
+// an independent slice of one launch (blockIdx.z), each wave a 32 x 32 tile
+// read straight from the planes (no staging, no barriers), written as int64
+// entangled outputs into that stream's output buffer (the checksum slot's
+// into workspace); recovery follows in place (the per-step extraction, or
+// the checksum recovery).
+constexpr int kGemmSplitRows = 64, kGemmSplitCols = 64;
 
 struct GemmSplit {
     int64_t Np, Pp, Qp;  // N, P, Q rounded up to the block rows, 64 and the block columns
     unsigned char *a;    // slots x LA planes of Np x Pp digit bytes ([slot][digit][row][k])
     unsigned char *b;    // LB planes of Qp x Pp digit bytes ([digit][column][k])
+    int64_t *e;          // checksum method: the checksum slot's N x Q products
 };
 
 inline int64_t gemm_round(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Workspace bytes of the two-phase path (256-byte aligned pieces).
-inline size_t gemm_split_bytes(int slots, int la, int lb, int64_t N, int64_t P, int64_t Q)
+inline size_t gemm_split_bytes(int slots, int la, int lb, int64_t N, int64_t P, int64_t Q,
+                               bool checksum)
 {
-    const size_t Np = gemm_round(N, kGemmSplitRows), Pp = gemm_round(P, kGemmK),
-                 Qp = gemm_round(Q, kGemmSplitCols);
-    return (size_t)gemm_round((int64_t)(slots * la * Np * Pp), 256) + (size_t)lb * Qp * Pp;
+    const int64_t Np = gemm_round(N, kGemmSplitRows), Pp = gemm_round(P, kGemmK),
+                  Qp = gemm_round(Q, kGemmSplitCols);
+    return (size_t)gemm_round((int64_t)slots * la * Np * Pp, 256) +
+           (size_t)gemm_round((int64_t)lb * Qp * Pp, 256) + (checksum ? (size_t)N * Q * 8 : 0);
 }
 
 using GemmLaunch = hipError_t (*)(const GemmArgs &a, hipStream_t s);

@@ -3,7 +3,10 @@
 // kernel variant of gemm_kernels.hip.
 #include <algorithm>
 
+#include <limits.h>
+
 #include "conv_variants.h"
+#include "fused_kernels.h"
 #include "gemm.h"
 #include "ne_internal.h"
 
@@ -21,6 +24,104 @@ const GemmKernel *gemm_kernel(int kclass, int slots, int la, int lb)
     default: return nullptr;
     }
 }
+}  // namespace ne
+
+namespace ne {
+namespace {
+
+// The computed slots of one call: their digit planes and output buffers.
+struct DigitJob {
+    const unsigned char *a[kMaxSlots];
+    int64_t *d[kMaxSlots];
+};
+
+typedef __attribute__((address_space(1))) const fk::v4i gcv4i_t;
+
+// Phase 2: slot blockIdx.z's product, every digit pair of 16 x 64 A and
+// 64 x 16 B fragments (16-byte loads from the planes) into the accumulator
+// of its weight; each wave a 32 x 32 tile (2 x 2 matrix-core tiles). The
+// entangled (or plain) int64 products y = sum_s 256^s acc_s (mod 2^64) go
+// to the slot's output buffer.
+template <int LA, int LB>
+__global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, const DigitJob job,
+                                                            int64_t N, int64_t Q)
+{
+    constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int fi = lane & 15, fh = lane >> 4;
+    const int64_t Pp = w.Pp;
+    const int64_t r0 = (int64_t)blockIdx.y * kGemmSplitRows + (wave >> 1) * 32;
+    const int64_t c0 = (int64_t)blockIdx.x * kGemmSplitCols + (wave & 1) * 32;
+    const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
+    const unsigned char *arow = job.a[blockIdx.z] + (r0 + fi) * Pp + 16 * fh;
+    const unsigned char *brow = w.b + (c0 + fi) * Pp + 16 * fh;
+    fk::v4i acc[2][2][S];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[rt][ct][s] = fk::v4i{0, 0, 0, 0};
+    for (int64_t kc = 0; kc < Pp; kc += kGemmK) {
+        fk::v4i af[2][LA], bf[2][LB];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int a = 0; a < LA; ++a)
+                af[rt][a] = *(gcv4i_t *)(arow + a * aplane + (size_t)16 * rt * Pp + kc);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int b = 0; b < LB; ++b)
+                bf[ct][b] = *(gcv4i_t *)(brow + b * bplane + (size_t)16 * ct * Pp + kc);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+#pragma unroll
+                    for (int a = 0; a < LA; ++a)
+                        if (a + b < 8)
+                            acc[rt][ct][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[rt][a], bf[ct][b], acc[rt][ct][a + b], 0, 0, 0);
+    }
+    int64_t *d = job.d[blockIdx.z];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            const int64_t col = c0 + 16 * ct + fi;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = r0 + 16 * rt + 4 * fh + v;
+                uint64_t y = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
+#pragma unroll
+                for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
+                if (row < N && col < Q) fk::store_out(d + row * Q + col, (int64_t)y);
+            }
+        }
+}
+
+using DigitLaunch = void (*)(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N,
+                             int64_t Q, hipStream_t s);
+
+template <int LA, int LB>
+void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q,
+                   hipStream_t s)
+{
+    const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows),
+                    (unsigned)nslots);
+    hipLaunchKernelGGL((k_gemm_digits<LA, LB>), grid, dim3(fk::kBlock), 0, s, w, job, N, Q);
+}
+
+#define NE_DIGITS_ROW(LA) {&launch_digits<LA, 1>, &launch_digits<LA, 2>, &launch_digits<LA, 3>}
+const DigitLaunch kDigits[kLimbsA][3] = {NE_DIGITS_ROW(1), NE_DIGITS_ROW(2), NE_DIGITS_ROW(3),
+                                         NE_DIGITS_ROW(4), NE_DIGITS_ROW(5), NE_DIGITS_ROW(6),
+                                         NE_DIGITS_ROW(7), NE_DIGITS_ROW(8)};
+#undef NE_DIGITS_ROW
+
+}  // namespace
 }  // namespace ne
 
 using namespace ne;
@@ -52,7 +153,8 @@ extern "C" ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, 
     const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc);
     if (st != NE_OK) return st;
     const int nslots = mode == kChecksum ? M + 1 : M;
-    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q);
+    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q,
+                                                       mode == kChecksum);
     return NE_OK;
 }
 
@@ -94,7 +196,7 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
     const int nslots = mode == kChecksum ? M + 1 : M;
     const GemmKernel *kern = gemm_kernel(conv_class_of_mode(mode), nslots, dc.la, dc.lb);
     if (!kern) return NE_EUNSUP;
-    const size_t need = gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q);
+    const size_t need = gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q, mode == kChecksum);
     if (workspace && (workspace_bytes < need || (uintptr_t)workspace % 256)) return NE_EINVAL;
 
     GemmArgs a{};
@@ -131,9 +233,41 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         w.Pp = gemm_round(P, kGemmK);
         w.Qp = gemm_round(Q, kGemmSplitCols);
         w.a = (unsigned char *)workspace;
-        w.b = w.a + gemm_round((int64_t)(nslots * dc.la * (size_t)w.Np * w.Pp), 256);
+        w.b = w.a + gemm_round((int64_t)nslots * dc.la * w.Np * w.Pp, 256);
+        w.e = (int64_t *)(w.b + gemm_round((int64_t)dc.lb * w.Qp * w.Pp, 256));
         if (w.Qp / kGemmSplitCols > 0x7fffffff || w.Np / kGemmSplitRows > 65535) return NE_EUNSUP;
-        e = kern->split(a, w, (hipStream_t)stream);
+        hipStream_t s = (hipStream_t)stream;
+        e = kern->split(a, w, s);
+        if (e != hipSuccess) return hip_fail(e);
+        // every computed slot's product, one z slice each
+        DigitJob job{};
+        int nj = 0;
+        const size_t slot_bytes = (size_t)dc.la * w.Np * w.Pp;
+        for (int t = 0; t < nslots; ++t) {
+            if (t == G.skip) continue;
+            job.a[nj] = w.a + (size_t)t * slot_bytes;
+            job.d[nj] = t < M ? G.out[t] : w.e;
+            ++nj;
+        }
+        kDigits[dc.la - 1][dc.lb - 1](w, job, nj, N, Q, s);
+        // recovery in place
+        const int64_t n = N * Q;
+        if (mode == kEntangled) {
+            PtrsCI64 in{};
+            PtrsI64 o{};
+            for (int t = 0; t < M; ++t) {
+                if (t < M - 1) in.p[t] = G.out[t];
+                o.p[t] = G.out[t];
+            }
+            launch_extract(M, l, n, in, o, s);
+        } else if (mode == kChecksum && G.lost) {
+            PtrsCI64 d{};
+            int cnt = 0;
+            for (int t = 0; t < M; ++t)
+                if (t != G.r) d.p[cnt++] = G.out[t];
+            launch_checksum_recover(cnt, n, d, w.e, G.out[G.r], s);
+        }
+        e = hipGetLastError();
     } else {
         e = kern->fused(a, (hipStream_t)stream);
     }

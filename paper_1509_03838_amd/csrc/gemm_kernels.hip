@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
 }
 
 // ---------------------------------------------------------- two phases
-
+//
 // Phase 1: the digit planes of every slot's value (entangled, plain, or the
 // checksum sum) for all Np x Pp positions (zero outside the matrix); the
 // lost slot's planes are not written (never read).
@@ -296,86 +296,6 @@ __global__ __launch_bounds__(kBlock) void k_gemm_split_b(const GemmArgs args, Ge
     if ((bd.lo < G->in_lo || bd.hi > G->in_hi) && args.flags) atomicOr(args.flags, kFlagInputRange);
 }
 
-typedef __attribute__((address_space(1))) const v4i gcv4i_t;
-
-// Phase 2: slot by slot, every digit pair of 16 x 64 A and 64 x 16 B
-// fragments read from the planes (16-byte global loads) into the
-// accumulator of its weight; each slot's tiles are recombined into 64-bit
-// words, kept until every slot is done, then recovered and stored.
-template <int LA, int LB, int NS, int KCLASS>
-__global__ __launch_bounds__(kBlock) void k_gemm_mma(const GemmArgs args, GemmSplit w)
-{
-    constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
-    constexpr int M = KCLASS == 2 ? NS - 1 : NS;
-    constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
-    constexpr int CT = 2;  // 16-column tiles per wave
-    const GroupDev *G = &args.g;
-    const int64_t N = args.N, Q = args.Q, Pp = w.Pp;
-    const int skip = G->skip, l = G->l;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int fi = lane & 15, fh = lane >> 4;
-    const int64_t r0 = (int64_t)blockIdx.y * kGemmSplitRows + (wave >> 1) * 16;
-    const int64_t c0 = (int64_t)blockIdx.x * kGemmSplitCols + (wave & 1) * 16 * CT;
-    const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
-    const unsigned char *brow = w.b + (c0 + fi) * Pp + 16 * fh;
-    uint32_t flag = 0;
-    int64_t dl[CT][NS][4];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        if (t == skip) {
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) dl[ct][t][v] = 0;
-            continue;
-        }
-        const unsigned char *arow = w.a + (size_t)t * LA * aplane + (r0 + fi) * Pp + 16 * fh;
-        v4i acc[CT][S];
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int s = 0; s < S; ++s) acc[ct][s] = v4i{0, 0, 0, 0};
-        for (int64_t kc = 0; kc < Pp; kc += kGemmK) {
-            v4i af[LA], bf[CT][LB];
-#pragma unroll
-            for (int a = 0; a < LA; ++a) af[a] = *(gcv4i_t *)(arow + a * aplane + kc);
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-                for (int b = 0; b < LB; ++b)
-                    bf[ct][b] = *(gcv4i_t *)(brow + b * bplane + (size_t)16 * ct * Pp + kc);
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-                for (int b = 0; b < LB; ++b)
-#pragma unroll
-                    for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[ct][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af[a], bf[ct][b], acc[ct][a + b], 0, 0, 0);
-        }
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                uint64_t y = (uint64_t)(int64_t)acc[ct][S - 1][v];
-#pragma unroll
-                for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[ct][s][v];
-                dl[ct][t][v] = (int64_t)y;
-            }
-    }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const int64_t orow = r0 + 4 * fh, ocol = c0 + 16 * ct + fi;
-        int loc[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            loc[v] = (orow + v < N && ocol < Q) ? (int)((4 * fh + v) * Q + fi) : INT_MAX;
-        epilogue<NS, 4>(G, mode, M, skip, l, r0 * Q + c0 + 16 * ct, INT_MAX, loc, dl[ct], flag);
-    }
-    if (flag && args.flags) atomicOr(args.flags, flag);
-}
-
 }  // namespace fk
 
 namespace {
@@ -386,6 +306,7 @@ unsigned grid_of(int64_t items)
     return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
 }
 
+// Phase 1 of the two-phase form: the digit planes of every slot and of G.
 template <int LA, int LB, int NS>
 hipError_t launch_split(const GemmArgs &a, const GemmSplit &w, hipStream_t s)
 {
@@ -393,8 +314,6 @@ hipError_t launch_split(const GemmArgs &a, const GemmSplit &w, hipStream_t s)
                        dim3(fk::kBlock), 0, s, a, w);
     hipLaunchKernelGGL((fk::k_gemm_split_b<LB>), dim3(grid_of(w.Qp * (w.Pp / 8))), dim3(fk::kBlock),
                        0, s, a, w);
-    const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows));
-    hipLaunchKernelGGL((fk::k_gemm_mma<LA, LB, NS, NE_KCLASS>), grid, dim3(fk::kBlock), 0, s, a, w);
     return hipGetLastError();
 }
 
