@@ -37,24 +37,54 @@ struct DigitJob {
 
 typedef __attribute__((address_space(1))) const fk::v4i gcv4i_t;
 
-// Phase 2: slot blockIdx.z's product, every digit pair of 16 x 64 A and
-// 64 x 16 B fragments (16-byte loads from the planes) into the accumulator
-// of its weight; each wave a 32 x 32 tile (2 x 2 matrix-core tiles). The
-// entangled (or plain) int64 products y = sum_s 256^s acc_s (mod 2^64) go
-// to the slot's output buffer.
+// Phase 2: slot blockIdx.z's product. The block stages each 64-deep chunk
+// of its 64 A rows and 64 B columns (all digit planes) in LDS once -- 16-byte
+// loads into registers one chunk ahead, written to the other of two LDS
+// buffers, one barrier per chunk -- and every wave reads its fragments from
+// there (rows of 80 bytes: conflict-free 16-byte reads): every digit pair
+// of 16 x 64 A and 64 x 16 B fragments goes into the accumulator of its
+// weight, each wave a 32 x 32 tile (2 x 2 matrix-core tiles). The entangled
+// (or plain) int64 products y = sum_s 256^s acc_s (mod 2^64) go to the
+// slot's output buffer.
+constexpr int kDigitRow = 80;                        // LDS bytes per staged row (64 + 16)
+constexpr int kDigitPlane = kGemmSplitRows * kDigitRow;  // one digit plane of a chunk
+
+__host__ __device__ constexpr size_t digits_lds(int la, int lb)
+{
+    return (size_t)2 * (la + lb) * kDigitPlane;
+}
+
 template <int LA, int LB>
 __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, const DigitJob job,
                                                             int64_t N, int64_t Q)
 {
+    static_assert(kGemmSplitRows == 64 && kGemmSplitCols == 64, "block tile");
     constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NP = LA + LB;  // staged planes per chunk: A digits, then B digits
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int fi = lane & 15, fh = lane >> 4;
     const int64_t Pp = w.Pp;
-    const int64_t r0 = (int64_t)blockIdx.y * kGemmSplitRows + (wave >> 1) * 32;
-    const int64_t c0 = (int64_t)blockIdx.x * kGemmSplitCols + (wave & 1) * 32;
+    const int64_t R0 = (int64_t)blockIdx.y * kGemmSplitRows, C0 = (int64_t)blockIdx.x * kGemmSplitCols;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
-    const unsigned char *arow = job.a[blockIdx.z] + (r0 + fi) * Pp + 16 * fh;
-    const unsigned char *brow = w.b + (c0 + fi) * Pp + 16 * fh;
+    // staging: thread tid copies 16 bytes (segment sg) of row / column sr of every plane
+    const int sr = tid >> 2, sg = (tid & 3) * 16;
+    const unsigned char *ga = job.a[blockIdx.z] + (R0 + sr) * Pp + sg;
+    const unsigned char *gb = w.b + (C0 + sr) * Pp + sg;
+    const int soff = sr * kDigitRow + sg;
+    fk::v4i st[NP];
+    auto fetch = [&](int64_t kc) {
+#pragma unroll
+        for (int a = 0; a < LA; ++a) st[a] = *(gcv4i_t *)(ga + a * aplane + kc);
+#pragma unroll
+        for (int b = 0; b < LB; ++b) st[LA + b] = *(gcv4i_t *)(gb + b * bplane + kc);
+    };
+    auto stage = [&](unsigned char *buf) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+            *reinterpret_cast<fk::v4i *>(buf + q * kDigitPlane + soff) = st[q];
+    };
     fk::v4i acc[2][2][S];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -62,18 +92,30 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int s = 0; s < S; ++s) acc[rt][ct][s] = fk::v4i{0, 0, 0, 0};
-    for (int64_t kc = 0; kc < Pp; kc += kGemmK) {
+    const int64_t nc = Pp / kGemmK;
+    if (nc > 0) {
+        fetch(0);
+        stage(smem);
+        __syncthreads();
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+        unsigned char *cur = smem + (c & 1) * NP * kDigitPlane;
+        unsigned char *nxt = smem + ((c + 1) & 1) * NP * kDigitPlane;
+        const bool more = c + 1 < nc;
+        if (more) fetch((c + 1) * kGemmK);  // in flight while this chunk's products run
         fk::v4i af[2][LA], bf[2][LB];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int a = 0; a < LA; ++a)
-                af[rt][a] = *(gcv4i_t *)(arow + a * aplane + (size_t)16 * rt * Pp + kc);
+                af[rt][a] = *reinterpret_cast<const fk::v4i *>(
+                    cur + a * kDigitPlane + (wr + 16 * rt + fi) * kDigitRow + 16 * fh);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int b = 0; b < LB; ++b)
-                bf[ct][b] = *(gcv4i_t *)(brow + b * bplane + (size_t)16 * ct * Pp + kc);
+                bf[ct][b] = *reinterpret_cast<const fk::v4i *>(
+                    cur + (LA + b) * kDigitPlane + (wc + 16 * ct + fi) * kDigitRow + 16 * fh);
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -85,16 +127,20 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
                         if (a + b < 8)
                             acc[rt][ct][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                                 af[rt][a], bf[ct][b], acc[rt][ct][a + b], 0, 0, 0);
+        // the other buffer was last read in the previous chunk, before the
+        // barrier that ended it
+        if (more) stage(nxt);
+        __syncthreads();
     }
     int64_t *d = job.d[blockIdx.z];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-            const int64_t col = c0 + 16 * ct + fi;
+            const int64_t col = C0 + wc + 16 * ct + fi;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = r0 + 16 * rt + 4 * fh + v;
+                const int64_t row = R0 + wr + 16 * rt + 4 * fh + v;
                 uint64_t y = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
 #pragma unroll
                 for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
@@ -110,9 +156,16 @@ template <int LA, int LB>
 void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q,
                    hipStream_t s)
 {
+    void (*k)(const GemmSplit, const DigitJob, int64_t, int64_t) = &k_gemm_digits<LA, LB>;
+    constexpr size_t lds = digits_lds(LA, LB);
+    if (lds > 64 * 1024) {
+        static const hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return;  // the launch below then reports the error
+    }
     const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows),
                     (unsigned)nslots);
-    hipLaunchKernelGGL((k_gemm_digits<LA, LB>), grid, dim3(fk::kBlock), 0, s, w, job, N, Q);
+    hipLaunchKernelGGL(k, grid, dim3(fk::kBlock), lds, s, w, job, N, Q);
 }
 
 #define NE_DIGITS_ROW(LA) {&launch_digits<LA, 1>, &launch_digits<LA, 2>, &launch_digits<LA, 3>}
