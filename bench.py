@@ -54,7 +54,7 @@ def parse():
                    help="use the default tile steps instead of the autotuner's")
     p.add_argument("--config", default="batched",
                    choices=("batched", "small", "uneven", "long", "serve", "fig2", "chain", "gemm",
-                            "ops"),
+                            "ops", "w32"),
                    help="workload; the benchmark line is the batched one")
     p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -128,6 +128,8 @@ def main():
         return chain_line(args, wl)
     if args.config == "gemm":
         return gemm_line(args, wl)
+    if args.config == "w32":
+        return w32_line(args, wl)
     if args.config == "ops":
         return ops_line(args, wl)
     t_gen = time.perf_counter()
@@ -690,6 +692,100 @@ def ops_line(args, wl):
                      "kernel": "all launches of the five pipelines (per-operator rows below; the "
                                "convolution-like ones are bound by the vector ALUs)"},
         "ops": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def w32_line(args, wl):
+    """32-bit entangled words (the paper's practical w = 32, l = 11 for
+    M = 3) on a workload whose range fits them: 3 streams of 2^22 samples in
+    [-2^7, 2^7), 16-tap convolution (the small configuration's range, worst
+    case 2^18 <= D = 1,046,528), entangle -> conv -> extract per-step, one
+    stream lost; against the same pipeline in 64-bit words, the plain
+    convolution, and the fused executor (64-bit recovery, one pass)."""
+    import torch
+    from paper_1509_03838_amd import ne
+
+    dev = torch.device("cuda:0")
+    M, n, K = 3, 1 << 22, 16
+    rng = wl.rng(wl.SEED_BASE + 11)
+    c = wl.uniform_i32(rng, -128, 128, (M, n))
+    g = wl.uniform_i32(rng, -128, 128, K)
+    no = n + K - 1
+    l32, l64 = ne.params(M, 32)[0], ne.params(M)[0]
+    stream = torch.cuda.Stream()
+    cd = [torch.from_numpy(row).to(dev) for row in c]
+    gd = torch.from_numpy(g).to(dev)
+    e32 = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(M)]
+    d32 = [torch.empty(no, dtype=torch.int32, device=dev) for _ in range(M)]
+    o32 = [torch.empty(no, dtype=torch.int32, device=dev) for _ in range(M)]
+    e64 = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(M)]
+    d64 = [torch.empty(no, dtype=torch.int64, device=dev) for _ in range(M)]
+    o64 = [torch.empty(no, dtype=torch.int64, device=dev) for _ in range(M)]
+    lost, mask = 1, 0b101
+
+    def w32():
+        ne.entangle32(cd, e32, l32, stream=stream)
+        ne.lsb_apply32("conv", e32, gd, d32, mask=mask, stream=stream)
+        ne.extract_recover32([d32[0], None, d32[2]], lost, o32, l32, stream=stream)
+
+    def w64():
+        ne.entangle(cd, e64, l64, stream=stream)
+        ne.lsb_apply("conv", e64, gd, d64, mask=mask, stream=stream)
+        ne.extract_recover([d64[0], None, d64[2]], lost, o64, l64, stream=stream)
+
+    def plain():
+        ne.plain_apply("conv", cd, gd, o64, stream=stream)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    t_plain = timed(plain)
+    ref = torch.stack([t[::4099] for t in o64]).cpu()
+    t64 = timed(w64)
+    t32 = timed(w32)
+    same = torch.equal(torch.stack([t[::4099] for t in o64]).cpu(), ref) and torch.equal(
+        torch.stack([t[::4099] for t in o32]).cpu().to(torch.int64), ref)
+    spec = ne.GroupSpec("conv", cd, gd, o64, 0, lost, 8)
+    plan = ne.Plan([spec], "entangled")
+    plan.capture(stream)
+    t_fused, _ = time_captured(torch, plan, stream, args.steps, args.warmup)
+    same = same and not plan.flags() and torch.equal(
+        torch.stack([t[::4099] for t in o64]).cpu(), ref)
+    plan.close()
+    if not same:
+        raise SystemExit("w32: the 32-bit, 64-bit, fused and plain results differ")
+    # algorithmic HBM bytes of the three launches (two streams computed)
+    def nbytes(word):
+        return (M * n * (4 + word) + (M - 1) * (n + no) * word + K * 4 +
+                (M - 1) * no * word + M * no * word)
+    b32, b64 = nbytes(4), nbytes(8)
+    hbm = b32 / (t32 * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": round(M * no / (t32 * 1e-3) / 1e9, 3),
+        "unit": "Gout-samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t32, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "32-bit words: 3 streams x 2^22 int32 samples in [-2^7,2^7), "
+                               "16-tap conv, stream 1 lost; entangle -> conv -> extract per-step",
+                   "w": 32, "l": l32, "D": ne.params(M, 32)[2]},
+        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "the three launches of the step", "alg_bytes_per_step": b32},
+        "baselines": {"ms_per_step": {"w32": round(t32, 4), "w64": round(t64, 4),
+                                      "plain": round(t_plain, 4),
+                                      "fused_w64_one_pass": round(t_fused, 4)},
+                      "alg_bytes_per_step": {"w32": b32, "w64": b64},
+                      "speedup_w32_vs_w64": round(t64 / t32, 3)},
     }
     print(json.dumps(line), flush=True)
 

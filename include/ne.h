@@ -52,7 +52,8 @@ extern "C" {
 #endif
 
 #define NE_MAX_M 32      /* largest group size accepted */
-#define NE_WORD_BITS 64  /* w: width of an entangled word */
+#define NE_WORD_BITS 64  /* w: width of an entangled word (the ne_*32 calls: 32) */
+#define NE_MAX_M32 17    /* largest group with an admissible l at w = 32 (l = 2, k = 0) */
 
 typedef int32_t ne_status;
 #define NE_OK 0
@@ -210,6 +211,47 @@ ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rs
  */
 ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
                               const int64_t *e, int32_t r, int64_t *d_r, ne_stream stream);
+
+/* ------------------------------------------------------------------------
+ * The same per-step method in 32-bit entangled words, the paper's practical
+ * instantiation (Sec. III-B; Table I's w = 32 column; l = 11, k = 10 for
+ * M = 3). Every entangled word, operand and recovered output is an int32,
+ * so each of these calls moves half the bytes of its 64-bit counterpart.
+ * Arithmetic wraps modulo 2^32, which is exact while every output satisfies
+ * |d_m[i]| <= D of ne_params(M, 32) (1,046,528 for M = 3; every input
+ * sample must be in that range too). Argument rules, aliasing, NULL
+ * zero-length buffers and errors are those of the 64-bit calls, except
+ * where stated.
+ */
+
+/* eps[m][i] = c[m][i] + 2^l c[(m-1) mod M][i] (mod 2^32), eq. (14)-(15).
+ * M in [3, NE_MAX_M32]; l in [1, 31], normally the l of ne_params(M, 32). */
+ne_status ne_entangle32(int32_t M, int32_t l, int64_t n, const int32_t *const *c,
+                        int32_t *const *eps, ne_stream stream);
+
+/* g_ent[i] = g[i] + 2^l g[i] (mod 2^32), footnote 3: the operand of
+ * NE_OP_ADD and NE_OP_SUB on 32-bit entangled streams. */
+ne_status ne_entangle_operand32(int32_t l, int64_t n, const int32_t *g, int32_t *g_ent,
+                                ne_stream stream);
+
+/* delta[m] = eps[m] op g (mod 2^32) for every m with bit m of stream_mask
+ * set (eq. (9); a cleared bit is a fail-stop loss). Operation codes, shapes
+ * and n_out are those of ne_lsb_apply; every operand is int32 (the entangled
+ * operand of ne_entangle_operand32 for NE_OP_ADD and NE_OP_SUB); the scalar
+ * of NE_OP_SCALE is taken modulo 2^32. M in [1, NE_MAX_M]. */
+ne_status ne_lsb_apply32(int32_t op, int32_t M, int64_t n_in, const int32_t *const *eps,
+                         const int32_t *operand, int64_t n_operand, int64_t scalar,
+                         int32_t *const *delta, int64_t n_out, uint32_t stream_mask,
+                         ne_stream stream);
+
+/* Extraction and recovery (eq. (16)-(19), the register-width form of
+ * Remark 1) from the int32 outputs of the M-1 streams other than r; all M
+ * recovered outputs are written as int32. delta[r] is never read; r = -1
+ * means no loss; dhat may alias delta stream by stream. Errors: NE_EFAILIDX
+ * for r outside [-1, M); NE_EINVAL for M outside [3, NE_MAX_M32], l outside
+ * [1, 31] or (M-1)l > 32. */
+ne_status ne_extract_recover32(int32_t M, int32_t l, int64_t n_out, const int32_t *const *delta,
+                               int32_t r, int32_t *const *dhat, ne_stream stream);
 
 /* ------------------------------------------------------------------------
  * Series of LSB operations (Sec. II: operators applied one after another,

@@ -23,29 +23,6 @@ ne_status launch_status()
     return e == hipSuccess ? NE_OK : hip_fail(e);
 }
 
-}  // namespace ne
-
-using namespace ne;
-
-namespace {
-
-inline bool bad_m(int32_t M, int32_t lo) { return M < lo || M > kMaxM; }
-
-// Copies the streams whose mask bit is set into a compacted table.
-template <typename In, typename Tab>
-int compact(int32_t M, In const *const *src, uint32_t mask, Tab &dst, bool &null_seen)
-{
-    int count = 0;
-    null_seen = false;
-    for (int m = 0; m < M; ++m) {
-        if (!((mask >> m) & 1u)) continue;
-        if (!src[m]) null_seen = true;
-        using P = std::remove_reference_t<decltype(dst.p[0])>;
-        dst.p[count++] = const_cast<P>(src[m]);
-    }
-    return count;
-}
-
 ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t n_operand,
                          int64_t n_out)
 {
@@ -81,6 +58,29 @@ ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t 
     default:
         return NE_EUNSUP;
     }
+}
+
+}  // namespace ne
+
+using namespace ne;
+
+namespace {
+
+inline bool bad_m(int32_t M, int32_t lo) { return M < lo || M > kMaxM; }
+
+// Copies the streams whose mask bit is set into a compacted table.
+template <typename In, typename Tab>
+int compact(int32_t M, In const *const *src, uint32_t mask, Tab &dst, bool &null_seen)
+{
+    int count = 0;
+    null_seen = false;
+    for (int m = 0; m < M; ++m) {
+        if (!((mask >> m) & 1u)) continue;
+        if (!src[m]) null_seen = true;
+        using P = std::remove_reference_t<decltype(dst.p[0])>;
+        dst.p[count++] = const_cast<P>(src[m]);
+    }
+    return count;
 }
 
 }  // namespace

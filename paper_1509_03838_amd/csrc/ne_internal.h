@@ -28,6 +28,10 @@ struct PtrsI64 {
 ne_status hip_fail(hipError_t e);
 // Checks hipGetLastError() after a launch.
 ne_status launch_status();
+// Shape rules of one LSB operation (ne_lsb_apply): NE_OK, NE_EINVAL or
+// NE_EUNSUP.
+ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t n_operand,
+                         int64_t n_out);
 
 // ------------------------------------------------------------- launchers
 // All launchers assume validated arguments (the C-ABI layer checks them).

@@ -21,6 +21,7 @@ SUB, MUL, CIRC, XCORR, OUTER = 5, 6, 7, 8, 9
 OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM,
        "sub": SUB, "mul": MUL, "circ": CIRC, "xcorr": XCORR, "outer": OUTER}
 MAX_M = 32
+MAX_M32 = 17
 
 EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_entangle",
            "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
@@ -28,7 +29,8 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_plan_run", "ne_plan_capture", "ne_plan_launch", "ne_plan_flags",
            "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in",
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
-           "ne_gemm_workspace_size")
+           "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
+           "ne_extract_recover32")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -117,6 +119,10 @@ def load() -> ctypes.CDLL:
                            ctypes.c_size_t, _P, _P]),
         "ne_gemm_workspace_size": (_i32, [_i32, _i32, _i64, _i64, _i64, _i32,
                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "ne_entangle32": (_i32, [_i32, _i32, _i64, _P, _P, _P]),
+        "ne_entangle_operand32": (_i32, [_i32, _i64, _P, _P, _P]),
+        "ne_lsb_apply32": (_i32, [_i32, _i32, _i64, _P, _P, _i64, _i64, _P, _i64, _u32, _P]),
+        "ne_extract_recover32": (_i32, [_i32, _i32, _i64, _P, _i32, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -238,6 +244,62 @@ def extract_recover(delta: Sequence, r: int, dhat: Sequence, l: int, n: int | No
         n = dhat[0].numel()
     _check("ne_extract_recover", load().ne_extract_recover(M, l, n, _ptr_array(delta), r,
                                                            _ptr_array(dhat), _stream(stream)))
+
+
+def entangle32(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=None):
+    """eps[m] = c[m] + 2^l c[m-1] modulo 2^32 (int32 -> int32), eq. (14)-(15)
+    in 32-bit words; l normally params(M, 32)[0]."""
+    import torch
+    _dtype(c, torch.int32, "c")
+    _dtype(eps, torch.int32, "eps")
+    if len(c) != len(eps):
+        raise ValueError("c and eps differ in length")
+    n = c[0].numel() if n is None else n
+    _check("ne_entangle32", load().ne_entangle32(len(c), l, n, _ptr_array(c), _ptr_array(eps),
+                                                 _stream(stream)))
+
+
+def entangle_operand32(g, g_ent, l: int, stream=None):
+    import torch
+    _dtype([g, g_ent], torch.int32, "g")
+    _check("ne_entangle_operand32", load().ne_entangle_operand32(l, g.numel(), _ptr(g),
+                                                                 _ptr(g_ent), _stream(stream)))
+
+
+def lsb_apply32(op: str, eps: Sequence, operand, delta: Sequence, scalar: int = 0,
+                mask: int | None = None, n_in: int | None = None, stream=None):
+    """delta[m] = eps[m] op operand modulo 2^32 for every stream whose mask
+    bit is set; int32 words, int32 operand."""
+    import torch
+    _dtype(eps, torch.int32, "eps")
+    _dtype(delta, torch.int32, "delta")
+    if operand is not None and not isinstance(operand, int):
+        _dtype([operand], torch.int32, "operand")
+    M = len(eps)
+    if mask is None:
+        mask = (1 << M) - 1
+    if n_in is None:
+        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    n_operand = 0 if operand is None or isinstance(operand, int) else operand.numel()
+    no = n_out(op, n_in, n_operand)
+    _check("ne_lsb_apply32", load().ne_lsb_apply32(OPS[op], M, n_in, _ptr_array(eps),
+                                                   _ptr(operand), n_operand, int(scalar),
+                                                   _ptr_array(delta), no, mask & 0xFFFFFFFF,
+                                                   _stream(stream)))
+
+
+def extract_recover32(delta: Sequence, r: int, dhat: Sequence, l: int, n: int | None = None,
+                      stream=None):
+    """Recover all M int32 outputs from the int32 words of the streams other
+    than r (eq. (16)-(19) in 32-bit words)."""
+    import torch
+    _dtype(delta, torch.int32, "delta")
+    _dtype(dhat, torch.int32, "dhat")
+    M = len(dhat)
+    if n is None:
+        n = dhat[0].numel()
+    _check("ne_extract_recover32", load().ne_extract_recover32(M, l, n, _ptr_array(delta), r,
+                                                               _ptr_array(dhat), _stream(stream)))
 
 
 def plain_apply(op: str, c: Sequence, operand, d: Sequence, scalar: int = 0, stream=None):

@@ -111,6 +111,36 @@ def test_empty_inputs_enqueue_nothing(lib):
     assert lib.ne_lsb_apply(1, 3, 10, p3, 0, 0, 2, p3, 10, 0, None) == 0
 
 
+def test_word32_validation_before_launch(lib):
+    """The 32-bit word calls check their own limits: M up to 17 (the largest
+    group with an admissible l at w = 32), l up to 31, (M - 1) l <= 32."""
+    p3 = _ptrs([FAKE, FAKE + 64, FAKE + 128])
+    p18 = _ptrs([FAKE + 64 * i for i in range(18)])
+    assert ne.MAX_M32 == 17 and ne.params(17, 32)[0] == 2
+    with pytest.raises(ne.NeError):
+        ne.params(18, 32)
+    assert lib.ne_entangle32(2, 11, 10, p3, p3, None) == -1
+    assert lib.ne_entangle32(18, 2, 10, p18, p18, None) == -1
+    assert lib.ne_entangle32(3, 32, 10, p3, p3, None) == -1
+    assert lib.ne_entangle32(3, 11, 10, _ptrs([FAKE, 0, FAKE]), p3, None) == -1
+    assert lib.ne_entangle_operand32(0, 10, FAKE, FAKE, None) == -1
+    assert lib.ne_entangle_operand32(11, 10, 0, FAKE, None) == -1
+    assert lib.ne_extract_recover32(3, 11, 10, p3, 3, p3, None) == -3
+    assert lib.ne_extract_recover32(3, 11, 10, p3, -2, p3, None) == -3
+    assert lib.ne_extract_recover32(3, 17, 10, p3, 0, p3, None) == -1   # (M-1) l = 34 > 32
+    assert lib.ne_extract_recover32(18, 2, 10, p18, 0, p18, None) == -1
+    assert lib.ne_extract_recover32(3, 11, 10, _ptrs([FAKE, 0, FAKE]), 0, p3, None) == -1
+    assert lib.ne_lsb_apply32(0, 3, 10, p3, FAKE, 4, 0, p3, 12, 7, None) == -1
+    assert lib.ne_lsb_apply32(3, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -1
+    assert lib.ne_lsb_apply32(10, 3, 10, p3, FAKE, 10, 0, p3, 10, 7, None) == -4
+    assert lib.ne_lsb_apply32(1, 3, 10, p3, 0, 0, 2, _ptrs([FAKE, 0, FAKE]), 10, 7, None) == -1
+    # zero lengths and all-lost masks enqueue nothing
+    assert lib.ne_entangle32(3, 11, 0, p3, p3, None) == 0
+    assert lib.ne_extract_recover32(3, 11, 0, p3, 1, p3, None) == 0
+    assert lib.ne_lsb_apply32(1, 3, 10, p3, 0, 0, 2, p3, 10, 0, None) == 0
+    assert lib.ne_lsb_apply32(0, 3, 0, p3, FAKE, 16, 0, p3, 0, 7, None) == 0
+
+
 def _group(**kw):
     g = ne.GroupC()
     g.op, g.M, g.n, g.n_operand, g.scalar, g.lost, g.in_bits = 0, 3, 100, 16, 0, -1, 12

@@ -1,0 +1,193 @@
+"""GPU parity of the 32-bit word path (ne_*32): entangle, every LSB
+operation and extraction in int32 words, through the C-ABI, against the CPU
+oracle run at w = 32 on the same seeded inputs, bit for bit. Input ranges
+keep every output within D of ne_params(M, 32)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_03838_amd import ne
+from paper_1509_03838_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+POISON = -0x5A5A5A5B
+
+
+def dev32(a, offset=0):
+    """An int32 device copy of a; with offset > 0 it starts `offset` words
+    into a larger buffer (not 16-byte aligned: the one-position kernels)."""
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    buf = torch.zeros(a.size + offset + 1, dtype=torch.int32, device=DEV)
+    t = buf[offset:offset + a.size]
+    if a.size:
+        t.copy_(torch.from_numpy(a))
+    return t
+
+
+def empty32(M, n, offset=0, fill=None):
+    out = []
+    for _ in range(M):
+        buf = torch.empty(n + offset + 1, dtype=torch.int32, device=DEV)
+        if fill is not None:
+            buf.fill_(fill)
+        out.append(buf[offset:offset + n])
+    return out
+
+
+def host(ts):
+    torch.cuda.synchronize()
+    return np.stack([t.cpu().numpy().astype(np.int64) for t in ts])
+
+
+# op -> (sample half-range, operand half-range, operand length or None for
+# a length-n operand); all within D(M = 3, w = 32) = 1,046,528 at n <= 4099
+RANGES = {"conv": (128, 128, 16), "circ": (128, 128, 16), "xcorr": (128, 128, 16),
+          "scale": (1 << 12, None, 0), "add": (1 << 18, 1 << 18, None),
+          "sub": (1 << 18, 1 << 18, None), "mul": (1 << 9, 1 << 9, None),
+          "inner": (15, 15, None), "perm": (1 << 19, None, None), "outer": (1 << 9, 1 << 9, 8)}
+
+
+def make_case(op, M, n, seed):
+    rng = wl.rng(seed)
+    a, b, K = RANGES[op]
+    c = wl.uniform_i32(rng, -a, a, (M, n))
+    g, s = None, 0
+    if op == "scale":
+        s = -201
+    elif op == "perm":
+        g = rng.permutation(n).astype(np.int32)
+    else:
+        g = wl.uniform_i32(rng, -b, b, n if K is None else K)
+    return c, g, s
+
+
+def run32(c, op, g, s, lost, offset=0):
+    """entangle32 -> lsb_apply32 on every stream but `lost` -> extract32.
+    Returns (eps, delta, dhat) on the host."""
+    M, n = c.shape
+    l = ne.params(M, 32)[0]
+    cd = [dev32(row, offset) for row in c]
+    eps = empty32(M, n, offset)
+    ne.entangle32(cd, eps, l, n=n)
+    operand = None
+    if g is not None:
+        operand = dev32(g, offset)
+        if op in ("add", "sub"):
+            ge = empty32(1, n, offset)[0]
+            ne.entangle_operand32(operand, ge, l)
+            operand = ge
+    no = ne.n_out(op, n, 0 if g is None else g.size)
+    delta = empty32(M, no, offset, fill=POISON)
+    mask = (1 << M) - 1 & ~(1 << lost if lost >= 0 else 0)
+    ne.lsb_apply32(op, eps, operand, delta, scalar=s, mask=mask, n_in=n)
+    dhat = empty32(M, no, offset, fill=POISON)
+    ne.extract_recover32([None if m == lost else delta[m] for m in range(M)], lost, dhat, l, n=no)
+    return host(eps), host(delta), host(dhat)
+
+
+@pytest.mark.parametrize("op", list(RANGES))
+@pytest.mark.parametrize("M", [3, 4, 5, 8])
+def test_word32_pipeline_matches_oracle(op, M):
+    """Every step at w = 32 equals the oracle at w = 32, and the recovered
+    outputs equal the plain operation, for no loss and each of three lost
+    streams; the lost stream's words are never written."""
+    n = 4099
+    c, g, s = make_case(op, M, n, 9100 + 17 * M + list(RANGES).index(op))
+    want = oracle.apply(op, c, g, s)
+    for lost in (-1, 0, M // 2, M - 1):
+        d_or, eps_or, delta_or = oracle.pipeline(c, op, g, s, r=max(lost, 0), w=32)
+        assert np.array_equal(d_or, want), (op, M, lost)
+        eps, delta, dhat = run32(c, op, g, s, lost)
+        assert np.array_equal(eps, eps_or), (op, M, lost)
+        live = [m for m in range(M) if m != lost]
+        assert np.array_equal(delta[live], delta_or[live]), (op, M, lost)
+        if lost >= 0:
+            assert (delta[lost] == POISON).all()
+        assert np.array_equal(dhat, want), (op, M, lost)
+
+
+@pytest.mark.parametrize("op", ["conv", "scale", "add", "perm", "xcorr"])
+def test_word32_unaligned_buffers(op):
+    """Buffers one word past a 16-byte boundary take the one-position
+    kernels; results are the same."""
+    M, n = 3, 1001
+    c, g, s = make_case(op, M, n, 9300)
+    _, _, dhat = run32(c, op, g, s, 1, offset=1)
+    assert np.array_equal(dhat, oracle.apply(op, c, g, s))
+
+
+@pytest.mark.parametrize("M", [3, 6, 9, 12, 16, 17])
+def test_word32_every_group_size(M):
+    """Entanglement and recovery for group sizes up to the largest that
+    w = 32 admits (M = 17: l = 2, k = 0), at the edge of the range
+    (samples of magnitude D and -D), every lost stream."""
+    l, _, D = ne.params(M, 32)
+    n = 1031
+    rng = wl.rng(9400 + M)
+    c = rng.integers(-D, D + 1, size=(M, n)).astype(np.int64)
+    c[:, 0], c[:, 1] = D, -D
+    c32 = c.astype(np.int32)
+    assert np.array_equal(c32, c)
+    for lost in range(-1, M):
+        d_or, eps_or, _ = oracle.pipeline(c, "scale", None, 1, r=max(lost, 0), w=32)
+        eps, _, dhat = run32(c32, "scale", None, 1, lost)
+        assert np.array_equal(eps, eps_or), (M, lost)
+        assert np.array_equal(dhat, c), (M, lost)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5])
+def test_word32_tiny_streams(n):
+    """Empty streams and streams shorter than one 4-position group; the
+    circular convolution with more taps than samples wraps them."""
+    M = 4
+    for op in ("conv", "circ", "inner", "outer", "mul"):
+        c, g, s = make_case(op, M, n, 9500 + n)
+        if op == "circ" and n:
+            g = wl.uniform_i32(wl.rng(9501), -128, 128, 37)
+        _, _, dhat = run32(c, op, g, s, 2)
+        assert np.array_equal(dhat, oracle.apply(op, c, g, s).reshape(dhat.shape)), (op, n)
+
+
+def test_word32_small_configuration_full_size():
+    """The small configuration (3 streams of 65,536 int32 samples in
+    [-2^7, 2^7), 16-tap convolution, worst case 2^18 within D = 1,046,528 at
+    w = 32) compared in full, each stream lost in turn."""
+    M, n, K = 3, 1 << 16, 16
+    rng = wl.rng(wl.SEED_BASE + 1)
+    c = wl.uniform_i32(rng, -128, 128, (M, n))
+    g = wl.uniform_i32(rng, -128, 128, K)
+    want = oracle.apply("conv", c, g)
+    for lost in (-1, 0, 1, 2):
+        _, _, dhat = run32(c, "conv", g, 0, lost)
+        assert np.array_equal(dhat, want), lost
+
+
+def test_word32_benchmark_size():
+    """The size the benchmark times (3 streams of 2^22 samples in
+    [-2^7, 2^7), 16 taps) with stream 1 lost: sampled outputs against the
+    oracle's convolution at those positions, and every output against the
+    64-bit path's result."""
+    M, n, K = 3, 1 << 22, 16
+    rng = wl.rng(wl.SEED_BASE + 11)
+    c = wl.uniform_i32(rng, -128, 128, (M, n))
+    g = wl.uniform_i32(rng, -128, 128, K)
+    _, _, dhat = run32(c, "conv", g, 0, 1)
+    pos = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n + K - 1),
+                                    wl.rng(7).integers(0, n + K - 1, 4000)]))
+    for m in range(M):
+        assert np.array_equal(dhat[m, pos], oracle.conv_at(c[m], g, pos)), m
+    # the 64-bit path on the same inputs: every output
+    l64 = ne.params(M)[0]
+    cd = [dev32(row) for row in c]
+    eps = [torch.empty(n, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ne.entangle(cd, eps, l64)
+    no = n + K - 1
+    delta = [torch.empty(no, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ne.lsb_apply("conv", eps, dev32(g), delta, mask=0b101)
+    out = [torch.empty(no, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ne.extract_recover([delta[0], None, delta[2]], 1, out, l64)
+    torch.cuda.synchronize()
+    for m in range(M):
+        assert np.array_equal(dhat[m], out[m].cpu().numpy()), m
