@@ -434,7 +434,11 @@ typedef struct ne_group {
                             only, for long kernels); 0: the plan's choice (1
                             only where it fits more blocks per CU than 4, or
                             4 does not fit at all) */
-    int32_t reserved;    /* must be 0 */
+    int32_t word_bits;   /* w, the width of the entangled words: 0 or 64
+                            (outputs int64, D of ne_params(M, 64)), or 32
+                            (the paper's practical width: l and D of
+                            ne_params(M, 32), outputs stored as int32; plain
+                            and checksum groups: results within 2^31 - 1) */
     const int32_t *c[NE_FUSED_MAX_M]; /* device inputs; 16-byte aligned */
     const int32_t *operand;           /* device int32 taps / vector /
                                          permutation indices, 16-byte aligned;
@@ -442,7 +446,8 @@ typedef struct ne_group {
                                          For add and sub, the plain vector g
                                          (the entangled mode entangles it
                                          itself, footnote 3). */
-    int64_t *out[NE_FUSED_MAX_M];     /* device outputs, n_out int64 each,
+    void *out[NE_FUSED_MAX_M];        /* device outputs, n_out int64 each
+                                         (int32 with word_bits = 32),
                                          16-byte aligned, disjoint */
 } ne_group;
 
@@ -455,7 +460,7 @@ typedef struct ne_tuning {
 typedef struct ne_plan_stats {
     int64_t groups, items, launches;
     int64_t in_bytes;     /* int32 input and operand bytes one run must read */
-    int64_t out_bytes;    /* int64 output bytes one run must write */
+    int64_t out_bytes;    /* output bytes one run must write */
     int64_t out_samples;  /* recovered output samples of one run */
     int64_t macs;         /* useful multiply-adds of one run (conv and inner) */
     int64_t mfma_macs;    /* i8 multiply-adds issued on the matrix cores */
@@ -467,8 +472,8 @@ typedef struct ne_plan ne_plan;
 /*
  * Validate the groups (host array of n_groups), choose digit counts from
  * in_bits, check that every group's worst-case output is admissible
- * (|d| <= D of eq. (11)/(13) in NE_MODE_ENTANGLED, |d| < 2^63 otherwise;
- * NE_ERANGE if not), build the work items and upload them. Allocates device
+ * (|d| <= D of eq. (11)/(13) for the group's word width in
+ * NE_MODE_ENTANGLED, |d| < 2^(w-1) otherwise; NE_ERANGE if not), build the work items and upload them. Allocates device
  * memory for the plan only (freed by ne_plan_destroy): its tables, plus, per
  * permutation group, n rows of 16 (at most 4 slots) or 32 bytes into which
  * every run first interleaves the group's streams (so that each gather at

@@ -55,6 +55,8 @@ struct GroupDev {
     int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
     int32_t skip;     // slot whose operation is not run (the lost stream), or -1
     int32_t kind;     // convolution kernel: 0 linear, 1 circular (length n), 2 cross-correlation
+    int32_t out32;    // 1: 32-bit words (w = 32): outputs stored as int32
+    int32_t pad_;
     int64_t n, K, n_out;
     int64_t scalar;
     // Inputs and outputs in slot order. Slot t of an entangled group is
@@ -64,7 +66,7 @@ struct GroupDev {
     // modes slot t is stream t (slot M: the checksum, which has no pointer).
     const int32_t *c[kFusedMaxM];
     const int32_t *operand;
-    int64_t *out[kFusedMaxM];
+    int64_t *out[kFusedMaxM];  // int32 storage when out32
     uint64_t *acc;    // inner product: kMaxSlots accumulators
     int32_t *rows;    // permutation: the streams interleaved, one row of 4 (<= 4 slots)
                       // or 8 int32 per position, in the plan's workspace

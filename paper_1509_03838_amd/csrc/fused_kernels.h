@@ -58,7 +58,20 @@ __device__ __forceinline__ int64_t ent(int64_t cur, int64_t prev, int l)
 typedef __attribute__((address_space(1))) int64_t gi64_t;
 typedef __attribute__((address_space(1))) const v4i gv4i_t;
 
+typedef __attribute__((address_space(1))) int32_t gi32_t;
+
 __device__ __forceinline__ void store_out(int64_t *p, int64_t v) { *(gi64_t *)p = v; }
+
+// One recovered output at index idx of an output stream: int64, or int32 in
+// groups of 32-bit words (the value then fits 32 bits by the plan's range
+// check).
+__device__ __forceinline__ void store_out(int64_t *base, int64_t idx, int64_t v, bool o32)
+{
+    if (o32)
+        *(gi32_t *)((int32_t *)base + idx) = (int32_t)v;
+    else
+        *(gi64_t *)(base + idx) = v;
+}
 __device__ __forceinline__ v4i load_in4(const int32_t *p) { return *(gv4i_t *)p; }
 __device__ __forceinline__ int32_t load_in1(const int32_t *p)
 {
@@ -94,13 +107,13 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
                                          int64_t base, int64_t lim, const int (&loc)[V],
                                          const int64_t (&dl)[NS][V], uint32_t &flag)
 {
+    const bool o32 = G->out32 != 0;
     if (mode == kEntangled) {
         const int s = 64 - (M - 1) * l;
-        int64_t *o_last = G->out[M - 2] + base;
-        int64_t *o_wrap = G->out[M - 1] + base;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const bool ok = loc[v] < lim;
+            const int64_t at = base + loc[v];
             uint64_t acc = 0;
 #pragma unroll
             for (int t = 0; t < NS - 1; ++t) {
@@ -111,13 +124,12 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
             }
             int64_t cur = ((int64_t)(acc << s)) >> s;  // output of slot M-2
             const int64_t d_prev = cur;
-            if (ok) store_out(o_last + loc[v], cur);
+            if (ok) store_out(G->out[M - 2], at, cur, o32);
 #pragma unroll
             for (int t = NS - 2; t >= 0; --t) {
                 if (t <= M - 2) {
                     cur = (int64_t)((uint64_t)dl[t][v] - (uint64_t)cur) >> l;  // slot t-1
-                    int64_t *o = t == 0 ? o_wrap : G->out[t == 0 ? 0 : t - 1] + base;
-                    if (ok) store_out(o + loc[v], cur);
+                    if (ok) store_out(G->out[t == 0 ? M - 1 : t - 1], at, cur, o32);
                 }
             }
             // cur is the output of slot M-1; delta_{M-1} = d_{M-1} + 2^l d_{M-2}
@@ -142,10 +154,10 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
             for (int t = 0; t < NS - 1; ++t)
                 if (t < M && t != skip) {
                     sum += (uint64_t)dl[t][v];
-                    store_out(G->out[t] + base + loc[v], dl[t][v]);
+                    store_out(G->out[t], base + loc[v], dl[t][v], o32);
                 }
             if (skip >= 0)
-                store_out(G->out[skip] + base + loc[v], (int64_t)(e - sum));
+                store_out(G->out[skip], base + loc[v], (int64_t)(e - sum), o32);
             else if (e != sum)
                 flag |= kFlagMismatch;
         }
@@ -153,10 +165,9 @@ __device__ __forceinline__ void epilogue(const GroupDev *G, int mode, int M, int
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             if (t >= M || t == skip) continue;
-            int64_t *o = G->out[t] + base;
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (loc[v] < lim) store_out(o + loc[v], dl[t][v]);
+                if (loc[v] < lim) store_out(G->out[t], base + loc[v], dl[t][v], o32);
         }
     }
 }
@@ -946,14 +957,30 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
         for (int t = 0; t < NS; ++t) {
             if (t >= M || (mode != kEntangled && mode != kChecksum && t == skip)) continue;
-            int64_t *o = G->out[t] + p;
-            if (full) {
+            if (G->out32) {
+                int32_t *o = (int32_t *)G->out[t] + p;
+                if (full) {
+                    if constexpr (V == 4)
+                        *reinterpret_cast<v4i *>(o) = v4i{(int32_t)dl[t][0], (int32_t)dl[t][1],
+                                                          (int32_t)dl[t][2], (int32_t)dl[t][3]};
+                    else
+                        *reinterpret_cast<int2 *>(o) = int2{(int32_t)dl[t][0], (int32_t)dl[t][1]};
+                } else {
 #pragma unroll
-                for (int v = 0; v < V; v += 2) *reinterpret_cast<I64x2 *>(o + v) = I64x2{dl[t][v], dl[t][v + 1]};
+                    for (int v = 0; v < V; ++v)
+                        if (p + v < n) o[v] = (int32_t)dl[t][v];
+                }
             } else {
+                int64_t *o = G->out[t] + p;
+                if (full) {
 #pragma unroll
-                for (int v = 0; v < V; ++v)
-                    if (p + v < n) o[v] = dl[t][v];
+                    for (int v = 0; v < V; v += 2)
+                        *reinterpret_cast<I64x2 *>(o + v) = I64x2{dl[t][v], dl[t][v + 1]};
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        if (p + v < n) o[v] = dl[t][v];
+                }
             }
         }
     }

@@ -137,7 +137,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         if (u.ring_waves != 0 && u.ring_waves != 1 && u.ring_waves != 4) return fail(NE_EINVAL);
         if (u.tap_copies != 0 && u.tap_copies != 1 && u.tap_copies != 4) return fail(NE_EINVAL);
         if (u.tap_copies == 1 && u.ring_waves == 1) return fail(NE_EINVAL);
-        if (u.reserved != 0) return fail(NE_EINVAL);
+        if (u.word_bits != 0 && u.word_bits != 32 && u.word_bits != 64) return fail(NE_EINVAL);
+        const int w = u.word_bits == 32 ? 32 : 64;
         const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
         const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
         // every operator but the outer product (whose output is n K long)
@@ -186,11 +187,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         int64_t D = 0;
         if (mode == kEntangled) {
             int32_t ll, kk;
-            if (ne_params(u.M, 64, &ll, &kk, &D) != NE_OK) return fail(NE_ERANGE);
+            if (ne_params(u.M, w, &ll, &kk, &D) != NE_OK) return fail(NE_ERANGE);
             l = ll;
             if (bound > (unsigned __int128)D) return fail(NE_ERANGE);
         } else {
-            const unsigned __int128 lim = ((unsigned __int128)1 << 63) - 1;
+            const unsigned __int128 lim = ((unsigned __int128)1 << (w - 1)) - 1;
             const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)u.M : bound;
             if (chk > lim) return fail(NE_ERANGE);
         }
@@ -206,6 +207,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         G.in_hi = u.in_bits == 32 ? INT32_MAX : (int32_t)(((int64_t)1 << (u.in_bits - 1)) - 1);
         G.n = u.n;
         G.K = convlike ? u.n_operand : 0;
+        G.out32 = w == 32;
         G.kind = u.op == NE_OP_CIRC ? kConvCircular : (u.op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
         G.n_out = n_out;
         G.scalar = u.scalar;
@@ -213,14 +215,14 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         for (int t = 0; t < u.M; ++t) {
             const int m = mode == kEntangled ? (G.r + 1 + t) % u.M : t;
             G.c[t] = u.c[m];
-            G.out[t] = u.out[m];
+            G.out[t] = (int64_t *)u.out[m];
         }
         G.operand = u.operand;
         const int cls = G.nslots <= 4 ? 0 : 1;
 
         // Algorithmic traffic and work of one run.
         st.in_bytes += (int64_t)u.M * u.n * 4 + (u.op == NE_OP_SCALE ? 0 : u.n_operand * 4);
-        st.out_bytes += (int64_t)u.M * n_out * 8;
+        st.out_bytes += (int64_t)u.M * n_out * (w / 8);
         st.out_samples += (int64_t)u.M * n_out;
         if (convlike) st.macs += (int64_t)u.M * (u.op == NE_OP_CIRC ? n_out : u.n) * u.n_operand;
         if (u.op == NE_OP_MUL) st.macs += (int64_t)u.M * u.n;
@@ -228,7 +230,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
 
         if (n_out == 0) continue;
         if (convlike) {
-            const DigitCounts dc = conv_digits(mode, u.M, u.in_bits);
+            const DigitCounts dc = conv_digits(mode, u.M, u.in_bits, w);
             const int la = dc.la, lb = dc.lb;
             if (la > kLimbsA || lb > kLimbsB) return fail(NE_EUNSUP);
             G.la = la;

@@ -43,7 +43,7 @@ class GroupC(ctypes.Structure):
                 ("n_operand", ctypes.c_int64), ("scalar", ctypes.c_int64),
                 ("lost", ctypes.c_int32), ("in_bits", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("ring_waves", ctypes.c_int32),
-                ("tap_copies", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tap_copies", ctypes.c_int32), ("word_bits", ctypes.c_int32),
                 ("c", ctypes.c_void_p * FUSED_MAX_M), ("operand", ctypes.c_void_p),
                 ("out", ctypes.c_void_p * FUSED_MAX_M)]
 
@@ -332,19 +332,21 @@ def checksum_recover(d: Sequence, e, r: int, d_r, stream=None):
 
 class GroupSpec:
     """One group for a Plan: M int32 input tensors, an int32 operand (or None
-    for scale), M int64 output tensors of n_out elements."""
+    for scale), M output tensors of n_out elements: int64, or int32 with
+    word_bits = 32 (the paper's 32-bit entangled words)."""
 
     def __init__(self, op: str, c: Sequence, operand, out: Sequence, scalar: int = 0,
                  lost: int = -1, in_bits: int = 32, steps: int = 0, ring_waves: int = 0,
-                 tap_copies: int = 0):
+                 tap_copies: int = 0, word_bits: int = 0):
         self.op, self.c, self.operand, self.out = op, list(c), operand, list(out)
         self.scalar, self.lost, self.in_bits = int(scalar), int(lost), int(in_bits)
         self.steps, self.ring_waves, self.tap_copies = int(steps), int(ring_waves), int(tap_copies)
+        self.word_bits = int(word_bits)
 
     def to_c(self) -> GroupC:
         import torch
         _dtype(self.c, torch.int32, "c")
-        _dtype(self.out, torch.int64, "out")
+        _dtype(self.out, torch.int32 if self.word_bits == 32 else torch.int64, "out")
         if self.operand is not None:
             _dtype([self.operand], torch.int32, "operand")
         g = GroupC()
@@ -358,6 +360,7 @@ class GroupSpec:
         g.steps = self.steps
         g.ring_waves = self.ring_waves
         g.tap_copies = self.tap_copies
+        g.word_bits = self.word_bits
         for m, t in enumerate(self.c):
             g.c[m] = _ptr(t)
         for m, t in enumerate(self.out):

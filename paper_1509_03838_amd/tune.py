@@ -12,7 +12,7 @@ candidate on a few representative groups of each class with HIP events, and
 keeps the fastest per class in a JSON cache on disk, so later plans (and
 later processes) reuse the choice without timing.
 
-Class key: convolution (mode, M, in_bits, K bucket, n bucket); element-wise
+Class key: convolution (mode, M, in_bits, 32-bit words or not, K bucket, n bucket); element-wise
 (mode, op, M <= 4 or not, n bucket); K buckets are powers of two, n buckets
 powers of four.
 """
@@ -39,7 +39,8 @@ def class_key(spec: ne.GroupSpec, mode: str) -> str:
     nb = _bucket(n) // 2
     if spec.op in CONV_LIKE:
         K = spec.operand.numel() if spec.operand is not None else 0
-        return f"{mode}|conv|M{len(spec.c)}|b{spec.in_bits}|K{_bucket(K)}|n{nb}"
+        w = "|w32" if getattr(spec, "word_bits", 0) == 32 else ""
+        return f"{mode}|conv|M{len(spec.c)}|b{spec.in_bits}{w}|K{_bucket(K)}|n{nb}"
     return f"{mode}|{spec.op}|M{'<=4' if len(spec.c) <= 4 else '>4'}|n{nb}"
 
 

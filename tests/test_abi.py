@@ -177,15 +177,17 @@ def test_plan_rejects_misaligned_inputs(lib):
     assert lib.ne_plan_create((ne.GroupC * 1)(g), 1, 0, None, ctypes.byref(h)) == -1
 
 
+@pytest.mark.parametrize("word_bits", [0, 32])
 @pytest.mark.parametrize("mode,m_lo", [(0, 3), (1, 1), (2, 1), (3, 2)])
-def test_every_planned_convolution_has_a_kernel_variant(lib, mode, m_lo):
+def test_every_planned_convolution_has_a_kernel_variant(lib, mode, m_lo, word_bits):
     """The planner picks the digit counts of a convolution group from its
-    declared input bits; a kernel variant must exist for every choice it can
+    declared input bits (and, for entangled and plain-same groups, the word
+    width's shift l); a kernel variant must exist for every choice it can
     make (sizing only: ne_plan_workspace_size touches no device)."""
     accepted = 0
     for M in range(m_lo, 9):
         for bits in range(1, 32):
-            g = _group(M=M, in_bits=bits, n_operand=1)
+            g = _group(M=M, in_bits=bits, n_operand=1, word_bits=word_bits)
             for m in range(M):
                 g.c[m] = FAKE + 256 * m
                 g.out[m] = FAKE + 4096 + 1024 * m
@@ -234,8 +236,26 @@ def test_tap_copies_values(lib, rw, tc, status):
     assert _ws(lib, [g])[0] == status
 
 
-def test_reserved_field_must_be_zero(lib):
-    assert _ws(lib, [_group(reserved=1)])[0] == -1
+@pytest.mark.parametrize("wb,status", [(0, 0), (64, 0), (32, 0), (1, -1), (16, -1), (128, -1)])
+def test_word_bits_values(lib, wb, status):
+    assert _ws(lib, [_group(word_bits=wb, in_bits=6)])[0] == status
+
+
+def test_word32_groups_check_the_narrower_range(lib):
+    """At w = 32 an entangled group's worst case must stay within
+    D = 1,046,528 (M = 3), a plain one within 2^31 - 1; the 64-bit width
+    accepts both. Output bytes per sample halve."""
+    def ws(mode, wb, bits, K, op=0):
+        g = _group(word_bits=wb, in_bits=bits, n_operand=K, op=op)
+        return _ws(lib, [g], mode)[0]
+    assert ws(0, 32, 7, 64) == 0          # 64 * 2^12 = 2^18
+    assert ws(0, 32, 10, 3) == 0          # 3 * 2^18 = 786,432
+    assert ws(0, 32, 10, 4) == -2         # 4 * 2^18 = 1,048,576 > D
+    assert ws(0, 32, 11, 1) == -2         # 2^20 > D
+    assert ws(0, 64, 11, 1) == 0
+    assert ws(1, 32, 16, 1) == 0 and ws(1, 32, 16, 2) == -2   # 2^30, 2^31
+    assert ws(3, 32, 12, 256) == -2       # checksum stream: 3 * 256 * 2^22 > 2^31 - 1
+    assert ws(3, 32, 12, 128) == 0        # 3 * 128 * 2^22 = 3 * 2^29
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])

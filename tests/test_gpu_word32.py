@@ -191,3 +191,144 @@ def test_word32_benchmark_size():
     torch.cuda.synchronize()
     for m in range(M):
         assert np.array_equal(dhat[m], out[m].cpu().numpy()), m
+
+
+# ------------------------------------------------ fused executor, w = 32
+
+MODES = ["entangled", "plain", "plain_same", "checksum"]
+
+
+def fused32(c, op, g, s, mode, lost, bits, K=None, **spec_kw):
+    """One group with word_bits = 32 in a plan: int32 outputs (poisoned
+    first); returns (outputs, flags)."""
+    M, n = c.shape
+    cd = [dev32(row) for row in c]
+    gd = None if g is None else dev32(g)
+    no = ne.n_out(op, n, 0 if g is None else g.size)
+    out = empty32(M, no, fill=POISON)
+    spec = ne.GroupSpec(op, cd, gd, out, s, lost, bits, word_bits=32, **spec_kw)
+    plan = ne.Plan([spec], mode)
+    plan.run()
+    torch.cuda.synchronize()
+    flags = plan.flags()
+    plan.close()
+    return host(out), flags
+
+
+def fused_case(op, M, n, seed, bits):
+    rng = wl.rng(seed)
+    lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+    c = wl.uniform_i32(rng, lo, hi, (M, n))
+    g, s = None, 0
+    if op in ("conv", "circ", "xcorr"):
+        g = wl.uniform_i32(rng, lo, hi, 16)
+    elif op == "perm":
+        g = rng.permutation(n).astype(np.int32)
+    elif op == "scale":
+        s = int(rng.integers(lo, hi))
+    else:
+        g = wl.uniform_i32(rng, lo, hi, n)
+    return c, g, s
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("op", ["conv", "circ", "xcorr", "scale", "add", "sub", "mul", "inner",
+                                "perm"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_fused_word32_matches_oracle(mode, op, M):
+    """Every fused operation in every mode with 32-bit words (l and D of
+    w = 32, int32 outputs): bit-exact against the oracle, every output
+    written, no flag raised; entangled and checksum groups also with a lost
+    stream."""
+    bits = 7 if op != "inner" else 5
+    for n in (1, 5, 3001):
+        c, g, s = fused_case(op, M, n, 9600 + 31 * M + n + len(op), bits)
+        want = oracle.apply(op, c, g, s)
+        if mode == "entangled":
+            # the same values through the oracle's w = 32 pipeline
+            assert np.array_equal(oracle.pipeline(c, op, g, s, r=1, w=32)[0], want)
+        losses = [-1, 1, M - 1] if mode in ("entangled", "checksum") else [-1]
+        for lost in losses:
+            got, flags = fused32(c, op, g, s, mode, lost, bits)
+            assert flags == 0, (mode, op, M, n, lost, flags)
+            assert np.array_equal(got, want), (mode, op, M, n, lost)
+
+
+@pytest.mark.parametrize("mode,m_lo", [("entangled", 3), ("plain_same", 1)])
+def test_fused_word32_every_convolution_variant(mode, m_lo):
+    """Every input width that 32-bit words admit for a convolution (the
+    digit counts follow the shorter shift l of w = 32), each LDS layout,
+    against the oracle; the range check refuses the rest."""
+    ran = 0
+    for M in range(m_lo, 9):
+        for bits in range(1, 17):
+            rng = wl.rng(9700 + 100 * M + bits)
+            lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
+            c = wl.uniform_i32(rng, lo, hi, (M, 1500))
+            g = wl.uniform_i32(rng, lo, hi, 1)
+            want = oracle.apply("conv", c, g)
+            for rw, tc in ((4, 4), (1, 0), (4, 1)):
+                lost = M - 1 if mode == "entangled" else -1
+                try:
+                    got, flags = fused32(c, "conv", g, 0, mode, lost, bits, ring_waves=rw,
+                                         tap_copies=tc)
+                except ne.NeError as e:
+                    assert e.status == -2, (mode, M, bits, e)
+                    continue
+                assert flags == 0, (mode, M, bits, rw, tc)
+                assert np.array_equal(got, want), (mode, M, bits, rw, tc)
+                ran += 1
+    assert ran > 0
+
+
+def test_fused_word32_and_word64_groups_in_one_captured_plan():
+    """Groups of both word widths share the plan's launches; the captured
+    graph is replayed three times with eager work in between, each replay
+    against the oracle."""
+    M, n = 3, 5000
+    rng = wl.rng(9800)
+    specs, wants, outs = [], [], []
+    for wb, op, K in ((32, "conv", 16), (0, "conv", 16), (32, "scale", 0), (0, "add", 0),
+                      (32, "perm", 0), (32, "inner", 0)):
+        bits = 4 if op == "inner" else 8
+        c, g, s = fused_case(op, M, n, int(rng.integers(1 << 30)), bits)
+        cd = [dev32(row) for row in c]
+        no = ne.n_out(op, n, 0 if g is None else g.size)
+        if wb == 32:
+            out = empty32(M, no, fill=POISON)
+        else:
+            out = [torch.full((no,), POISON, dtype=torch.int64, device=DEV) for _ in range(M)]
+        specs.append(ne.GroupSpec(op, cd, None if g is None else dev32(g), out, s, 1, bits,
+                                  word_bits=wb))
+        wants.append(oracle.apply(op, c, g, s))
+        outs.append(out)
+    plan = ne.Plan(specs, "entangled")
+    stream = torch.cuda.Stream()
+    plan.capture(stream)
+    for rep in range(3):
+        for out in outs:
+            for t in out:
+                t.fill_(POISON if t.dtype == torch.int32 else -7)
+        torch.cuda.synchronize()
+        plan.launch(stream)
+        stream.synchronize()
+        assert plan.flags() == 0
+        for out, want in zip(outs, wants):
+            assert np.array_equal(host(out), want), rep
+    plan.close()
+
+
+def test_fused_word32_benchmark_size():
+    """The w = 32 benchmark workload in the fused executor (3 streams of 2^22
+    samples in [-2^7, 2^7), 16 taps, stream 1 lost): sampled outputs against
+    the oracle's convolution at those positions."""
+    M, n, K = 3, 1 << 22, 16
+    rng = wl.rng(wl.SEED_BASE + 11)
+    c = wl.uniform_i32(rng, -128, 128, (M, n))
+    g = wl.uniform_i32(rng, -128, 128, K)
+    got, flags = fused32(c, "conv", g, 0, "entangled", 1, 8)
+    assert flags == 0
+    pos = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n + K - 1),
+                                    wl.rng(8).integers(0, n + K - 1, 4000)]))
+    for m in range(M):
+        assert np.array_equal(got[m, pos], oracle.conv_at(c[m], g, pos)), m
