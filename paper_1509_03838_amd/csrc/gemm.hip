@@ -68,8 +68,12 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
     const int64_t R0 = (int64_t)blockIdx.y * kGemmSplitRows, C0 = (int64_t)blockIdx.x * kGemmSplitCols;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
-    // staging: thread tid copies 16 bytes (segment sg) of row / column sr of every plane
-    const int sr = tid >> 2, sg = (tid & 3) * 16;
+    // staging: thread tid copies 16 bytes (segment sg) of row / column sr of every plane.
+    // The 16 lanes of one LDS write pass take rows 4 apart (j = 4k + i -> row
+    // (k & 3) + 4 i + 16 (k >> 2)): with 80-byte rows their 16-byte pieces
+    // then fall on 16 distinct groups of 4 banks.
+    const int sj = tid >> 2, sk = sj >> 2;
+    const int sr = (sk & 3) + 4 * (sj & 3) + 16 * (sk >> 2), sg = (tid & 3) * 16;
     const unsigned char *ga = job.a[blockIdx.z] + (R0 + sr) * Pp + sg;
     const unsigned char *gb = w.b + (C0 + sr) * Pp + sg;
     const int soff = sr * kDigitRow + sg;
