@@ -98,8 +98,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each GPU would run its own share of groups; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(each GPU would run a plan over its own share of the groups)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -146,9 +146,8 @@ def main():
 
     tuner = None
     if not args.no_autotune and not args.conv_steps and not args.stream_steps:
-        from paper_1509_03838_amd.tune import Tuner
-        tuner = Tuner(os.environ.get("NE_TUNE_CACHE", os.path.join(ROOT, "gpurun_out",
-                                                                   "ne_tune.json")))
+        from paper_1509_03838_amd.tune import DEFAULT_CACHE, Tuner
+        tuner = Tuner(os.environ.get("NE_TUNE_CACHE", DEFAULT_CACHE))
     tuned = {}
 
     def make_plan(mode, lost=-1):
@@ -292,9 +291,8 @@ def fig2_line(args, wl):
     stream = torch.cuda.Stream()
     tuner = None
     if not args.no_autotune and not args.conv_steps:
-        from paper_1509_03838_amd.tune import Tuner
-        tuner = Tuner(os.environ.get("NE_TUNE_CACHE", os.path.join(ROOT, "gpurun_out",
-                                                                   "ne_tune.json")))
+        from paper_1509_03838_amd.tune import DEFAULT_CACHE, Tuner
+        tuner = Tuner(os.environ.get("NE_TUNE_CACHE", DEFAULT_CACHE))
     modes = ("entangled", "plain", "plain_same", "checksum")
     points, tot = [], {m: 0.0 for m in modes}
     samples_all = 0

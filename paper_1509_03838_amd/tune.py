@@ -68,14 +68,18 @@ class Tuner:
                 self.cache = {}
 
     def save(self):
+        """Writes the cache; an unwritable location only loses the reuse."""
         if not self.path:
             return
-        os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
-        tmp = self.path + f".tmp{os.getpid()}"
-        with open(tmp, "w") as f:
-            json.dump({"steps": {k: list(v) for k, v in self.cache.items()}}, f, indent=1,
-                      sort_keys=True)
-        os.replace(tmp, self.path)
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
+            tmp = self.path + f".tmp{os.getpid()}"
+            with open(tmp, "w") as f:
+                json.dump({"steps": {k: list(v) for k, v in self.cache.items()}}, f, indent=1,
+                          sort_keys=True)
+            os.replace(tmp, self.path)
+        except OSError:
+            pass
 
     @staticmethod
     def _apply(specs, choice):
