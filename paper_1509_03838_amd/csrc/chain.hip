@@ -69,21 +69,20 @@ ne_status walk(int64_t n_in, const ne_chain_op *ops, int32_t n_ops, int64_t *n_o
     return NE_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
-                         int32_t n_ops, int64_t *n_out, int64_t *bound)
+// The range bookkeeping of a series in w-bit words (groups of up to max_m
+// streams).
+ne_status check_w(int32_t M, int32_t w, int32_t max_m, int32_t in_bits, int64_t n_in,
+                  const ne_chain_op *ops, int32_t n_ops, int64_t *n_out, int64_t *bound)
 {
-    if (M < 3 || M > kMaxM || in_bits < 1 || in_bits > 32) return NE_EINVAL;
+    if (M < 3 || M > max_m || in_bits < 1 || in_bits > 32) return NE_EINVAL;
     const ne_status st = walk(n_in, ops, n_ops, n_out, nullptr);
     if (st != NE_OK) return st;
     int64_t D = 0;
-    if (ne_params(M, 64, nullptr, nullptr, &D) != NE_OK) return NE_ERANGE;
-    // Worst-case |d| after each stage, in 128 bits; every stage stays <= D
-    // (< 2^62), so no product below can overflow before the comparison.
+    if (ne_params(M, w, nullptr, nullptr, &D) != NE_OK) return NE_ERANGE;
+    // Worst-case |d| after each stage, in 128 bits; products saturate, so an
+    // absurd operand length cannot wrap below D.
     using u128 = unsigned __int128;
+    const auto mul = [](u128 a, u128 b) { return (b != 0 && a > ~(u128)0 / b) ? ~(u128)0 : a * b; };
     u128 B = (u128)1 << (in_bits - 1);
     if (B > (u128)D) return NE_ERANGE;
     int64_t n = n_in;
@@ -93,18 +92,18 @@ ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chai
         switch (o.op) {
         case NE_OP_CONV:
         case NE_OP_CIRC:
-        case NE_OP_XCORR: B = B * G * (u128)o.n_operand; break;
+        case NE_OP_XCORR: B = mul(mul(B, G), (u128)o.n_operand); break;
         case NE_OP_MUL:
-        case NE_OP_OUTER: B = B * G; break;
+        case NE_OP_OUTER: B = mul(B, G); break;
         case NE_OP_SCALE: {
             const u128 s = o.scalar < 0 ? (u128)0 - (u128)(__int128)o.scalar : (u128)o.scalar;
             if (s > ((u128)1 << 62)) return NE_ERANGE;
-            B = B * s;
+            B = mul(B, s);
             break;
         }
         case NE_OP_ADD:
         case NE_OP_SUB: B = B + G; break;
-        case NE_OP_INNER: B = B * G * (u128)std::max<int64_t>(n, 1); break;
+        case NE_OP_INNER: B = mul(mul(B, G), (u128)std::max<int64_t>(n, 1)); break;
         case NE_OP_PERM: break;
         }
         if (B > (u128)D) return NE_ERANGE;
@@ -114,28 +113,82 @@ ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chai
     return NE_OK;
 }
 
-ne_status ne_chain_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
-                                  size_t *bytes)
+ne_status workspace_w(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
+                      size_t word, size_t *bytes)
 {
     if (M < 1 || M > kMaxM || !bytes) return NE_EINVAL;
     int64_t longest = 0;
     const ne_status st = walk(n_in, ops, n_ops, nullptr, &longest);
     if (st != NE_OK) return st;
-    *bytes = n_ops > 1 ? 2 * (size_t)M * align_up((size_t)longest * 8) : 0;
+    *bytes = n_ops > 1 ? 2 * (size_t)M * align_up((size_t)longest * word) : 0;
     return NE_OK;
 }
 
-ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
-                         const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
-                         int64_t n_out, uint32_t stream_mask, void *workspace,
-                         size_t workspace_bytes, ne_stream stream)
+// Word-width traits of the series' execution: the stream tables and the
+// launch of one operation.
+struct Words64 {
+    using W = int64_t;
+    using In = PtrsCI64;
+    using Out = PtrsI64;
+    static ne_status launch(const ne_chain_op &o, int count, int64_t n, const In &cur,
+                            const Out &dst, int64_t m, hipStream_t s)
+    {
+        switch (o.op) {
+        case NE_OP_CONV:
+            launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
+            break;
+        case NE_OP_SCALE: launch_scale_i64(count, n, cur, o.scalar, dst, s); break;
+        case NE_OP_ADD: launch_add_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
+        case NE_OP_INNER:
+            launch_inner_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
+            break;
+        case NE_OP_PERM:
+            launch_perm_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
+            break;
+        case NE_OP_SUB: launch_sub_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
+        case NE_OP_MUL: launch_mul_i64(count, n, cur, (const int32_t *)o.operand, dst, s); break;
+        case NE_OP_CIRC:
+            launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
+                            kConvCircular);
+            break;
+        case NE_OP_XCORR:
+            launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
+                            kConvXcorr);
+            break;
+        case NE_OP_OUTER:
+            launch_outer_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
+            break;
+        }
+        return launch_status();
+    }
+};
+
+struct Words32 {
+    using W = int32_t;
+    using In = PtrsI32;
+    using Out = PtrsW32;
+    static ne_status launch(const ne_chain_op &o, int count, int64_t n, const In &cur,
+                            const Out &dst, int64_t m, hipStream_t s)
+    {
+        launch_op32(o.op, count, n, cur, (const int32_t *)o.operand, o.n_operand, o.scalar, dst,
+                    m, s);
+        return launch_status();
+    }
+};
+
+template <typename T>
+ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
+                  const ne_chain_op *ops, int32_t n_ops, typename T::W *const *delta,
+                  int64_t n_out, uint32_t stream_mask, void *workspace, size_t workspace_bytes,
+                  ne_stream stream)
 {
+    using W = typename T::W;
     if (M < 1 || M > kMaxM || !eps || !delta) return NE_EINVAL;
     int64_t want = 0, longest = 0;
     ne_status st = walk(n_in, ops, n_ops, &want, &longest);
     if (st != NE_OK) return st;
     if (n_out != want) return NE_EINVAL;
-    const size_t plane = align_up((size_t)longest * 8);
+    const size_t plane = align_up((size_t)longest * sizeof(W));
     if (n_ops > 1 && plane > 0) {
         if (!workspace || workspace_bytes < 2 * (size_t)M * plane) return NE_EINVAL;
         if ((uintptr_t)workspace % kWsAlign) return NE_EINVAL;
@@ -148,8 +201,8 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
     if (M < 32) stream_mask &= (1u << M) - 1u;
     // The computed streams, compacted; stage i reads `cur` and writes the
     // workspace buffer (i & 1), or delta for the last stage.
-    PtrsCI64 cur{};
-    PtrsI64 fin{};
+    typename T::In cur{};
+    typename T::Out fin{};
     int count = 0;
     for (int m = 0; m < M; ++m) {
         if (!((stream_mask >> m) & 1u)) continue;
@@ -165,41 +218,15 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
     for (int32_t i = 0; i < n_ops; ++i) {
         const ne_chain_op &o = ops[i];
         const int64_t m = stage_out(o, n);
-        PtrsI64 dst{};
+        typename T::Out dst{};
         if (i + 1 == n_ops) {
             dst = fin;
         } else {
             for (int t = 0; t < count; ++t)
-                dst.p[t] = (int64_t *)(ws + ((size_t)(i & 1) * M + t) * plane);
+                dst.p[t] = (W *)(ws + ((size_t)(i & 1) * M + t) * plane);
         }
         if (m > 0) {
-            switch (o.op) {
-            case NE_OP_CONV:
-                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
-                break;
-            case NE_OP_SCALE: launch_scale_i64(count, n, cur, o.scalar, dst, s); break;
-            case NE_OP_ADD: launch_add_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
-            case NE_OP_INNER:
-                launch_inner_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
-                break;
-            case NE_OP_PERM:
-                launch_perm_i64(count, n, cur, (const int32_t *)o.operand, dst, s);
-                break;
-            case NE_OP_SUB: launch_sub_i64(count, n, cur, (const int64_t *)o.operand, dst, s); break;
-            case NE_OP_MUL: launch_mul_i64(count, n, cur, (const int32_t *)o.operand, dst, s); break;
-            case NE_OP_CIRC:
-                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
-                                kConvCircular);
-                break;
-            case NE_OP_XCORR:
-                launch_conv_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s,
-                                kConvXcorr);
-                break;
-            case NE_OP_OUTER:
-                launch_outer_i64(count, n, cur, (const int32_t *)o.operand, o.n_operand, dst, s);
-                break;
-            }
-            st = launch_status();
+            st = T::launch(o, count, n, cur, dst, m, s);
             if (st != NE_OK) return st;
         }
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
@@ -207,5 +234,52 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
     }
     return NE_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+ne_status ne_chain_check(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
+                         int32_t n_ops, int64_t *n_out, int64_t *bound)
+{
+    return check_w(M, 64, kMaxM, in_bits, n_in, ops, n_ops, n_out, bound);
+}
+
+ne_status ne_chain_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
+                                  size_t *bytes)
+{
+    return workspace_w(M, n_in, ops, n_ops, sizeof(int64_t), bytes);
+}
+
+ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
+                         const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
+                         int64_t n_out, uint32_t stream_mask, void *workspace,
+                         size_t workspace_bytes, ne_stream stream)
+{
+    return apply_w<Words64>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, workspace,
+                            workspace_bytes, stream);
+}
+
+ne_status ne_chain_check32(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
+                           int32_t n_ops, int64_t *n_out, int64_t *bound)
+{
+    return check_w(M, 32, NE_MAX_M32, in_bits, n_in, ops, n_ops, n_out, bound);
+}
+
+ne_status ne_chain_workspace_size32(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                    int32_t n_ops, size_t *bytes)
+{
+    return workspace_w(M, n_in, ops, n_ops, sizeof(int32_t), bytes);
+}
+
+ne_status ne_chain_apply32(int32_t M, int64_t n_in, const int32_t *const *eps,
+                           const ne_chain_op *ops, int32_t n_ops, int32_t *const *delta,
+                           int64_t n_out, uint32_t stream_mask, void *workspace,
+                           size_t workspace_bytes, ne_stream stream)
+{
+    return apply_w<Words32>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, workspace,
+                            workspace_bytes, stream);
+}
+
 
 }  // extern "C"

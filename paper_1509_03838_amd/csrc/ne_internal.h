@@ -23,6 +23,9 @@ struct PtrsCI64 {
 struct PtrsI64 {
     int64_t *p[kMaxM];
 };
+struct PtrsW32 {
+    int32_t *p[kMaxM];
+};
 
 // Records a failed HIP call for ne_last_hip_error() and returns NE_EHIP.
 ne_status hip_fail(hipError_t e);
@@ -87,6 +90,12 @@ void launch_mul_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, co
                     hipStream_t s);
 void launch_outer_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, int64_t K,
                       const PtrsI64 &y, hipStream_t s);
+
+// One LSB operation on `count` int32 streams of 32-bit entangled words
+// (modulo 2^32), shapes already checked; every operand is int32.
+void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const int32_t *operand,
+                 int64_t n_operand, int64_t scalar, const PtrsW32 &y, int64_t n_out,
+                 hipStream_t s);
 
 // Checksum method.
 void launch_checksum(int M, int64_t n, const PtrsI32 &c, int64_t *rsum, hipStream_t s);

@@ -18,10 +18,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-struct PtrsW32 {
-    int32_t *p[kMaxM];
-};
-
 inline unsigned grid_for(int64_t items, int64_t per_block = kBlock, int64_t cap = 1 << 16)
 {
     int64_t g = (items + per_block - 1) / per_block;
@@ -392,6 +388,41 @@ void map32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsW
 }
 
 }  // namespace
+
+void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const int32_t *operand,
+                 int64_t n_operand, int64_t scalar, const PtrsW32 &y, int64_t n_out,
+                 hipStream_t s)
+{
+    const uint32_t sv = (uint32_t)(uint64_t)scalar;
+    switch (op) {
+    case NE_OP_SCALE: map32<kMapScale>(count, n_in, x, nullptr, y, sv, s); break;
+    case NE_OP_ADD: map32<kMapAdd>(count, n_in, x, operand, y, 0, s); break;
+    case NE_OP_SUB: map32<kMapSub>(count, n_in, x, operand, y, 0, s); break;
+    case NE_OP_MUL: map32<kMapMul>(count, n_in, x, operand, y, 0, s); break;
+    case NE_OP_PERM:
+        hipLaunchKernelGGL(k_perm32, dim3(grid_for(n_in, kBlock, 4096), count), dim3(kBlock), 0,
+                           s, x, operand, y, n_in);
+        break;
+    case NE_OP_INNER:
+        hipLaunchKernelGGL(k_zero_first32, dim3(count), dim3(64), 0, s, y);
+        hipLaunchKernelGGL(k_inner32, dim3(grid_for(n_in, kBlock * 8, 1024), count), dim3(kBlock),
+                           0, s, x, operand, y, n_in);
+        break;
+    case NE_OP_OUTER:
+        hipLaunchKernelGGL(k_outer32, dim3(grid_for(n_out, kBlock, 4096), count), dim3(kBlock), 0,
+                           s, x, operand, y, n_in, n_operand);
+        break;
+    default: {  // NE_OP_CONV, NE_OP_CIRC, NE_OP_XCORR
+        const int kind =
+            op == NE_OP_CIRC ? kConvCircular : (op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
+        ConvArgs32 a{x, y, operand, n_in, n_operand, n_out, kind, 0};
+        hipLaunchKernelGGL(k_conv32, dim3((unsigned)((n_out + kTile - 1) / kTile), count),
+                           dim3(kBlock), 0, s, a);
+        break;
+    }
+    }
+}
+
 }  // namespace ne
 
 using namespace ne;
@@ -453,35 +484,8 @@ ne_status ne_lsb_apply32(int32_t op, int32_t M, int64_t n_in, const int32_t *con
         ++count;
     }
     if (count == 0 || n_out == 0) return NE_OK;
-    hipStream_t s = (hipStream_t)stream;
-    const uint32_t sv = (uint32_t)(uint64_t)scalar;
-    switch (op) {
-    case NE_OP_SCALE: map32<kMapScale>(count, n_in, px, nullptr, py, sv, s); break;
-    case NE_OP_ADD: map32<kMapAdd>(count, n_in, px, operand, py, 0, s); break;
-    case NE_OP_SUB: map32<kMapSub>(count, n_in, px, operand, py, 0, s); break;
-    case NE_OP_MUL: map32<kMapMul>(count, n_in, px, operand, py, 0, s); break;
-    case NE_OP_PERM:
-        hipLaunchKernelGGL(k_perm32, dim3(grid_for(n_in, kBlock, 4096), count), dim3(kBlock), 0,
-                           s, px, operand, py, n_in);
-        break;
-    case NE_OP_INNER:
-        hipLaunchKernelGGL(k_zero_first32, dim3(count), dim3(64), 0, s, py);
-        hipLaunchKernelGGL(k_inner32, dim3(grid_for(n_in, kBlock * 8, 1024), count), dim3(kBlock),
-                           0, s, px, operand, py, n_in);
-        break;
-    case NE_OP_OUTER:
-        hipLaunchKernelGGL(k_outer32, dim3(grid_for(n_out, kBlock, 4096), count), dim3(kBlock), 0,
-                           s, px, operand, py, n_in, n_operand);
-        break;
-    default: {  // NE_OP_CONV, NE_OP_CIRC, NE_OP_XCORR
-        const int kind =
-            op == NE_OP_CIRC ? kConvCircular : (op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
-        ConvArgs32 a{px, py, operand, n_in, n_operand, n_out, kind, 0};
-        hipLaunchKernelGGL(k_conv32, dim3((unsigned)((n_out + kTile - 1) / kTile), count),
-                           dim3(kBlock), 0, s, a);
-        break;
-    }
-    }
+    launch_op32(op, count, n_in, px, operand, n_operand, scalar, py, n_out,
+                (hipStream_t)stream);
     return launch_status();
 }
 

@@ -30,7 +30,8 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_plan_stats_get", "ne_plan_destroy", "ne_plan_workspace_size", "ne_plan_create_in",
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
-           "ne_extract_recover32")
+           "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
+           "ne_chain_apply32")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -123,6 +124,12 @@ def load() -> ctypes.CDLL:
         "ne_entangle_operand32": (_i32, [_i32, _i64, _P, _P, _P]),
         "ne_lsb_apply32": (_i32, [_i32, _i32, _i64, _P, _P, _i64, _i64, _P, _i64, _u32, _P]),
         "ne_extract_recover32": (_i32, [_i32, _i32, _i64, _P, _i32, _P, _P]),
+        "ne_chain_check32": (_i32, [_i32, _i32, _i64, ctypes.POINTER(ChainOpC), _i32,
+                                    ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "ne_chain_workspace_size32": (_i32, [_i32, _i64, ctypes.POINTER(ChainOpC), _i32,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+        "ne_chain_apply32": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64,
+                                    _u32, _P, ctypes.c_size_t, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -460,30 +467,34 @@ def _chain_c(ops: Sequence[ChainOp]):
     return (ChainOpC * max(1, len(ops)))(*[o.to_c() for o in ops])
 
 
-def chain_check(M: int, in_bits: int, n_in: int, ops: Sequence[ChainOp]) -> tuple[int, int]:
-    """(output length, worst-case |d| of the last stage) of a series; raises
-    NeError (status -2) if some stage's bound exceeds D."""
+def chain_check(M: int, in_bits: int, n_in: int, ops: Sequence[ChainOp],
+                w: int = 64) -> tuple[int, int]:
+    """(output length, worst-case |d| of the last stage) of a series in w-bit
+    words (64 or 32); raises NeError (status -2) if some stage's bound
+    exceeds D."""
+    fn = "ne_chain_check32" if w == 32 else "ne_chain_check"
     no, b = _i64(), _i64()
-    _check("ne_chain_check", load().ne_chain_check(M, in_bits, n_in, _chain_c(ops), len(ops),
-                                                   ctypes.byref(no), ctypes.byref(b)))
+    _check(fn, getattr(load(), fn)(M, in_bits, n_in, _chain_c(ops), len(ops), ctypes.byref(no),
+                                   ctypes.byref(b)))
     return no.value, b.value
 
 
-def chain_workspace_size(M: int, n_in: int, ops: Sequence[ChainOp]) -> int:
+def chain_workspace_size(M: int, n_in: int, ops: Sequence[ChainOp], w: int = 64) -> int:
+    fn = "ne_chain_workspace_size32" if w == 32 else "ne_chain_workspace_size"
     sz = ctypes.c_size_t()
-    _check("ne_chain_workspace_size", load().ne_chain_workspace_size(M, n_in, _chain_c(ops), len(ops),
-                                                                     ctypes.byref(sz)))
+    _check(fn, getattr(load(), fn)(M, n_in, _chain_c(ops), len(ops), ctypes.byref(sz)))
     return sz.value
 
 
 def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: int | None = None,
-                workspace=None, n_in: int | None = None, stream=None):
+                workspace=None, n_in: int | None = None, stream=None, w: int = 64):
     """delta[m] = the series applied to eps[m], for every stream whose mask
-    bit is set. workspace: a uint8 device tensor of chain_workspace_size
-    bytes (allocated here if None)."""
+    bit is set; int64 words, or int32 words with w = 32. workspace: a uint8
+    device tensor of chain_workspace_size bytes (allocated here if None)."""
     import torch
-    _dtype(eps, torch.int64, "eps")
-    _dtype(delta, torch.int64, "delta")
+    word = torch.int32 if w == 32 else torch.int64
+    _dtype(eps, word, "eps")
+    _dtype(delta, word, "delta")
     M = len(eps)
     if mask is None:
         mask = (1 << M) - 1
@@ -492,16 +503,17 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
     n = n_in
     for o in ops:
         n = n_out(o.op, n, o.n_operand)
-    ws_bytes = chain_workspace_size(M, n_in, ops)
+    ws_bytes = chain_workspace_size(M, n_in, ops, w)
     if workspace is not None and not isinstance(workspace, int) and workspace.numel() < ws_bytes:
         raise ValueError(f"workspace holds {workspace.numel()} bytes, the series needs {ws_bytes}")
     if workspace is None and ws_bytes:
         dev = next(t.device for t in eps if t is not None and not isinstance(t, int))
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
         workspace = workspace[(-workspace.data_ptr()) % 256:]
-    _check("ne_chain_apply", load().ne_chain_apply(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
-                                                   _ptr_array(delta), n, mask & 0xFFFFFFFF,
-                                                   _ptr(workspace), ws_bytes, _stream(stream)))
+    fn = "ne_chain_apply32" if w == 32 else "ne_chain_apply"
+    _check(fn, getattr(load(), fn)(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
+                                   _ptr_array(delta), n, mask & 0xFFFFFFFF, _ptr(workspace),
+                                   ws_bytes, _stream(stream)))
 
 
 def gemm_workspace_size(mode: str, M: int, N: int, P: int, Q: int, in_bits: int) -> int:

@@ -367,6 +367,44 @@ def test_series_workspace_size():
     assert L.ne_chain_apply(3, n, eps, arr, 3, out, 1, 7, FAKE + 8, ws, None) == -1  # misaligned
 
 
+def test_series_in_32_bit_words():
+    """The 32-bit series bounds every stage by D of w = 32 (1,046,528 for
+    M = 3; 2^28 for M = 17, the largest group w = 32 admits), counts int32
+    intermediates, and refuses a short workspace before touching the device."""
+    n = 1000
+    ok = _series(("conv", 16, 0, 8), ("scale", 0, 3, 0))        # 16 * 2^14 * 3 < D
+    bad = _series(("conv", 16, 0, 8), ("scale", 0, 5, 0))       # 16 * 2^14 * 5 > D
+    assert ne.chain_check(3, 8, n, ok, w=32) == (n + 15, 16 * 2**14 * 3)
+    with pytest.raises(ne.NeError) as e:
+        ne.chain_check(3, 8, n, bad, w=32)
+    assert e.value.status == -2
+    assert ne.chain_check(3, 8, n, bad)[1] == 16 * 2**14 * 5      # fits 64-bit words
+    assert ne.chain_check(17, 8, n, bad, w=32)[1] == 16 * 2**14 * 5
+    with pytest.raises(ne.NeError) as e:
+        ne.chain_check(18, 8, n, ok, w=32)
+    assert e.value.status == -1
+    up = lambda x: (x + 255) // 256 * 256
+    assert ne.chain_workspace_size(5, n, ok, w=32) == 2 * 5 * up(4 * (n + 15))
+    assert ne.chain_workspace_size(5, n, ok) == 2 * 5 * up(8 * (n + 15))
+    L = ne.load()
+    eps = ne._ptr_array([FAKE + 64 * m for m in range(3)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 64 * m for m in range(3)])
+    arr = ne._chain_c(ok)
+    ws = ne.chain_workspace_size(3, n, ok, w=32)
+    assert L.ne_chain_apply32(3, n, eps, arr, 2, out, n + 15, 7, FAKE, ws - 1, None) == -1
+    assert L.ne_chain_apply32(3, n, eps, arr, 2, out, n + 14, 7, FAKE, ws, None) == -1
+
+
+def test_series_bound_saturates():
+    """An absurd operand length cannot wrap the 128-bit bound below D:
+    2^40 (after scaling 2^31 by 2^9) times 2^31 times 2^62 taps is 2^133,
+    which modulo 2^128 would be 32."""
+    ops = _series(("scale", 0, 1 << 9, 0), ("conv", 1 << 62, 0, 32))
+    with pytest.raises(ne.NeError) as e:
+        ne.chain_check(3, 32, 1, ops)
+    assert e.value.status == -2
+
+
 def test_series_of_empty_streams_needs_no_workspace(lib):
     """Streams of length 0: every stage is empty, the workspace size is 0,
     NULL stream and workspace pointers are accepted and nothing is

@@ -332,3 +332,58 @@ def test_fused_word32_benchmark_size():
                                     wl.rng(8).integers(0, n + K - 1, 4000)]))
     for m in range(M):
         assert np.array_equal(got[m, pos], oracle.conv_at(c[m], g, pos)), m
+
+
+# ------------------------------------------------- series, w = 32
+
+SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
+          ("perm", "add", "conv", "inner"), ("sub", "mul", "circ", "xcorr"),
+          ("outer", "sub", "perm")]
+
+
+def series32(c, ops, lost, bits):
+    """entangle32 -> the series on every stream but `lost` (ne_chain_apply32)
+    -> extract32; returns (recovered outputs, last-stage words)."""
+    M, n = c.shape
+    l = ne.params(M, 32)[0]
+    dops = []
+    for op, g, s in ops:
+        if op == "scale":
+            dops.append(ne.ChainOp(op, None, s))
+            continue
+        dg = dev32(g)
+        if op in ("add", "sub"):
+            ge = empty32(1, g.size)[0]
+            ne.entangle_operand32(dg, ge, l)
+            dg = ge
+        dops.append(ne.ChainOp(op, dg, s, operand_bits=bits))
+    no, _ = ne.chain_check(M, bits, n, dops, w=32)
+    cd = [dev32(r) for r in c]
+    eps = empty32(M, n)
+    ne.entangle32(cd, eps, l, n=n)
+    delta = empty32(M, no, fill=POISON)
+    mask = ((1 << M) - 1) & ~(1 << lost if lost >= 0 else 0)
+    ne.chain_apply(eps, dops, delta, mask=mask, n_in=n, w=32)
+    dhat = empty32(M, no, fill=POISON)
+    ne.extract_recover32([None if m == lost else delta[m] for m in range(M)], lost, dhat, l, n=no)
+    return host(dhat), host(delta)
+
+
+@pytest.mark.parametrize("recipe", SERIES)
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_word32_series_matches_oracle(recipe, M):
+    """A series between one entanglement and one extraction in 32-bit words
+    (2-bit samples and operands keep every stage within D of w = 32):
+    the recovered outputs equal the plain series, the live streams' last
+    stage equals the oracle's w = 32 pipeline, for no loss and two losses."""
+    n = 3001
+    rng = wl.rng(9900 + M + len(recipe))
+    c = wl.uniform_i32(rng, -2, 2, (M, n))
+    ops = wl.chain_series(rng, n, recipe, bits=2, K=9)
+    want = oracle.chain(c, ops)
+    _, last = oracle.chain_pipeline(c, ops, r=0, w=32)
+    for lost in (-1, 0, M - 1):
+        dhat, delta = series32(c, ops, lost, 2)
+        assert np.array_equal(dhat, want), (recipe, M, lost)
+        live = [m for m in range(M) if m != lost]
+        assert np.array_equal(delta[live], last[live]), (recipe, M, lost)
