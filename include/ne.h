@@ -8,7 +8,8 @@
  *   1. entangle  (Sec. III, eq. (6), (14)-(15)): M >= 3 integer input streams
  *      c_m are superimposed pairwise into M entangled streams
  *          eps_m = c_m + S_l{c_{(m-1) mod M}}
- *      held in 64-bit words (w = 64);
+ *      held in 64-bit words (w = 64), or in the paper's practical 32-bit
+ *      words (w = 32: the ne_*32 calls and ne_group.word_bits);
  *   2. lsb_apply (eq. (2), (9)): one linear, sesquilinear or bijective
  *      operation runs on every entangled stream independently,
  *          delta_m = eps_m op g;
@@ -33,10 +34,11 @@
  *    errors are reported synchronously, before anything is enqueued;
  *    asynchronous HIP errors surface on a later call or on the caller's
  *    synchronisation. Calls on distinct streams are thread-safe.
- *  - Integer arithmetic on 64-bit words wraps modulo 2^64. That is exact for
- *    this method: the admissible output range of eq. (11)/(13) guarantees
- *    every entangled output fits in 64 bits, and wrap-around arithmetic is a
- *    ring homomorphism, so intermediate wrap-around cancels.
+ *  - Integer arithmetic on 64-bit words wraps modulo 2^64 (on 32-bit words,
+ *    modulo 2^32). That is exact for this method: the admissible output
+ *    range of eq. (11)/(13) guarantees every entangled output fits in the
+ *    word, and wrap-around arithmetic is a ring homomorphism, so
+ *    intermediate wrap-around cancels.
  *  - Lengths are element counts (int64). A length of 0 is valid and
  *    enqueues nothing; a device pointer whose buffer has length 0 is never
  *    dereferenced and may be NULL (host pointer arrays may not).
