@@ -590,8 +590,8 @@ def ops_line(args, wl):
     subtraction, element-by-element product, circular convolution (64 taps),
     cross-correlation (64 taps) and outer product (8 values), 3 streams of
     2^22 samples in [-2^9, 2^9) through entangle -> op -> extract, against
-    the plain op on the raw streams; and, for all but the outer product, the
-    same operation in the fused executor (one pass, one captured launch)."""
+    the plain op on the raw streams; and the same operation in the fused
+    executor (one pass, one captured launch)."""
     import numpy as np
     import torch
     from paper_1509_03838_amd import ne
@@ -645,17 +645,16 @@ def ops_line(args, wl):
         if not torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref):
             raise SystemExit(f"ops: {op} entangled and plain results differ")
         fused = {}
-        if op != "outer":
-            # the same operation in the fused executor: one pass, one captured launch
-            for mode in ("entangled", "plain"):
-                spec = ne.GroupSpec(op, cd, g32, dhat, 0, -1, bits)
-                plan = ne.Plan([spec], mode)
-                plan.capture(stream)
-                fused[mode], _ = time_captured(torch, plan, stream, args.steps, args.warmup)
-                same = torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref)
-                if plan.flags() or not same:
-                    raise SystemExit(f"ops: fused {op} ({mode}) differs from the per-step result")
-                plan.close()
+        # the same operation in the fused executor: one pass, one captured launch
+        for mode in ("entangled", "plain"):
+            spec = ne.GroupSpec(op, cd, g32, dhat, 0, -1, bits)
+            plan = ne.Plan([spec], mode)
+            plan.capture(stream)
+            fused[mode], _ = time_captured(torch, plan, stream, args.steps, args.warmup)
+            same = torch.equal(torch.stack([t[::4099] for t in dhat]).cpu(), ref)
+            if plan.flags() or not same:
+                raise SystemExit(f"ops: fused {op} ({mode}) differs from the per-step result")
+            plan.close()
         # algorithmic HBM bytes of the three launches: entangle, op, extract
         nb = (M * n * 12 + M * (n + no) * 8 + operand.numel() * operand.element_size() +
               (2 * M - 1) * no * 8)

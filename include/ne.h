@@ -74,8 +74,8 @@ typedef enum ne_op {
     NE_OP_ADD = 2,   /* y[i] = x[i] + g[i] (element-wise addition) */
     NE_OP_INNER = 3, /* y[0] = sum_i x[i] g[i] (inner product) */
     NE_OP_PERM = 4,  /* y[i] = x[p[i]] for a fixed bijection p (footnote 2) */
-    /* The other operators eq. (2) lists (per-step calls and series; the
-       batched executor runs all of them but NE_OP_OUTER): */
+    /* The other operators eq. (2) lists (per-step calls, series and the
+       batched executor): */
     NE_OP_SUB = 5,   /* y[i] = x[i] - g[i] (element-wise subtraction) */
     NE_OP_MUL = 6,   /* y[i] = x[i] g[i] (element-by-element product) */
     NE_OP_CIRC = 7,  /* circular convolution of length n with K taps:
@@ -430,11 +430,11 @@ typedef enum ne_mode {
 
 /* One group: M streams of n int32 samples sharing one operand. */
 typedef struct ne_group {
-    int32_t op;          /* ne_op: any but NE_OP_OUTER */
+    int32_t op;          /* ne_op: any of the ten */
     int32_t M;           /* streams: 3..8 (entangled), 2..8 (checksum), 1..8 */
     int64_t n;           /* samples per stream (>= 0) */
-    int64_t n_operand;   /* K taps (conv, circ, xcorr), n (add, sub, mul, inner,
-                            perm), 0 (scale) */
+    int64_t n_operand;   /* K taps (conv, circ, xcorr), K values (outer: n K
+                            outputs), n (add, sub, mul, inner, perm), 0 (scale) */
     int64_t scalar;      /* scale factor (NE_OP_SCALE) */
     int32_t lost;        /* -1, or the stream whose operation is dropped */
     int32_t in_bits;     /* 1..31 (conv, circ, xcorr) or 1..32: every sample and operand

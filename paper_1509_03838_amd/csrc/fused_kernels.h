@@ -834,7 +834,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     const GroupDev *G = groups + it.g;
     const int skip = G->skip, l = G->l;
     const int steps = G->steps;
-    const int64_t n = G->n, sv = G->scalar;
+    // the outer product iterates over its n K outputs: output o takes input
+    // o / K and operand value o mod K
+    const int64_t n = op == NE_OP_OUTER ? G->n_out : G->n, sv = G->scalar;
+    const int64_t K = G->K;
     const int32_t *__restrict__ opd = G->operand;
     uint32_t flag = 0;
     Bounds bd;
@@ -848,8 +851,22 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
         const int64_t p = pb + V * threadIdx.x;
         const bool full = p + V <= n;
         int64_t src[V];
+        int64_t gj[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) src[v] = p + v < n ? p + v : 0;
+        if (op == NE_OP_OUTER) {
+            // one division per lane and step; (i, j) then advance by one
+            int64_t i = p / K, j = p - i * K;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                src[v] = p + v < n ? i : 0;
+                gj[v] = p + v < n ? j : 0;
+                if (++j == K) {
+                    j = 0;
+                    ++i;
+                }
+            }
+        }
         if (op == NE_OP_PERM) {
             if (full) {
                 load_vec<V>(opd + p, src);
@@ -861,7 +878,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
             for (int v = 0; v < V; ++v) src[v] = src[v] < 0 ? 0 : (src[v] >= n ? n - 1 : src[v]);
         }
         auto load = [&](const int32_t *base, int32_t (&x)[V]) {
-            if (op != NE_OP_PERM && full) {
+            if (op != NE_OP_PERM && op != NE_OP_OUTER && full) {
                 load_vec<V>(base + p, x);
             } else {
 #pragma unroll
@@ -922,6 +939,12 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) bd.add(gv[v]);
+        } else if (op == NE_OP_OUTER) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                gv[v] = p + v < n ? opd[gj[v]] : 0;
+                bd.add(gv[v]);
+            }
         }
         int64_t dl[NS][V];
 #pragma unroll
@@ -945,7 +968,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
                 case NE_OP_SCALE: y = (uint64_t)x * (uint64_t)sv; break;
                 case NE_OP_ADD: y = (uint64_t)x + (uint64_t)gs; break;
                 case NE_OP_SUB: y = (uint64_t)x - (uint64_t)gs; break;
-                case NE_OP_MUL: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
+                case NE_OP_MUL:
+                case NE_OP_OUTER: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
                 case NE_OP_INNER: y = (uint64_t)x * (uint64_t)(int64_t)gv[v]; break;
                 default: y = (uint64_t)x; break;  // permutation: the gather above
                 }

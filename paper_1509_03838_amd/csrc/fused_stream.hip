@@ -1,6 +1,6 @@
 // Fused element-wise kernel variants of one kernel class (-DNE_KCLASS=k):
-// scale, add, inner product, permutation, subtraction and element-by-element
-// product for every slot count the class
+// scale, add, inner product, permutation, subtraction, element-by-element
+// product and outer product for every slot count the class
 // has (entangled 3..8, plain 1..8, checksum 3..9).
 #include "fused_kernels.h"
 
@@ -39,17 +39,20 @@ constexpr StreamLaunch entry()
     {entry<OP, 1>(), entry<OP, 2>(), entry<OP, 3>(), entry<OP, 4>(), entry<OP, 5>(),       \
      entry<OP, 6>(), entry<OP, 7>(), entry<OP, 8>(), entry<OP, 9>()}
 // rows: scale, add, inner product, permutation, subtraction, product
-// (NE_OP_SCALE .. NE_OP_MUL)
-const StreamLaunch table[6][kMaxSlots] = {NE_ROW(NE_OP_SCALE), NE_ROW(NE_OP_ADD),
+// (NE_OP_SCALE .. NE_OP_MUL), then the outer product
+const StreamLaunch table[7][kMaxSlots] = {NE_ROW(NE_OP_SCALE), NE_ROW(NE_OP_ADD),
                                           NE_ROW(NE_OP_INNER), NE_ROW(NE_OP_PERM),
-                                          NE_ROW(NE_OP_SUB),   NE_ROW(NE_OP_MUL)};
+                                          NE_ROW(NE_OP_SUB),   NE_ROW(NE_OP_MUL),
+                                          NE_ROW(NE_OP_OUTER)};
 #undef NE_ROW
 
 }  // namespace
 
 StreamLaunch NE_NAME(stream_kernel_, NE_KCLASS)(int op, int slots)
 {
-    if (op < NE_OP_SCALE || op > NE_OP_MUL || slots < 1 || slots > kMaxSlots) return nullptr;
+    if (slots < 1 || slots > kMaxSlots) return nullptr;
+    if (op == NE_OP_OUTER) return table[6][slots - 1];
+    if (op < NE_OP_SCALE || op > NE_OP_MUL) return nullptr;
     return table[op - NE_OP_SCALE][slots - 1];
 }
 

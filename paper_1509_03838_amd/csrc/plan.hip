@@ -141,8 +141,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         const int w = u.word_bits == 32 ? 32 : 64;
         const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
         const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
-        // every operator but the outer product (whose output is n K long)
-        if (u.op < NE_OP_CONV || u.op > NE_OP_XCORR) return fail(NE_EUNSUP);
+        if (u.op < NE_OP_CONV || u.op > NE_OP_OUTER) return fail(NE_EUNSUP);
         const bool convlike = u.op == NE_OP_CONV || u.op == NE_OP_CIRC || u.op == NE_OP_XCORR;
         for (int m = 0; m < u.M; ++m) {
             if (!u.c[m] || !u.out[m] || !aligned(u.c[m], 16) || !aligned(u.out[m], 16))
@@ -158,6 +157,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             break;
         case NE_OP_SCALE: n_out = u.n; break;
         case NE_OP_INNER: n_out = 1; break;
+        case NE_OP_OUTER:
+            if (u.n_operand < 0 || (u.n_operand > 0 && !u.operand)) return fail(NE_EINVAL);
+            if (u.n_operand > 0 && u.n > INT64_MAX / u.n_operand) return fail(NE_EUNSUP);
+            n_out = u.n * u.n_operand;
+            break;
         default: n_out = u.n; break;
         }
         if (u.op == NE_OP_ADD || u.op == NE_OP_SUB || u.op == NE_OP_MUL || u.op == NE_OP_INNER ||
@@ -179,7 +183,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         case NE_OP_SCALE: bound = B * s_abs; break;
         case NE_OP_ADD:
         case NE_OP_SUB: bound = 2 * B; break;
-        case NE_OP_MUL: bound = B * B; break;
+        case NE_OP_MUL:
+        case NE_OP_OUTER: bound = B * B; break;
         case NE_OP_INNER: bound = B * B * (unsigned __int128)(u.n > 0 ? u.n : 1); break;
         case NE_OP_PERM: bound = B; break;
         }
@@ -206,7 +211,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         G.in_lo = u.in_bits == 32 ? INT32_MIN : -(int32_t)((int64_t)1 << (u.in_bits - 1));
         G.in_hi = u.in_bits == 32 ? INT32_MAX : (int32_t)(((int64_t)1 << (u.in_bits - 1)) - 1);
         G.n = u.n;
-        G.K = convlike ? u.n_operand : 0;
+        G.K = (convlike || u.op == NE_OP_OUTER) ? u.n_operand : 0;
         G.out32 = w == 32;
         G.kind = u.op == NE_OP_CIRC ? kConvCircular : (u.op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
         G.n_out = n_out;
@@ -226,6 +231,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         st.out_samples += (int64_t)u.M * n_out;
         if (convlike) st.macs += (int64_t)u.M * (u.op == NE_OP_CIRC ? n_out : u.n) * u.n_operand;
         if (u.op == NE_OP_MUL) st.macs += (int64_t)u.M * u.n;
+        if (u.op == NE_OP_OUTER) st.macs += (int64_t)u.M * n_out;
         if (u.op == NE_OP_INNER) st.macs += (int64_t)u.M * u.n;
 
         if (n_out == 0) continue;
@@ -309,7 +315,10 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = g_stream_steps;
             const int64_t strip = (int64_t)g_stream_steps * 256 * stream_positions(G.nslots);
-            const int64_t nstrips = (u.n + strip - 1) / strip;
+            // (the outer product's lanes run over its n K outputs)
+            const int64_t nit = u.op == NE_OP_OUTER ? n_out : u.n;
+            const int64_t nstrips = (nit + strip - 1) / strip;
+            if (nstrips > ((int64_t)1 << 24)) return fail(NE_EUNSUP);  // work-item table size
             const int kclass = conv_class_of_mode(mode);
             if (!stream_kernel(u.op, kclass, G.nslots)) return fail(NE_EUNSUP);
             auto key = std::make_tuple(0, (u.op * 4 + kclass) * 16 + G.nslots, 0, 0);

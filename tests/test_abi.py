@@ -157,7 +157,7 @@ def _group(**kw):
     ({"M": 2}, -1),                      # entangled needs M >= 3
     ({"M": 9}, -1),                      # above the fused limit
     ({"lost": 3}, -3),                   # failed index out of range
-    ({"op": 9}, -4),                     # the outer product: per-step calls only
+    ({"op": 9, "n_operand": -1}, -1),    # the outer product needs K >= 0
     ({"op": 10}, -4),                    # unknown operation
     ({"n_operand": 0}, -1),              # convolution without taps
     ({"in_bits": 32}, -1),               # 32-bit convolution operands
@@ -234,6 +234,17 @@ def test_tap_copies_values(lib, rw, tc, status):
     """One tap copy exists only with a block ring."""
     g = _group(ring_waves=rw, tap_copies=tc)
     assert _ws(lib, [g])[0] == status
+
+
+def test_outer_product_plans(lib):
+    """The batched executor plans the outer product over its n K outputs:
+    the worst case 2^(b-1) 2^(b-1), no taps needed (K = 0 plans nothing),
+    and an n K beyond the work-item table is refused."""
+    assert _ws(lib, [_group(op=9, n_operand=8)])[0] == 0
+    assert _ws(lib, [_group(op=9, n_operand=0, operand=0)])[0] == 0
+    assert _ws(lib, [_group(op=9, n_operand=8, in_bits=32)], 1)[0] == 0      # plain: 2^62
+    assert _ws(lib, [_group(op=9, n_operand=8, in_bits=22)])[0] == -2        # 2^42 > D(3)
+    assert _ws(lib, [_group(op=9, n=1 << 40, n_operand=1 << 10, in_bits=4)])[0] == -4
 
 
 @pytest.mark.parametrize("wb,status", [(0, 0), (64, 0), (32, 0), (1, -1), (16, -1), (128, -1)])

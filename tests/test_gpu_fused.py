@@ -284,11 +284,11 @@ def test_sparse_top_tap_digit_windows(ring_waves, tap_copies):
 
 def make_more(op, M, n, K, bits, seed):
     """Subtraction and product take a vector of n values, circular
-    convolution and cross-correlation K taps."""
+    convolution and cross-correlation K taps, the outer product K values."""
     g = wl.rng(seed)
     lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
     c = wl.uniform_i32(g, lo, hi, (M, n))
-    operand = wl.uniform_i32(g, lo, hi, K if op in ("circ", "xcorr") else n)
+    operand = wl.uniform_i32(g, lo, hi, K if op in ("circ", "xcorr", "outer") else n)
     return wl.Group(op, c, operand, 0)
 
 
@@ -308,6 +308,23 @@ def test_more_streaming_ops_fused(mode, op, M):
             _, flags = run([dg], mode)
             assert flags == 0
             assert np.array_equal(dg.result(), ref), (mode, op, M, n, lost)
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("M", [3, 5, 8])
+@pytest.mark.parametrize("n,K", [(1, 1), (5, 3), (1001, 1), (777, 13), (4097, 64), (3, 1500)])
+def test_outer_product_fused(mode, M, n, K):
+    """The outer product in the element-wise fused kernel: lanes over the
+    n K outputs (input o / K, operand value o mod K), ragged in both, every
+    mode and loss position; outputs equal the oracle's row-major product."""
+    grp = make_more("outer", M, n, K, 10, seed=n * 7 + K + M)
+    ref = oracle.apply("outer", grp.c, grp.operand)
+    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+    for lost in losses:
+        dg = DevGroup(grp, 10, lost, mode)
+        _, flags = run([dg], mode)
+        assert flags == 0
+        assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost)
 
 
 @pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
@@ -334,17 +351,19 @@ def test_circular_and_cross_correlation_fused(mode, op, M, n, K, bits):
             assert np.array_equal(dg.result(), ref), (mode, op, M, n, K, lost, rw, tc)
 
 
-def test_all_fused_operators_in_one_captured_plan():
-    """Groups of all nine fused operators with uneven M, lengths and losses
-    in one plan, captured as a graph and replayed twice with eager work in
-    between: every replay matches the oracle."""
+def test_all_operators_in_one_captured_plan():
+    """Groups of all ten operators with uneven M, lengths and losses in one
+    plan, captured as a graph and replayed twice with eager work in between:
+    every replay matches the oracle."""
     rng = wl.rng(4242)
     specs = []
     for i, op in enumerate(["conv", "scale", "add", "inner", "perm", "sub", "mul", "circ",
-                            "xcorr"] * 3):
+                            "xcorr", "outer"] * 3):
         M = int(rng.integers(3, 9))
         n = int(rng.integers(1, 20000))
-        if op in ("conv", "circ", "xcorr"):
+        if op == "outer":
+            grp = make_more(op, M, n // 16 + 1, int(rng.integers(1, 40)), 10, seed=5000 + i)
+        elif op in ("conv", "circ", "xcorr"):
             grp = make_more("circ", M, n, int(rng.integers(1, 300)), 10, seed=5000 + i)
             grp = wl.Group(op, grp.c, grp.operand, 0)
         elif op in ("sub", "mul"):

@@ -220,7 +220,7 @@ def fused_case(op, M, n, seed, bits):
     lo, hi = -(1 << (bits - 1)), 1 << (bits - 1)
     c = wl.uniform_i32(rng, lo, hi, (M, n))
     g, s = None, 0
-    if op in ("conv", "circ", "xcorr"):
+    if op in ("conv", "circ", "xcorr", "outer"):
         g = wl.uniform_i32(rng, lo, hi, 16)
     elif op == "perm":
         g = rng.permutation(n).astype(np.int32)
@@ -233,7 +233,7 @@ def fused_case(op, M, n, seed, bits):
 
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("op", ["conv", "circ", "xcorr", "scale", "add", "sub", "mul", "inner",
-                                "perm"])
+                                "perm", "outer"])
 @pytest.mark.parametrize("M", [3, 5, 8])
 def test_fused_word32_matches_oracle(mode, op, M):
     """Every fused operation in every mode with 32-bit words (l and D of
