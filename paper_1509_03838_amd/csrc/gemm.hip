@@ -36,6 +36,14 @@ struct DigitJob {
 };
 
 typedef __attribute__((address_space(1))) const fk::v4i gcv4i_t;
+typedef __attribute__((address_space(1))) int64_t gi64_t;
+
+// The product's int64 outputs are written once: non-temporal stores (the
+// plain and checksum calls measured 2-7% faster).
+__device__ __forceinline__ void store_nt(int64_t *p, int64_t v)
+{
+    __builtin_nontemporal_store(v, (gi64_t *)p);
+}
 
 // Phase 2: slot blockIdx.z's product. The block stages each 64-deep chunk
 // of its 64 A rows and 64 B columns (all digit planes) in LDS once -- 16-byte
@@ -148,7 +156,7 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
                 uint64_t y = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
 #pragma unroll
                 for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
-                if (row < N && col < Q) fk::store_out(d + row * Q + col, (int64_t)y);
+                if (row < N && col < Q) store_nt(d + row * Q + col, (int64_t)y);
             }
         }
 }
