@@ -30,7 +30,8 @@
  *    buffer per stream (structure of arrays). Streams within a call must not
  *    overlap unless a function says that aliasing is allowed.
  *  - `stream` is a hipStream_t (NULL is the null stream). Work is enqueued
- *    asynchronously; the library never synchronises the device. Argument
+ *    asynchronously; the library synchronises the device only in the
+ *    calls documented as synchronous (ne_device_flags, ne_plan_flags). Argument
  *    errors are reported synchronously, before anything is enqueued;
  *    asynchronous HIP errors surface on a later call or on the caller's
  *    synchronisation. Calls on distinct streams are thread-safe.
@@ -96,6 +97,17 @@ int32_t ne_last_hip_error(void);
 int32_t ne_version(void);
 
 /*
+ * The device flag word of the per-step calls on the calling thread's
+ * current device: NE_FLAG_* bits (below) that kernels raised since the
+ * last clear -- today NE_FLAG_PERM_INDEX from NE_OP_PERM. Every call
+ * that uses the device shares the word, so a bit names the kind of error,
+ * not the call. Synchronous: waits for all work on the device, then reads
+ * (and, with clear != 0, zeroes) the word. flags: host output.
+ * Errors: NE_EINVAL (NULL flags), NE_EHIP.
+ */
+ne_status ne_device_flags(uint32_t *flags, int32_t clear);
+
+/*
  * Parameters (Sec. III-A eq. (8), Sec. III-B eq. (12), Table I, eq. (11),
  * eq. (13)). For M streams in w-bit words, returns the shift l, the headroom
  * k and D, the largest output magnitude the method recovers exactly:
@@ -150,8 +162,12 @@ ne_status ne_entangle_operand(int32_t l, int64_t n, const int32_t *g, int64_t *g
  *                ne_entangle_operand); n_out = n_in
  *   NE_OP_INNER: operand = int32 vector of n_operand = n_in; n_out = 1
  *   NE_OP_PERM : operand = int32 indices p of n_operand = n_in, a
- *                permutation of [0, n_in) (not checked; an index outside
- *                the range is clamped into it); n_out = n_in
+ *                permutation of [0, n_in); n_out = n_in. The indices live
+ *                on the device and the call is asynchronous, so they are
+ *                checked there: an index outside [0, n_in) reads nothing,
+ *                its output is 0 and NE_FLAG_PERM_INDEX is raised in the
+ *                library's device flag word (ne_device_flags). Repeated
+ *                in-range indices are not detected.
  *   NE_OP_SUB  : as NE_OP_ADD (the operand entangled likewise)
  *   NE_OP_MUL  : operand = int32 vector of n_operand = n_in; n_out = n_in
  *   NE_OP_CIRC : operand = int32 kernel of K >= 1 taps (K may exceed
@@ -427,6 +443,9 @@ typedef enum ne_mode {
 #define NE_FLAG_LIMBS 2u       /* reserved, never raised: digit counts follow
                                   in_bits, which every input is checked against */
 #define NE_FLAG_MISMATCH 4u    /* redundant stream disagrees with the outputs */
+#define NE_FLAG_PERM_INDEX 8u  /* a permutation index outside [0, n): that
+                                  output is undefined (ne_plan_flags) or 0
+                                  (the per-step calls, ne_device_flags) */
 
 /* One group: M streams of n int32 samples sharing one operand. */
 typedef struct ne_group {

@@ -1,8 +1,10 @@
 // C-ABI of libne (include/ne.h): argument validation, stream-mask
 // compaction, the stream rotation used by recovery, and dispatch to the
-// kernels. Nothing here allocates memory or synchronises the device.
+// kernels. Nothing here allocates memory; only ne_device_flags (documented
+// as synchronous) synchronises the device.
 #include <string.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "ne_internal.h"
@@ -60,6 +62,34 @@ ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t 
     }
 }
 
+// The per-step kernels' device flag word: one copy per device (each device
+// that loads the library's code object holds its own), found by symbol
+// lookup with that device current and cached per device.
+static __device__ uint32_t g_device_flags;
+
+uint32_t *device_flag_word()
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static uint32_t *addr[kDevices];
+    static bool done[kDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_device_flags)) == hipSuccess)
+            addr[dev] = (uint32_t *)p;
+        else
+            (void)hipGetLastError();
+        done[dev] = true;
+    }
+    return addr[dev];
+}
+
 }  // namespace ne
 
 using namespace ne;
@@ -103,7 +133,21 @@ const char *ne_strerror(ne_status s)
 
 int32_t ne_last_hip_error(void) { return g_last_hip_error; }
 
-int32_t ne_version(void) { return 10000 * 0 + 100 * 1 + 0; }
+int32_t ne_version(void) { return 10000 * 0 + 100 * 2 + 0; }
+
+ne_status ne_device_flags(uint32_t *flags, int32_t clear)
+{
+    if (!flags) return NE_EINVAL;
+    uint32_t *w = device_flag_word();
+    if (!w) return hip_fail(hipErrorInvalidSymbol);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(flags, w, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && clear) {
+        const uint32_t z = 0;
+        e = hipMemcpy(w, &z, sizeof(uint32_t), hipMemcpyHostToDevice);
+    }
+    return e == hipSuccess ? NE_OK : hip_fail(e);
+}
 
 // Closed form of the Table I rule: the output bit-width (M-2)l + k with
 // k = w - (M-1)l is w - l, which decreases in l, while k <= l needs

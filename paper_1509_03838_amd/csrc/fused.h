@@ -33,7 +33,8 @@ enum Mode : int32_t {
 enum Flag : uint32_t {
     kFlagInputRange = 1u,   // an input or operand value outside the declared bits
     kFlagLimbs = 2u,        // reserved: digit counts follow the declared (checked) range
-    kFlagMismatch = 4u      // the redundant stream disagreed with the recovered outputs
+    kFlagMismatch = 4u,     // the redundant stream disagreed with the recovered outputs
+    kFlagPermIndex = 8u     // a permutation index outside [0, n)
 };
 
 struct GroupDev {

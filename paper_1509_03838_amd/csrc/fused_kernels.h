@@ -874,8 +874,15 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
                 for (int v = 0; v < V; ++v) src[v] = p + v < n ? opd[p + v] : 0;
             }
+            // an index outside [0, n) is not a permutation index: it is
+            // flagged, and row 0 is read in its place (defined memory)
 #pragma unroll
-            for (int v = 0; v < V; ++v) src[v] = src[v] < 0 ? 0 : (src[v] >= n ? n - 1 : src[v]);
+            for (int v = 0; v < V; ++v) {
+                if (src[v] < 0 || src[v] >= n) {
+                    flag |= kFlagPermIndex;
+                    src[v] = 0;
+                }
+            }
         }
         auto load = [&](const int32_t *base, int32_t (&x)[V]) {
             if (op != NE_OP_PERM && op != NE_OP_OUTER && full) {

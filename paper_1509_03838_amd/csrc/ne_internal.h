@@ -31,6 +31,11 @@ struct PtrsW32 {
 ne_status hip_fail(hipError_t e);
 // Checks hipGetLastError() after a launch.
 ne_status launch_status();
+// The library's device flag word on the current device (ne_device_flags):
+// kernels of the per-step calls OR NE_FLAG_* bits into it. Its address is
+// looked up once per device; NULL if the lookup failed (the kernels then
+// report nothing).
+uint32_t *device_flag_word();
 // Shape rules of one LSB operation (ne_lsb_apply): NE_OK, NE_EINVAL or
 // NE_EUNSUP.
 ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t n_operand,

@@ -252,19 +252,24 @@ __global__ __launch_bounds__(kBlock) void k_outer(Ptrs x, const int32_t *g, Ptrs
     }
 }
 
-// y[i] = x[p[i]] (gather); an index outside [0, n) is clamped so that a bad
-// permutation cannot read out of bounds.
+// y[i] = x[p[i]] (gather). An index outside [0, n) is not a permutation
+// index: nothing is read for it, y[i] = 0, and NE_FLAG_PERM_INDEX is raised
+// in the library's device flag word (ne_device_flags).
 template <typename Ptrs>
-__global__ __launch_bounds__(kBlock) void k_perm(Ptrs x, const int32_t *p, PtrsI64 y, int64_t n)
+__global__ __launch_bounds__(kBlock) void k_perm(Ptrs x, const int32_t *p, PtrsI64 y, int64_t n,
+                                                 uint32_t *err)
 {
     const auto *xs = x.p[blockIdx.y];
     int64_t *ys = y.p[blockIdx.y];
+    bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
-        int64_t src = p[i];
-        src = src < 0 ? 0 : (src >= n ? n - 1 : src);
-        ys[i] = widen(xs[src]);
+        const int64_t src = p[i];
+        const bool ok = src >= 0 && src < n;
+        bad |= !ok;
+        ys[i] = ok ? widen(xs[src]) : 0;
     }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_first(PtrsI64 y)
@@ -437,7 +442,7 @@ void launch_perm_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *p, 
                      hipStream_t s)
 {
     hipLaunchKernelGGL(k_perm<PtrsCI64>, dim3(grid_for(n, kBlock, 4096), count), dim3(kBlock), 0,
-                       s, x, p, y, n);
+                       s, x, p, y, n, device_flag_word());
 }
 
 void launch_inner_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,
@@ -487,7 +492,7 @@ void launch_perm_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *p, c
                      hipStream_t s)
 {
     hipLaunchKernelGGL(k_perm<PtrsI32>, dim3(grid_for(n, kBlock, 4096), count), dim3(kBlock), 0,
-                       s, x, p, y, n);
+                       s, x, p, y, n, device_flag_word());
 }
 
 void launch_inner_i32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsI64 &y,

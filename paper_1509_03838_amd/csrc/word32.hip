@@ -204,18 +204,22 @@ __global__ __launch_bounds__(kBlock) void k_map32(PtrsI32 x, const int32_t *g, P
     }
 }
 
-// y[i] = x[p[i]]; an index outside [0, n) is clamped into it.
+// y[i] = x[p[i]]; an index outside [0, n) reads nothing, gives y[i] = 0 and
+// raises NE_FLAG_PERM_INDEX in the library's device flag word.
 __global__ __launch_bounds__(kBlock) void k_perm32(PtrsI32 x, const int32_t *p, PtrsW32 y,
-                                                   int64_t n)
+                                                   int64_t n, uint32_t *err)
 {
     const int32_t *xs = x.p[blockIdx.y];
     int32_t *ys = y.p[blockIdx.y];
+    bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
-        int64_t src = p[i];
-        src = src < 0 ? 0 : (src >= n ? n - 1 : src);
-        ys[i] = xs[src];
+        const int64_t src = p[i];
+        const bool ok = src >= 0 && src < n;
+        bad |= !ok;
+        ys[i] = ok ? xs[src] : 0;
     }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
 }
 
 // y[i K + j] = x[i] g[j] (mod 2^32); one output per lane, (i, j) advanced
@@ -401,7 +405,7 @@ void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const in
     case NE_OP_MUL: map32<kMapMul>(count, n_in, x, operand, y, 0, s); break;
     case NE_OP_PERM:
         hipLaunchKernelGGL(k_perm32, dim3(grid_for(n_in, kBlock, 4096), count), dim3(kBlock), 0,
-                           s, x, operand, y, n_in);
+                           s, x, operand, y, n_in, device_flag_word());
         break;
     case NE_OP_INNER:
         hipLaunchKernelGGL(k_zero_first32, dim3(count), dim3(64), 0, s, y);

@@ -31,11 +31,11 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
-           "ne_chain_apply32")
+           "ne_chain_apply32", "ne_device_flags")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
-FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH = 1, 2, 4
+FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH, FLAG_PERM_INDEX = 1, 2, 4, 8
 
 
 class GroupC(ctypes.Structure):
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
         "ne_strerror": (ctypes.c_char_p, [_i32]),
         "ne_last_hip_error": (_i32, []),
         "ne_version": (_i32, []),
+        "ne_device_flags": (_i32, [ctypes.POINTER(ctypes.c_uint32), _i32]),
         "ne_params": (_i32, [_i32, _i32, _P, _P, _P]),
         "ne_entangle": (_i32, [_i32, _i32, _i64, _P, _P, _P]),
         "ne_entangle_inplace": (_i32, [_i32, _i32, _i64, _P, _P]),
@@ -175,6 +176,61 @@ def _dtype(ts, dt, what):
             raise TypeError(f"{what} must be {dt}, got {t.dtype}")
 
 
+def _tensors(ts) -> list:
+    """The tensors among ts (None and raw integer addresses are the caller's
+    responsibility and are skipped)."""
+    return [t for t in ts if t is not None and not isinstance(t, int)]
+
+
+def _on_device(what: str, ts, device=None):
+    """Every tensor in ts must live on one GPU (the library dereferences the
+    pointers on the device; a host tensor would be an out-of-bounds device
+    access). Returns that device, or `device` if ts holds no tensor."""
+    for t in _tensors(ts):
+        if t.device.type != "cuda":
+            raise ValueError(f"{what} must be on the GPU, got a tensor on {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if device is None:
+            device = t.device
+        elif t.device != device:
+            raise ValueError(f"{what} is on {t.device}, other buffers on {device}")
+    return device
+
+
+def _lengths(what: str, ts, n: int, exact: bool):
+    """Every tensor in ts holds n elements (exact) or at least n."""
+    for i, t in enumerate(ts):
+        if t is None or isinstance(t, int):
+            continue
+        k = t.numel()
+        if (exact and k != n) or k < n:
+            raise ValueError(f"{what}[{i}] holds {k} elements, "
+                             f"{'exactly' if exact else 'at least'} {n} needed")
+
+
+def _n_of(ts, n, what: str) -> int:
+    """n if given, else the common length of the tensors in ts (which must
+    agree: the C ABI takes one length for all of them)."""
+    known = [t.numel() for t in _tensors(ts)]
+    if n is None:
+        if not known:
+            raise ValueError(f"{what}: no tensor to take the length from; pass n")
+        n = known[0]
+        _lengths(what, ts, n, exact=True)
+    else:
+        _lengths(what, ts, n, exact=False)
+    return n
+
+
+def device_flags(clear: bool = False) -> int:
+    """NE_FLAG_* bits the per-step kernels raised on the current device
+    (synchronous: waits for the device); clear zeroes the word."""
+    f = ctypes.c_uint32()
+    _check("ne_device_flags", load().ne_device_flags(ctypes.byref(f), int(clear)))
+    return f.value
+
+
 def params(M: int, w: int = 64) -> tuple[int, int, int]:
     """(l, k, D) per Table I and eq. (11)/(13)."""
     l, k, D = _i32(), _i32(), _i64()
@@ -189,7 +245,9 @@ def entangle(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=No
     _dtype(eps, torch.int64, "eps")
     if len(c) != len(eps):
         raise ValueError("c and eps differ in length")
-    n = c[0].numel() if n is None else n
+    _on_device("c and eps", list(c) + list(eps))
+    n = _n_of(c, n, "c")
+    _lengths("eps", eps, n, exact=False)
     _check("ne_entangle", load().ne_entangle(len(c), l, n, _ptr_array(c), _ptr_array(eps),
                                              _stream(stream)))
 
@@ -197,7 +255,8 @@ def entangle(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=No
 def entangle_inplace(x: Sequence, l: int, n: int | None = None, stream=None):
     import torch
     _dtype(x, torch.int64, "x")
-    n = x[0].numel() if n is None else n
+    _on_device("x", x)
+    n = _n_of(x, n, "x")
     _check("ne_entangle_inplace", load().ne_entangle_inplace(len(x), l, n, _ptr_array(x),
                                                              _stream(stream)))
 
@@ -206,6 +265,8 @@ def entangle_operand(g, g_ent, l: int, stream=None):
     import torch
     _dtype([g], torch.int32, "g")
     _dtype([g_ent], torch.int64, "g_ent")
+    _on_device("g and g_ent", [g, g_ent])
+    _lengths("g_ent", [g_ent], g.numel(), exact=False)
     _check("ne_entangle_operand", load().ne_entangle_operand(l, g.numel(), _ptr(g), _ptr(g_ent),
                                                              _stream(stream)))
 
@@ -227,14 +288,21 @@ def lsb_apply(op: str, eps: Sequence, operand, delta: Sequence, scalar: int = 0,
     import torch
     _dtype(eps, torch.int64, "eps")
     _dtype(delta, torch.int64, "delta")
+    if operand is not None and not isinstance(operand, int):
+        _dtype([operand], torch.int64 if op in ("add", "sub") else torch.int32, "operand")
     M = len(eps)
+    if len(delta) != M:
+        raise ValueError("eps and delta differ in length")
     if mask is None:
         mask = (1 << M) - 1
-    if n_in is None:
-        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    _on_device("eps, operand and delta", list(eps) + list(delta) + [operand])
+    n_in = _n_of(eps, n_in, "eps")
     if n_operand is None:
         n_operand = 0 if operand is None or isinstance(operand, int) else operand.numel()
+    elif operand is not None and not isinstance(operand, int):
+        _lengths("operand", [operand], n_operand, exact=False)
     no = n_out(op, n_in, n_operand)
+    _lengths("delta", [t for m, t in enumerate(delta) if (mask >> m) & 1], no, exact=False)
     _check("ne_lsb_apply", load().ne_lsb_apply(OPS[op], M, n_in, _ptr_array(eps), _ptr(operand),
                                                n_operand, int(scalar), _ptr_array(delta), no,
                                                mask & 0xFFFFFFFF, _stream(stream)))
@@ -247,8 +315,11 @@ def extract_recover(delta: Sequence, r: int, dhat: Sequence, l: int, n: int | No
     _dtype(delta, torch.int64, "delta")
     _dtype(dhat, torch.int64, "dhat")
     M = len(dhat)
-    if n is None:
-        n = dhat[0].numel()
+    if len(delta) != M:
+        raise ValueError("delta and dhat differ in length")
+    _on_device("delta and dhat", list(delta) + list(dhat))
+    n = _n_of(dhat, n, "dhat")
+    _lengths("delta", [t for m, t in enumerate(delta) if m != r], n, exact=False)
     _check("ne_extract_recover", load().ne_extract_recover(M, l, n, _ptr_array(delta), r,
                                                            _ptr_array(dhat), _stream(stream)))
 
@@ -261,7 +332,9 @@ def entangle32(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=
     _dtype(eps, torch.int32, "eps")
     if len(c) != len(eps):
         raise ValueError("c and eps differ in length")
-    n = c[0].numel() if n is None else n
+    _on_device("c and eps", list(c) + list(eps))
+    n = _n_of(c, n, "c")
+    _lengths("eps", eps, n, exact=False)
     _check("ne_entangle32", load().ne_entangle32(len(c), l, n, _ptr_array(c), _ptr_array(eps),
                                                  _stream(stream)))
 
@@ -269,6 +342,8 @@ def entangle32(c: Sequence, eps: Sequence, l: int, n: int | None = None, stream=
 def entangle_operand32(g, g_ent, l: int, stream=None):
     import torch
     _dtype([g, g_ent], torch.int32, "g")
+    _on_device("g and g_ent", [g, g_ent])
+    _lengths("g_ent", [g_ent], g.numel(), exact=False)
     _check("ne_entangle_operand32", load().ne_entangle_operand32(l, g.numel(), _ptr(g),
                                                                  _ptr(g_ent), _stream(stream)))
 
@@ -283,12 +358,15 @@ def lsb_apply32(op: str, eps: Sequence, operand, delta: Sequence, scalar: int = 
     if operand is not None and not isinstance(operand, int):
         _dtype([operand], torch.int32, "operand")
     M = len(eps)
+    if len(delta) != M:
+        raise ValueError("eps and delta differ in length")
     if mask is None:
         mask = (1 << M) - 1
-    if n_in is None:
-        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    _on_device("eps, operand and delta", list(eps) + list(delta) + [operand])
+    n_in = _n_of(eps, n_in, "eps")
     n_operand = 0 if operand is None or isinstance(operand, int) else operand.numel()
     no = n_out(op, n_in, n_operand)
+    _lengths("delta", [t for m, t in enumerate(delta) if (mask >> m) & 1], no, exact=False)
     _check("ne_lsb_apply32", load().ne_lsb_apply32(OPS[op], M, n_in, _ptr_array(eps),
                                                    _ptr(operand), n_operand, int(scalar),
                                                    _ptr_array(delta), no, mask & 0xFFFFFFFF,
@@ -303,8 +381,11 @@ def extract_recover32(delta: Sequence, r: int, dhat: Sequence, l: int, n: int | 
     _dtype(delta, torch.int32, "delta")
     _dtype(dhat, torch.int32, "dhat")
     M = len(dhat)
-    if n is None:
-        n = dhat[0].numel()
+    if len(delta) != M:
+        raise ValueError("delta and dhat differ in length")
+    _on_device("delta and dhat", list(delta) + list(dhat))
+    n = _n_of(dhat, n, "dhat")
+    _lengths("delta", [t for m, t in enumerate(delta) if m != r], n, exact=False)
     _check("ne_extract_recover32", load().ne_extract_recover32(M, l, n, _ptr_array(delta), r,
                                                                _ptr_array(dhat), _stream(stream)))
 
@@ -313,9 +394,15 @@ def plain_apply(op: str, c: Sequence, operand, d: Sequence, scalar: int = 0, str
     import torch
     _dtype(c, torch.int32, "c")
     _dtype(d, torch.int64, "d")
-    n_in = c[0].numel()
+    if operand is not None:
+        _dtype([operand], torch.int32, "operand")
+    if len(c) != len(d):
+        raise ValueError("c and d differ in length")
+    _on_device("c, operand and d", list(c) + list(d) + [operand])
+    n_in = _n_of(c, None, "c")
     n_operand = 0 if operand is None else operand.numel()
     no = n_out(op, n_in, n_operand)
+    _lengths("d", d, no, exact=False)
     _check("ne_plain_apply", load().ne_plain_apply(OPS[op], len(c), n_in, _ptr_array(c),
                                                    _ptr(operand), n_operand, int(scalar),
                                                    _ptr_array(d), no, _stream(stream)))
@@ -325,14 +412,21 @@ def checksum(c: Sequence, rsum, stream=None):
     import torch
     _dtype(c, torch.int32, "c")
     _dtype([rsum], torch.int64, "rsum")
-    _check("ne_checksum", load().ne_checksum(len(c), c[0].numel(), _ptr_array(c), _ptr(rsum),
+    _on_device("c and rsum", list(c) + [rsum])
+    n = _n_of(c, None, "c")
+    _lengths("rsum", [rsum], n, exact=False)
+    _check("ne_checksum", load().ne_checksum(len(c), n, _ptr_array(c), _ptr(rsum),
                                              _stream(stream)))
 
 
 def checksum_recover(d: Sequence, e, r: int, d_r, stream=None):
     import torch
     _dtype(d, torch.int64, "d")
+    _dtype([e, d_r], torch.int64, "e and d_r")
+    _on_device("d, e and d_r", list(d) + [e, d_r])
     n = e.numel()
+    _lengths("d", [t for m, t in enumerate(d) if m != r], n, exact=False)
+    _lengths("d_r", [d_r], n, exact=False)
     _check("ne_checksum_recover", load().ne_checksum_recover(len(d), n, _ptr_array(d), _ptr(e), r,
                                                              _ptr(d_r), _stream(stream)))
 
@@ -356,11 +450,21 @@ class GroupSpec:
         _dtype(self.out, torch.int32 if self.word_bits == 32 else torch.int64, "out")
         if self.operand is not None:
             _dtype([self.operand], torch.int32, "operand")
+        if len(self.out) != len(self.c):
+            raise ValueError("a group needs one output per input stream")
+        if len(self.c) > FUSED_MAX_M:
+            raise ValueError(f"a group holds at most {FUSED_MAX_M} streams")
+        if any(t is None or isinstance(t, int) for t in self.c + self.out):
+            raise ValueError("every input and output of a group must be a tensor")
+        _on_device("group inputs, operand and outputs", self.c + self.out + [self.operand])
+        n = _n_of(self.c, None, "c") if self.c else 0
+        n_operand = 0 if self.operand is None else self.operand.numel()
+        _lengths("out", self.out, n_out(self.op, n, n_operand), exact=False)
         g = GroupC()
         g.op = OPS[self.op]
         g.M = len(self.c)
-        g.n = self.c[0].numel() if self.c else 0
-        g.n_operand = 0 if self.operand is None else self.operand.numel()
+        g.n = n
+        g.n_operand = n_operand
         g.scalar = self.scalar
         g.lost = self.lost
         g.in_bits = self.in_bits
@@ -398,6 +502,8 @@ class Plan:
         L = load()
         self._groups = list(groups)  # keeps the tensors alive
         self._ws = workspace
+        if workspace is not None:
+            _on_device("workspace", [workspace])
         arr = (GroupC * max(1, len(self._groups)))()
         for i, g in enumerate(self._groups):
             arr[i] = g.to_c()
@@ -496,18 +602,22 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
     _dtype(eps, word, "eps")
     _dtype(delta, word, "delta")
     M = len(eps)
+    if len(delta) != M:
+        raise ValueError("eps and delta differ in length")
     if mask is None:
         mask = (1 << M) - 1
-    if n_in is None:
-        n_in = next(t.numel() for t in eps if t is not None and not isinstance(t, int))
+    live = [m for m in range(M) if (mask >> m) & 1]
+    dev = _on_device("eps, operands, delta and workspace",
+                     list(eps) + list(delta) + [o.operand for o in ops] + [workspace])
+    n_in = _n_of([eps[m] for m in live], n_in, "eps")
     n = n_in
     for o in ops:
         n = n_out(o.op, n, o.n_operand)
+    _lengths("delta", [delta[m] for m in live], n, exact=False)
     ws_bytes = chain_workspace_size(M, n_in, ops, w)
     if workspace is not None and not isinstance(workspace, int) and workspace.numel() < ws_bytes:
         raise ValueError(f"workspace holds {workspace.numel()} bytes, the series needs {ws_bytes}")
     if workspace is None and ws_bytes:
-        dev = next(t.device for t in eps if t is not None and not isinstance(t, int))
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
         workspace = workspace[(-workspace.data_ptr()) % 256:]
     fn = "ne_chain_apply32" if w == 32 else "ne_chain_apply"
@@ -535,6 +645,10 @@ def gemm(c: Sequence, g, out: Sequence, mode: str = "entangled", lost: int = -1,
     _dtype(out, torch.int64, "out")
     if g.dim() != 2:
         raise ValueError("g must be a matrix")
+    if len(out) != len(c):
+        raise ValueError("one output per block")
+    _on_device("blocks, kernel matrix, outputs, flags and workspace",
+               list(c) + [g] + list(out) + [flags, workspace])
     P, Q = g.shape
     N = out[0].shape[0] if out[0].dim() == 2 else 0
     for t in c:
