@@ -283,7 +283,8 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
         for (int q = 0; q < 4; ++q) {
             int64_t x;
             if (MODE == kChecksum && pl == DM) {
-                int32_t sum = 0;
+                // the sum of DM b-bit samples needs up to b + 3 bits: 64-bit adds
+                int64_t sum = 0;
 #pragma unroll
                 for (int m = 0; m < DM; ++m) sum += raw.cv[m][q];
                 x = sum;
@@ -893,7 +894,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
             }
         };
         // Inputs in slot order; prev0: the partner of slot 0 (slot M - 1).
-        int32_t cv[NS][V], prev0[V], csum[V], gv[V];
+        // csum: the checksum stream's sample, summed in 64 bits (M b-bit
+        // samples need up to b + 3 bits)
+        int32_t cv[NS][V], prev0[V], gv[V];
+        int64_t csum[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) csum[v] = prev0[v] = gv[v] = 0;
 #pragma unroll
