@@ -66,6 +66,8 @@ typedef int32_t ne_status;
 #define NE_EUNSUP (-4)    /* operation or shape not supported */
 #define NE_EHIP (-5)      /* a HIP call failed; see ne_last_hip_error() */
 #define NE_ENOMEM (-6)    /* device allocation failed (plan creation only) */
+#define NE_ESCRATCH (-7)  /* needs more than the library's fixed scratch buffer
+                             (ne_chain_apply_noalloc) */
 
 /* The LSB operations of eq. (2) that the library runs. */
 typedef enum ne_op {
@@ -341,6 +343,28 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
                          const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
                          int64_t n_out, uint32_t stream_mask, void *workspace,
                          size_t workspace_bytes, ne_stream stream);
+
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * series as ne_chain_apply, with the intermediates in a fixed buffer that
+ * the library holds in device memory instead of caller workspace. The
+ * buffer is NE_CHAIN_SCRATCH_BYTES on every device the library runs on (a
+ * static device array, held until the process ends); the call allocates
+ * nothing and launches on `stream` only. Every call on one device shares
+ * that device's buffer: calls that overlap in time on one device (other
+ * streams or threads) race on it and must be serialised by the caller; each
+ * stage writes every intermediate it later reads, so nothing in the buffer
+ * needs clearing. Arguments as ne_chain_apply without the workspace.
+ * Errors: as ne_chain_apply (checked before the device is touched), and
+ * NE_ESCRATCH when ne_chain_workspace_size for these arguments exceeds
+ * NE_CHAIN_SCRATCH_BYTES (e.g. a series of two or more stages on three
+ * streams longer than about 1.4 million samples).
+ */
+#define NE_CHAIN_SCRATCH_BYTES ((size_t)64 << 20)
+ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *eps,
+                                 const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
+                                 int64_t n_out, uint32_t stream_mask, ne_stream stream);
 
 /*
  * The same series in 32-bit entangled words (the paper's practical w = 32):

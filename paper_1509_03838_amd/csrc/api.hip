@@ -127,6 +127,7 @@ const char *ne_strerror(ne_status s)
     case NE_EUNSUP: return "operation or shape not supported";
     case NE_EHIP: return "HIP runtime error";
     case NE_ENOMEM: return "device allocation failed";
+    case NE_ESCRATCH: return "needs more than the library's fixed scratch buffer";
     default: return "unknown status";
     }
 }

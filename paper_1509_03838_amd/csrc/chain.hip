@@ -1,8 +1,10 @@
 // Series of LSB operations on entangled streams (ne_chain_*): the shape and
 // range bookkeeping of the series (host) and its execution as one launch
-// per operation over ping-pong buffers in the caller's workspace. The
-// operations are the per-step kernels of ne_lsb_apply.
+// per operation over ping-pong buffers in the caller's workspace (or, for
+// ne_chain_apply_noalloc, in a fixed device buffer of the library's own).
+// The operations are the per-step kernels of ne_lsb_apply.
 #include <algorithm>
+#include <mutex>
 
 #include "ne_internal.h"
 
@@ -124,6 +126,44 @@ ne_status workspace_w(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n
     return NE_OK;
 }
 
+// Intermediates of ne_chain_apply_noalloc: a fixed buffer in device memory,
+// one copy on every device that loads the library, held until the process
+// ends. On the host, `scratch` only stands in for the device array: kernels
+// and copies take the per-device address that hipGetSymbolAddress returns
+// (scratch_address), never the array's name.
+static __device__ __align__(256) unsigned char scratch[NE_CHAIN_SCRATCH_BYTES];
+
+// The address of `scratch` on the calling thread's current device, looked
+// up once per device with that device current and kept; NULL with *st set
+// on a HIP error.
+unsigned char *scratch_address(ne_status *st)
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static unsigned char *addr[kDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *st = hip_fail(e);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kDevices) {
+        *st = NE_EUNSUP;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *st = hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return nullptr;
+        }
+        addr[dev] = (unsigned char *)p;
+    }
+    return addr[dev];
+}
+
 // Word-width traits of the series' execution: the stream tables and the
 // launch of one operation.
 struct Words64 {
@@ -180,7 +220,7 @@ template <typename T>
 ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
                   const ne_chain_op *ops, int32_t n_ops, typename T::W *const *delta,
                   int64_t n_out, uint32_t stream_mask, void *workspace, size_t workspace_bytes,
-                  ne_stream stream)
+                  ne_stream stream, bool use_scratch = false)
 {
     using W = typename T::W;
     if (M < 1 || M > kMaxM || !eps || !delta) return NE_EINVAL;
@@ -189,7 +229,10 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
     if (st != NE_OK) return st;
     if (n_out != want) return NE_EINVAL;
     const size_t plane = align_up((size_t)longest * sizeof(W));
-    if (n_ops > 1 && plane > 0) {
+    const bool need_ws = n_ops > 1 && plane > 0;
+    if (need_ws && use_scratch) {
+        if (2 * (size_t)M * plane > NE_CHAIN_SCRATCH_BYTES) return NE_ESCRATCH;
+    } else if (need_ws) {
         if (!workspace || workspace_bytes < 2 * (size_t)M * plane) return NE_EINVAL;
         if ((uintptr_t)workspace % kWsAlign) return NE_EINVAL;
     }
@@ -212,6 +255,12 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
         ++count;
     }
     if (count == 0) return NE_OK;
+    if (need_ws && use_scratch) {
+        // every argument has been checked: only now is the device touched
+        ne_status sst = NE_OK;
+        workspace = scratch_address(&sst);
+        if (!workspace) return sst;
+    }
     hipStream_t s = (hipStream_t)stream;
     unsigned char *ws = (unsigned char *)workspace;
     int64_t n = n_in;
@@ -258,6 +307,14 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
 {
     return apply_w<Words64>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, workspace,
                             workspace_bytes, stream);
+}
+
+ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *eps,
+                                 const ne_chain_op *ops, int32_t n_ops, int64_t *const *delta,
+                                 int64_t n_out, uint32_t stream_mask, ne_stream stream)
+{
+    return apply_w<Words64>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, nullptr, 0,
+                            stream, true);
 }
 
 ne_status ne_chain_check32(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,

@@ -22,6 +22,7 @@ OPS = {"conv": CONV, "scale": SCALE, "add": ADD, "inner": INNER, "perm": PERM,
        "sub": SUB, "mul": MUL, "circ": CIRC, "xcorr": XCORR, "outer": OUTER}
 MAX_M = 32
 MAX_M32 = 17
+CHAIN_SCRATCH_BYTES = 64 << 20  # NE_CHAIN_SCRATCH_BYTES: the fixed buffer of chain_apply_noalloc
 
 EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_entangle",
            "ne_entangle_inplace", "ne_entangle_operand", "ne_lsb_apply", "ne_extract_recover",
@@ -31,7 +32,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
-           "ne_chain_apply32", "ne_device_flags")
+           "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
@@ -117,6 +118,8 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
+        "ne_chain_apply_noalloc": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P,
+                                          _i64, _u32, _P]),
         "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P,
                            ctypes.c_size_t, _P, _P]),
         "ne_gemm_workspace_size": (_i32, [_i32, _i32, _i64, _i64, _i64, _i32,
@@ -624,6 +627,34 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
     _check(fn, getattr(load(), fn)(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
                                    _ptr_array(delta), n, mask & 0xFFFFFFFF, _ptr(workspace),
                                    ws_bytes, _stream(stream)))
+
+
+def chain_apply_noalloc(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence,
+                        mask: int | None = None, n_in: int | None = None, stream=None):
+    """chain_apply in 64-bit words with the intermediates in the library's
+    fixed device buffer (CHAIN_SCRATCH_BYTES per device) instead of a
+    workspace: nothing is allocated, here or in the library. Calls that
+    overlap on one device race on that buffer. Raises NeError (status -7)
+    when the series needs more than the buffer holds."""
+    import torch
+    _dtype(eps, torch.int64, "eps")
+    _dtype(delta, torch.int64, "delta")
+    M = len(eps)
+    if len(delta) != M:
+        raise ValueError("eps and delta differ in length")
+    if mask is None:
+        mask = (1 << M) - 1
+    live = [m for m in range(M) if (mask >> m) & 1]
+    _on_device("eps, operands and delta", list(eps) + list(delta) + [o.operand for o in ops])
+    n_in = _n_of([eps[m] for m in live], n_in, "eps")
+    n = n_in
+    for o in ops:
+        n = n_out(o.op, n, o.n_operand)
+    _lengths("delta", [delta[m] for m in live], n, exact=False)
+    _check("ne_chain_apply_noalloc",
+           load().ne_chain_apply_noalloc(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
+                                         _ptr_array(delta), n, mask & 0xFFFFFFFF,
+                                         _stream(stream)))
 
 
 def gemm_workspace_size(mode: str, M: int, N: int, P: int, Q: int, in_bits: int) -> int:

@@ -470,3 +470,20 @@ def test_gemm_workspace_size_and_checks(lib):
     out = ne._ptr_array([FAKE + (1 << 20) + 4096 * m for m in range(3)])
     assert lib.ne_gemm(0, 3, 100, 70, 90, c, FAKE, out, -1, 12, FAKE, size - 1, None, None) == -1
     assert lib.ne_gemm(0, 3, 100, 70, 90, c, FAKE, out, -1, 12, FAKE + 16, size, None, None) == -1
+
+
+def test_chain_noalloc_refuses_series_past_its_buffer(lib):
+    """ne_chain_apply_noalloc checks the series against its fixed buffer
+    before anything touches the device: the pointers here are never read."""
+    import ctypes
+    M = 3
+    n = ne.CHAIN_SCRATCH_BYTES // (2 * M) // 8 + 1
+    ops = [ne.ChainOp("scale", None, 3), ne.ChainOp("scale", None, 5)]
+    assert ne.chain_workspace_size(M, n, ops) > ne.CHAIN_SCRATCH_BYTES
+    assert ne.chain_workspace_size(M, n - 64, ops) <= ne.CHAIN_SCRATCH_BYTES
+    fake = (ctypes.c_void_p * M)(*([0x1000] * M))
+    st = lib.ne_chain_apply_noalloc(M, n, fake, ne._chain_c(ops), len(ops), fake, n, 7, None)
+    assert st == -7 and b"scratch" in lib.ne_strerror(st)
+    # argument errors come first as well (a wrong n_out)
+    st = lib.ne_chain_apply_noalloc(M, 100, fake, ne._chain_c(ops), len(ops), fake, 99, 7, None)
+    assert st == -1
