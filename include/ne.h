@@ -232,6 +232,18 @@ ne_status ne_checksum(int32_t M, int64_t n, const int32_t *const *c, int64_t *rs
 ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
                               const int64_t *e, int32_t r, int64_t *d_r, ne_stream stream);
 
+/*
+ * Memory-bandwidth reference, none of the method's arithmetic:
+ *     out[i] = in[i] (sign-extended to int64)     for i < n,
+ * the HBM traffic of a fused convolution's inputs and outputs (4 bytes read
+ * and 8 written per element) with the same access widths (16-byte loads,
+ * non-temporal 16-byte stores). Its rate is the practical ceiling the fused
+ * kernels are measured against. in and out: device memory, 16-byte aligned,
+ * disjoint. Errors: NE_EINVAL (n < 0, NULL, misaligned or overlapping
+ * buffers of a non-empty copy), NE_EHIP.
+ */
+ne_status ne_stream_widen(const int32_t *in, int64_t n, int64_t *out, ne_stream stream);
+
 /* ------------------------------------------------------------------------
  * The same per-step method in 32-bit entangled words, the paper's practical
  * instantiation (Sec. III-B; Table I's w = 32 column; l = 11, k = 10 for
@@ -450,7 +462,19 @@ ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, int64_t P, 
  * input range needs; NE_MODE_PLAIN_SAME the same operation on the datapath
  * (digit counts) the entangled words need; NE_MODE_CHECKSUM the checksum
  * method of eq. (3)-(5) (M data streams plus their sum, with recovery of a
- * lost stream as d_r = e - sum of the others).
+ * lost stream as d_r = e - sum of the others), with the fewest digits the
+ * sum stream needs; NE_MODE_CHECKSUM_SAME the checksum method on the
+ * entangled words' datapath (the paper's comparison ran every variant
+ * through one routine, Sec. V). Element-wise operations have one datapath,
+ * so the two checksum modes and the two plain modes coincide for them.
+ *
+ * Digits of a convolution: the inputs and taps are cut into balanced
+ * base-256 digits for the i8 matrix cores. Where it takes fewer digit planes,
+ * every data word x is first split at bit l into a balanced low field lo and
+ * a high field hi = (x - lo) / 2^l, each with its own digits (an entangled
+ * word of 12-bit samples at M = 3: 2 + 2 digits instead of 5); the split is
+ * computed from x alone, so each stream's product still depends only on its
+ * own entangled input.
  * ------------------------------------------------------------------------ */
 
 #define NE_FUSED_MAX_M 8
@@ -459,7 +483,8 @@ typedef enum ne_mode {
     NE_MODE_ENTANGLED = 0,
     NE_MODE_PLAIN = 1,
     NE_MODE_PLAIN_SAME = 2,
-    NE_MODE_CHECKSUM = 3
+    NE_MODE_CHECKSUM = 3,
+    NE_MODE_CHECKSUM_SAME = 4
 } ne_mode;
 
 /* Device-side error bits (ne_plan_flags). */

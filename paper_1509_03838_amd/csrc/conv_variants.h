@@ -3,10 +3,11 @@
 // counts of a group, and by the kernel translation units, which instantiate
 // exactly the variants some group can need, so the two cannot disagree.
 //
-// A variant is (kernel class, slot count, LA, LB):
+// A variant is (kernel class, slot count, LA, LB, shape):
 //   kernel class 0: entangled groups, M = slots (M >= 3);
 //   kernel class 1: plain and plain-same groups, M = slots;
-//   kernel class 2: checksum groups, M = slots - 1 data streams + their sum.
+//   kernel class 2: checksum groups (either datapath), M = slots - 1 data
+//   streams + their sum.
 #pragma once
 
 #include <stdint.h>
@@ -55,7 +56,14 @@ constexpr int64_t dmax_w32(int M)
 struct DigitCounts {
     int la, lb;
     int sparse;  // 1: the taps' top digit is nonzero only for a sliver of their range
+    int split;   // 1: data words split at bit l into two fields of la/2 digits each
+    int l;       // split words: the field boundary (Table I's l of the datapath, <= 22)
 };
+
+// Variant shape index of a digit count: 0 plain digits, 1 sparse top tap
+// digit, 2 data words split into two fields (the two never combine).
+constexpr int conv_shape(const DigitCounts &d) { return d.sparse ? 1 : (d.split ? 2 : 0); }
+constexpr int kConvShapes = 3;
 
 // Balanced digits reach 127 * R on the positive side (R = (256^L - 1)/255),
 // one step short of a power of two: taps of 16 bits need a third digit, but
@@ -80,21 +88,46 @@ constexpr int sparse_top_digit(int in_bits, int lb)
 // c + 2^l c' (l of Table I at word width w) lie in (2^l + 1) times that
 // range (plain-same groups use the same digit count on raw words, so that
 // both modes run one datapath); the checksum stream in M times that range.
-// mode: 0 entangled, 1 plain, 2 plain-same, 3 checksum (the plan's modes).
-constexpr DigitCounts conv_digits(int mode, int M, int in_bits, int w = 64)
+// mode: 0 entangled, 1 plain, 2 plain-same, 3 checksum, 4 checksum on the
+// entangled datapath (the plan's modes).
+//
+// Split words (split = 1, allow_split): a word x is cut at bit l into
+// lo = x - 2^l floor(x / 2^l + 1/2), the balanced low field, and
+// hi = (x - lo) / 2^l, so x = lo + 2^l hi for every x; each field gets la/2
+// balanced digits and the digit planes carry weights 256^a (lo) and
+// 2^l 256^a (hi). An entangled word whose streams fit the lo field
+// (|c| < 2^(l-1)) then needs the digits of two raw samples, not those of a
+// word (2^l + 1) times wider: 4 instead of 5 for 12-bit samples at M = 3.
+// It is chosen only where it needs fewer digit planes.
+constexpr DigitCounts conv_digits(int mode, int M, int in_bits, int w = 64, bool allow_split = false)
 {
     const unsigned __int128 B = (unsigned __int128)1 << (in_bits - 1);
     unsigned __int128 neg = B, pos = B - 1;
-    if (mode == 0 || mode == 2) {
-        const unsigned __int128 f = ((unsigned __int128)1 << table1_shift(M < 3 ? 3 : M, w)) + 1;
-        neg *= f;
-        pos *= f;
-    } else if (mode == 3) {
+    const int lb = digits_for(B, B - 1);
+    const DigitCounts narrow{0, lb, sparse_top_digit(in_bits, lb), 0, 0};
+    if (mode == 0 || mode == 2 || mode == 4) {
+        const int l = table1_shift(M < 3 ? 3 : M, w);
+        const unsigned __int128 f = ((unsigned __int128)1 << l) + 1;
+        int la = digits_for(neg * f, pos * f);
+        // checksum on this datapath: the sum stream must fit it too
+        if (mode == 4 && digits_for(neg * (unsigned)M, pos * (unsigned)M) > la)
+            la = digits_for(neg * (unsigned)M, pos * (unsigned)M);
+        if (allow_split && narrow.sparse == 0 && l <= 31) {
+            // the lo field must hold every raw value (and the checksum sum)
+            const unsigned __int128 fneg = mode == 4 ? neg * (unsigned)M : neg;
+            const unsigned __int128 fpos = mode == 4 ? pos * (unsigned)M : pos;
+            const unsigned __int128 half = (unsigned __int128)1 << (l - 1);
+            const int fs = digits_for(fneg, fpos);
+            if (fneg <= half && fpos < half && 2 * fs < la && 2 * fs <= 8)
+                return DigitCounts{2 * fs, lb, 0, 1, l};
+        }
+        return DigitCounts{la, lb, narrow.sparse, 0, 0};
+    }
+    if (mode == 3) {
         neg *= (unsigned)M;
         pos *= (unsigned)M;
     }
-    const int lb = digits_for(B, B - 1);
-    return DigitCounts{digits_for(neg, pos), lb, sparse_top_digit(in_bits, lb)};
+    return DigitCounts{digits_for(neg, pos), lb, narrow.sparse, 0, 0};
 }
 
 // Widest inputs of a convolution group in 32-bit words: its worst case
@@ -108,29 +141,34 @@ constexpr int conv_w32_max_bits(int mode, int M)
     return b;
 }
 
-constexpr int conv_class_of_mode(int mode) { return mode == 0 ? 0 : (mode == 3 ? 2 : 1); }
+constexpr int kConvModes = 5;
+constexpr bool conv_checksum_mode(int mode) { return mode == 3 || mode == 4; }
+constexpr int conv_class_of_mode(int mode)
+{
+    return mode == 0 ? 0 : (conv_checksum_mode(mode) ? 2 : 1);
+}
 
 // Slots of a group: M, or M + 1 with the checksum stream.
-constexpr int conv_slots(int mode, int M) { return mode == 3 ? M + 1 : M; }
+constexpr int conv_slots(int mode, int M) { return conv_checksum_mode(mode) ? M + 1 : M; }
 
 // Whether some group of this kernel class and slot count, with inputs of
 // 1..31 bits (64-bit words) or of the widths 32-bit words admit, uses digit
 // counts (la, lb) with a sparse top tap digit or not.
-constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb, int sparse)
+constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb, int shape)
 {
-    for (int mode = 0; mode < 4; ++mode) {
+    for (int mode = 0; mode < kConvModes; ++mode) {
         if (conv_class_of_mode(mode) != kclass) continue;
-        const int M = mode == 3 ? slots - 1 : slots;
-        if (M < (mode == 0 ? 3 : (mode == 3 ? 2 : 1))) continue;
+        const int M = conv_checksum_mode(mode) ? slots - 1 : slots;
+        if (M < (mode == 0 ? 3 : (conv_checksum_mode(mode) ? 2 : 1))) continue;
         for (int b = 1; b <= 31; ++b) {
-            const DigitCounts d = conv_digits(mode, M, b);
-            if (d.la == la && d.lb == lb && d.sparse == sparse) return true;
+            const DigitCounts d = conv_digits(mode, M, b, 64, true);
+            if (d.la == la && d.lb == lb && conv_shape(d) == shape) return true;
         }
-        if (mode == 0 || mode == 2) {  // 32-bit words: a shorter shift l
+        if (mode == 0 || mode == 2 || mode == 4) {  // 32-bit words: a shorter shift l
             const int bmax = conv_w32_max_bits(mode == 0 ? 0 : 1, M);
             for (int b = 1; b <= bmax; ++b) {
-                const DigitCounts d = conv_digits(mode, M, b, 32);
-                if (d.la == la && d.lb == lb && d.sparse == sparse) return true;
+                const DigitCounts d = conv_digits(mode, M, b, 32, true);
+                if (d.la == la && d.lb == lb && conv_shape(d) == shape) return true;
             }
         }
     }
@@ -141,7 +179,7 @@ constexpr bool conv_variant_needed(int kclass, int slots, int la, int lb, int sp
 // 1..max_bits bits, uses digit counts (la, lb) (any top-digit sparsity).
 constexpr bool digits_needed(int kclass, int slots, int la, int lb, int max_bits)
 {
-    for (int mode = 0; mode < 4; ++mode) {
+    for (int mode = 0; mode < 4; ++mode) {  // (the matrix product has no mode 4)
         if (conv_class_of_mode(mode) != kclass) continue;
         const int M = mode == 3 ? slots - 1 : slots;
         if (M < (mode == 0 ? 3 : (mode == 3 ? 2 : 1)) || M > 8) continue;

@@ -26,7 +26,8 @@ enum Mode : int32_t {
     kEntangled = 0,  // the method: entangle, op per stream, extract
     kPlain = 1,      // failure-intolerant op on the raw streams, narrow limbs
     kPlainSame = 2,  // failure-intolerant op on the same datapath as kEntangled
-    kChecksum = 3    // checksum method: M data streams + their sum
+    kChecksum = 3,   // checksum method: M data streams + their sum
+    kChecksumSame = 4  // the checksum method on the same datapath as kEntangled
 };
 
 // Error bits reported through the plan's flag word.
@@ -43,7 +44,7 @@ struct GroupDev {
     int32_t mode;     // Mode
     int32_t r;        // stream left out of recovery (the lost one, else 0)
     int32_t lost;     // 1 if stream r was lost (its operation is not run)
-    int32_t l;        // shift (entangled mode)
+    int32_t l;        // shift (entangled mode; split words: the field boundary too)
     int32_t la, lb;   // limbs of data words / operand values (conv)
     int32_t nslots;   // streams whose operation runs: M, or M + 1 (checksum)
     int32_t nch;      // 64-wide chunks of the inner dimension (conv)
@@ -52,7 +53,8 @@ struct GroupDev {
     int32_t in_lo, in_hi;  // declared input range [in_lo, in_hi]
     int32_t steps;    // conv tile steps (or streaming positions / 256) per block
     int32_t ring;     // positions per LDS digit-plane ring: 256 * ring_waves + kp (conv)
-    int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv)
+    int32_t acc16;    // 1: every acc_s + 256 acc_{s+1} fits in int32 (conv); split
+                      // words: every field's whole digit sum fits in int32
     int32_t dma;      // 1: next-step inputs are prefetched into LDS (conv)
     int32_t skip;     // slot whose operation is not run (the lost stream), or -1
     int32_t kind;     // convolution kernel: 0 linear, 1 circular (length n), 2 cross-correlation
@@ -105,16 +107,16 @@ struct Item {
 };
 
 // One fused convolution kernel variant (fused_conv.hip, compiled once per
-// kernel class and slot count).
-// First index: the taps' top digit is dense (0) or sparse (1); second: one
-// staging ring per block of 4 waves (0) or one per wave (1). Null where no
-// group needs the variant.
-// Indexed [sparse top tap digit][layout].
+// kernel class and slot count), indexed [shape][layout]: shape 0 plain
+// digits, 1 the taps' top digit sparse, 2 data words split into two fields
+// (conv_shape); layout as above. Null where no group needs the variant.
+constexpr int kConvShapeCount = 3;
 struct ConvKernel {
-    void (*launch[2][kConvLayouts])(const GroupDev *g, const Item *items, uint32_t nitems,
-                                    uint32_t *flags, size_t lds, hipStream_t s);
-    hipError_t (*prepare[2][kConvLayouts])(size_t lds);  // raises the dynamic LDS limit
-    hipError_t (*attributes[2][kConvLayouts])(hipFuncAttributes *a);  // of the loaded kernel
+    void (*launch[kConvShapeCount][kConvLayouts])(const GroupDev *g, const Item *items,
+                                                  uint32_t nitems, uint32_t *flags, size_t lds,
+                                                  hipStream_t s);
+    hipError_t (*prepare[kConvShapeCount][kConvLayouts])(size_t lds);  // raises the LDS limit
+    hipError_t (*attributes[kConvShapeCount][kConvLayouts])(hipFuncAttributes *a);  // loaded kernel
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);

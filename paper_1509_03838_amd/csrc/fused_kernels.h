@@ -203,6 +203,24 @@ __device__ __forceinline__ constexpr uint64_t digit_offset()
     return L >= 8 ? 0x8080808080808080ull : (0x8080808080808080ull >> (64 - 8 * L));
 }
 
+// The digit bytes of a split word: the FS low bytes of a (the low field plus
+// its digit offset) and then the FS low bytes of b (the high field), as one
+// little-endian 64-bit value.
+template <int FS>
+__device__ __forceinline__ uint64_t pack_fields(uint32_t a, uint32_t b)
+{
+    if constexpr (FS == 1) {
+        return __builtin_amdgcn_perm(b, a, 0x0c0c0400u);
+    } else if constexpr (FS == 2) {
+        return __builtin_amdgcn_perm(b, a, 0x05040100u);
+    } else if constexpr (FS == 3) {
+        return (uint64_t)__builtin_amdgcn_perm(b, a, 0x04020100u) |
+               ((uint64_t)__builtin_amdgcn_perm(b, b, 0x0c0c0605u) << 32);
+    } else {
+        return (uint64_t)a | ((uint64_t)b << 32);
+    }
+}
+
 // Stage 4 consecutive positions p..p+3 of every data word into the LA digit
 // planes at ring offset `off`. Entanglement happens here, on load.
 // Digit planes in LDS: plane (stream) pl occupies LAP * ring bytes; the 16
@@ -264,10 +282,16 @@ __device__ __forceinline__ void load4(const GroupDev *G, int64_t p, int64_t n, R
 // Converts raw inputs of 4 positions into the LA digit planes (one per slot,
 // NP slots) at ring offset `off`: entanglement (or the checksum sum) happens
 // here. Slot t entangles with slot t - 1, slot 0 with slot DM - 1.
-template <int LA, int DM, int NP, int MODE>
+//
+// FS > 0: every word x is split at bit l into the balanced low field
+// lo = x - 2^l floor(x / 2^l + 1/2) and hi = (x - lo) / 2^l (x = lo + 2^l hi),
+// and each field is cut into FS digits: planes 0 .. FS-1 hold lo's digits,
+// planes FS .. 2 FS - 1 hi's. Computed from x alone, like any digit split.
+template <int LA, int DM, int NP, int MODE, int FS = 0>
 __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char *planes, int ring,
                                        int off, Bounds &bd)
 {
+    static_assert(FS == 0 || (2 * FS == LA && FS <= 4), "field digits");
     constexpr uint64_t C = digit_offset<LA>();
     constexpr int LAP = lap<LA>();
 #pragma unroll
@@ -279,15 +303,31 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
 #pragma unroll
     for (int pl = 0; pl < NP; ++pl) {
         uint32_t lo[4], hi[4];
+        int32_t fields[4][2];  // split words: (lo, hi) of every position (FS > 0 only)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            int64_t x;
+            int64_t x = 0;
             if (MODE == kChecksum && pl == DM) {
                 // the sum of DM b-bit samples needs up to b + 3 bits: 64-bit adds
                 int64_t sum = 0;
 #pragma unroll
                 for (int m = 0; m < DM; ++m) sum += raw.cv[m][q];
                 x = sum;
+                if constexpr (FS > 0) {
+                    fields[q][0] = __builtin_amdgcn_sbfe((int32_t)sum, 0, l);
+                    fields[q][1] = (int32_t)((sum - fields[q][0]) >> l);
+                }
+            } else if constexpr (FS > 0) {
+                // The fields of x = c + 2^l c' (l <= 31; c' = 0 on raw
+                // words) without forming it: x's low l bits are c's, so
+                // lo = c's low l bits sign-extended, hi = c' + (c - lo) / 2^l
+                // (an exact shift). Unsigned wrap keeps inputs outside the
+                // declared range (flagged) well defined.
+                const int32_t c = raw.cv[pl % DM][q];
+                const int32_t cp = MODE == kEntangled ? raw.cv[(pl + DM - 1) % DM][q] : 0;
+                fields[q][0] = __builtin_amdgcn_sbfe(c, 0, l);
+                fields[q][1] = (int32_t)((uint32_t)cp +
+                                         (uint32_t)((int32_t)((uint32_t)c - (uint32_t)fields[q][0]) >> l));
             } else if (MODE == kEntangled) {
                 x = ent(raw.cv[pl % DM][q], raw.cv[(pl + DM - 1) % DM][q], l);
             } else {
@@ -295,7 +335,13 @@ __device__ __forceinline__ void store4(const Raw4<DM> &raw, int l, unsigned char
             }
             // (x has LA digits whenever the inputs lie in the declared range,
             // which the plan sized LA for and the kernel verifies.)
-            const uint64_t u = (uint64_t)x + C;
+            uint64_t u;
+            if constexpr (FS > 0) {
+                constexpr uint32_t CF = (uint32_t)digit_offset<FS>();
+                u = pack_fields<FS>((uint32_t)fields[q][0] + CF, (uint32_t)fields[q][1] + CF);
+            } else {
+                u = (uint64_t)x + C;
+            }
             lo[q] = (uint32_t)u;
             hi[q] = (uint32_t)(u >> 32);
         }
@@ -318,6 +364,29 @@ struct TapWords {
     uint32_t w[n];
 };
 
+// Digit pairs of the convolution's products. The accumulator of data digit a
+// and tap digit b is acc_of(a) + b: weight a + b, or, for words split into
+// fields of FS digits, the high field's weights after the SL = FS + LB - 1 of
+// the low field. Without a split a pair of weight 256^8 or more is a multiple
+// of 2^64 and does not run; with one every pair runs (the high field's weight
+// 2^l 256^(a + b) depends on the group's l). Pairs run b-major, a-minor:
+// pair_first says which one writes its accumulator first.
+template <int FS, int LB>
+__device__ __forceinline__ constexpr int acc_of(int a)
+{
+    return FS && a >= FS ? a + LB - 1 : a;
+}
+template <int FS>
+__device__ __forceinline__ constexpr bool pair_runs(int a, int b)
+{
+    return FS ? true : a + b < 8;
+}
+template <int LA, int FS>
+__device__ __forceinline__ constexpr bool pair_first(int a, int b)
+{
+    return b == 0 || a == LA - 1 || (FS && a == FS - 1);
+}
+
 // One variant per kernel class (0 entangled, 1 plain, 2 checksum) and slot
 // count NS, so that the mode, M and the slot loop are compile-time: the
 // descriptor's mode and M must match (the planner picks the variant).
@@ -331,7 +400,8 @@ struct TapWords {
 // step loop has no barrier at all, at the price of a window of kp extra
 // positions per wave instead of per block.
 // TC: copies of each tap-digit plane (4, or 1 with GW = 4, below).
-template <int LA, int LB, int NS, int KCLASS, int GW, int SP, int TC>
+// FS: digits per field of words split at bit l (0: not split; LA = 2 FS).
+template <int LA, int LB, int NS, int KCLASS, int GW, int SP, int TC, int FS = 0>
 __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
                                                        const Item *__restrict__ items,
                                                        uint32_t nitems, uint32_t *flags)
@@ -343,6 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     static_assert(GW == 1 || GW == 4, "waves per ring");
     static_assert(SP == 0 || (SP == 1 && LB >= 2), "sparse top tap digit");
     static_assert(TC == 4 || (TC == 1 && GW == 4), "tap-plane copies");
+    static_assert(FS == 0 || (2 * FS == LA && SP == 0), "split words");
     constexpr int LBM = LB - SP;     // tap digit planes of the main pass
     constexpr int SPAN = 256 * GW;   // positions a ring advances per step
     constexpr int GT = 64 * GW;      // threads staging one ring
@@ -445,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
         Raw4<M> raw;
         for (int gi = gt; gi < (ring >> 2); gi += GT) {
             load4<M>(G, base + 4 * gi, n, raw);
-            store4<LA, M, nplanes, mode>(raw, l, planes, ring, 4 * gi, bd);
+            store4<LA, M, nplanes, mode, FS>(raw, l, planes, ring, 4 * gi, bd);
         }
     }
     __syncthreads();  // tap planes (and the first windows) complete
@@ -512,8 +583,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             // One accumulator per digit weight s = a + b: the matrix core
             // sums the digit pairs of equal weight. A pair with a + b >= 8 is
             // a multiple of 2^64 and is skipped. Chunk 0 (there is always
-            // one) starts every weight from zero.
-            constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+            // one) starts every weight from zero. Split words: weights
+            // 256^s of the low field in acc[0 .. SL), 2^l 256^s of the high
+            // field in acc[SL ..); every pair runs (l is not known here).
+            constexpr int SL = FS + LB - 1;
+            constexpr int S = FS ? 2 * SL : ((LA + LB - 1) < 8 ? (LA + LB - 1) : 8);
             v4i acc[S];
             int o = aoff;
             using TW = TapWords<TC>;
@@ -532,9 +606,9 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                     const v4i bf = tap_frag(bw[b]);
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf,
-                                                                              acc[a + b], 0, 0, 0);
+                        if (pair_runs<FS>(a, b))
+                            acc[acc_of<FS, LB>(a) + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bf, acc[acc_of<FS, LB>(a) + b], 0, 0, 0);
                 }
             };
             // chunk 0 starts every weight the main pass reaches (its first pair
@@ -547,9 +621,11 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                     const v4i bf = tap_frag(bw[b]);
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af[a], bf, (b == 0 || a == LA - 1) ? v4i{0, 0, 0, 0} : acc[a + b],
+                        if (pair_runs<FS>(a, b))
+                            acc[acc_of<FS, LB>(a) + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                af[a], bf,
+                                pair_first<LA, FS>(a, b) ? v4i{0, 0, 0, 0}
+                                                         : acc[acc_of<FS, LB>(a) + b],
                                 0, 0, 0);
                 }
             };
@@ -624,7 +700,33 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             // sums are merged in 32 bits first and the 64-bit Horner steps
             // over 16-bit shifts.
             constexpr int H = (S + 1) / 2;
-            if (acc16) {
+            if constexpr (FS > 0) {
+                // y = lo + 2^l hi, each field's sum sum_s 256^s acc_s in 32
+                // bits when the plan has shown it fits (acc16), else in 64
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    uint64_t ylo, yhi;
+                    if (acc16) {
+                        uint32_t zl = (uint32_t)acc[SL - 1][v], zh = (uint32_t)acc[S - 1][v];
+#pragma unroll
+                        for (int k = SL - 2; k >= 0; --k) {
+                            zl = (zl << 8) + (uint32_t)acc[k][v];
+                            zh = (zh << 8) + (uint32_t)acc[SL + k][v];
+                        }
+                        ylo = (uint64_t)(int64_t)(int32_t)zl;
+                        yhi = (uint64_t)(int64_t)(int32_t)zh;
+                    } else {
+                        ylo = (uint64_t)(int64_t)acc[SL - 1][v];
+                        yhi = (uint64_t)(int64_t)acc[S - 1][v];
+#pragma unroll
+                        for (int k = SL - 2; k >= 0; --k) {
+                            ylo = (ylo << 8) + (uint64_t)(int64_t)acc[k][v];
+                            yhi = (yhi << 8) + (uint64_t)(int64_t)acc[SL + k][v];
+                        }
+                    }
+                    dl[t][v] = (int64_t)(ylo + (yhi << l));
+                }
+            } else if (acc16) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     int32_t z[H];
@@ -669,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             }
             epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);
             if (GW > 1) __syncthreads();  // every wave is done with the ring slots reused here
-            store4<LA, M, nplanes, mode>(raw, l, planes, ring, soff, bd);
+            store4<LA, M, nplanes, mode, FS>(raw, l, planes, ring, soff, bd);
             if (step + 2 < steps && Tn + SPAN < n_out) dma(Tn + SPAN);
         } else {
             epilogue<NS, 4>(G, mode, M, skip, l, P0, n_out - P0, loc, dl, flag);

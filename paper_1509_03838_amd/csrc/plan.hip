@@ -62,17 +62,17 @@ inline bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p % a) == 0
 // block's 4 waves take one wave slot on each SIMD, and a SIMD holds
 // 512 / (VGPRs per lane, in granules of 8) waves. Read from the loaded
 // kernel once per variant; 4 (the plan's cap) where no device can say.
-int register_blocks(const ConvKernel *ck, int sparse, int layout)
+int register_blocks(const ConvKernel *ck, int shape, int layout)
 {
     static std::mutex mu;
     static std::map<std::tuple<const ConvKernel *, int, int>, int> cache;
-    const auto key = std::make_tuple(ck, sparse, layout);
+    const auto key = std::make_tuple(ck, shape, layout);
     std::lock_guard<std::mutex> lock(mu);
     const auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int blocks = 4;
     hipFuncAttributes a{};
-    if (ck->attributes[sparse][layout] && ck->attributes[sparse][layout](&a) == hipSuccess &&
+    if (ck->attributes[shape][layout] && ck->attributes[shape][layout](&a) == hipSuccess &&
         a.numRegs > 0)
         blocks = std::min(4, 512 / ((a.numRegs + 7) & ~7));
     else
@@ -89,7 +89,7 @@ static hipError_t plan_prepare(const ne_plan *plan)
 {
     for (const Bucket &b : plan->buckets) {
         if (b.conv <= 0 || b.lds <= 64 * 1024) continue;
-        const hipError_t e = b.ck->prepare[(b.cls >> 2) & 1][b.cls & 3](b.lds);
+        const hipError_t e = b.ck->prepare[(b.cls >> 2) & 3][b.cls & 3](b.lds);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -101,8 +101,9 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
                             const ne_tuning *tuning, ne_plan **out_plan)
 {
     if (!out_plan || n_groups < 0 || (n_groups > 0 && !groups)) return NE_EINVAL;
-    if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
+    if (mode < kEntangled || mode > kChecksumSame) return NE_EINVAL;
     *out_plan = nullptr;
+    const bool checksum = mode == kChecksum || mode == kChecksumSame;
     const int conv_steps = (tuning && tuning->conv_steps > 0) ? tuning->conv_steps : kConvStepsDefault;
     const int stream_steps =
         (tuning && tuning->stream_steps > 0) ? tuning->stream_steps : kStreamStepsDefault;
@@ -129,7 +130,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             delete plan;
             return s;
         };
-        const int minM = mode == kEntangled ? 3 : (mode == kChecksum ? 2 : 1);
+        const int minM = mode == kEntangled ? 3 : (checksum ? 2 : 1);
         if (u.M < minM || u.M > kFusedMaxM || u.n < 0 || u.in_bits < 1 || u.in_bits > 32)
             return fail(NE_EINVAL);
         if (u.lost < -1 || u.lost >= u.M) return fail(NE_EFAILIDX);
@@ -197,17 +198,17 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             if (bound > (unsigned __int128)D) return fail(NE_ERANGE);
         } else {
             const unsigned __int128 lim = ((unsigned __int128)1 << (w - 1)) - 1;
-            const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)u.M : bound;
+            const unsigned __int128 chk = checksum ? bound * (unsigned)u.M : bound;
             if (chk > lim) return fail(NE_ERANGE);
         }
 
         G.op = u.op;
         G.M = u.M;
-        G.mode = mode;
+        G.mode = checksum ? kChecksum : mode;  // the kernels run either checksum datapath alike
         G.lost = u.lost >= 0 ? 1 : 0;
         G.r = u.lost >= 0 ? u.lost : 0;
         G.l = l;
-        G.nslots = mode == kChecksum ? u.M + 1 : u.M;
+        G.nslots = checksum ? u.M + 1 : u.M;
         G.in_lo = u.in_bits == 32 ? INT32_MIN : -(int32_t)((int64_t)1 << (u.in_bits - 1));
         G.in_hi = u.in_bits == 32 ? INT32_MAX : (int32_t)(((int64_t)1 << (u.in_bits - 1)) - 1);
         G.n = u.n;
@@ -236,22 +237,36 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
 
         if (n_out == 0) continue;
         if (convlike) {
-            const DigitCounts dc = conv_digits(mode, u.M, u.in_bits, w);
-            const int la = dc.la, lb = dc.lb;
+            const DigitCounts dc = conv_digits(mode, u.M, u.in_bits, w, true);
+            const int la = dc.la, lb = dc.lb, shape = conv_shape(dc);
             if (la > kLimbsA || lb > kLimbsB) return fail(NE_EUNSUP);
             G.la = la;
             G.lb = lb;
             G.nch = (int)((u.n_operand + 15 + 63) / 64);
             G.kp = 64 * G.nch - 16;
-            // Neighbouring digit sums merge in int32 when
-            // |acc_s| + 256 |acc_{s+1}| < 2^31, |acc_s| <= min(la, lb) 64 nch 2^14.
-            G.acc16 = (int64_t)257 * std::min(la, lb) * 64 * G.nch * 16384 < ((int64_t)1 << 31);
+            // digits per field: a split word's pairs of one weight come from
+            // one field
+            const int fa = dc.split ? la / 2 : la;
+            if (dc.split) {
+                // the field boundary is the datapath's shift l in every mode
+                // (groups of fewer than 3 streams take M = 3's)
+                G.l = dc.l;
+                // each field's whole digit sum fits in int32 when its
+                // convolution does: |field| <= M 2^(b-1) (the checksum sum),
+                // |taps| <= 2^(b-1), K taps
+                const unsigned __int128 field = checksum ? B * (unsigned)u.M : B;
+                G.acc16 = field * B * (unsigned __int128)u.n_operand < ((unsigned __int128)1 << 31);
+            } else {
+                // Neighbouring digit sums merge in int32 when
+                // |acc_s| + 256 |acc_{s+1}| < 2^31, |acc_s| <= min(la, lb) 64 nch 2^14.
+                G.acc16 = (int64_t)257 * std::min(la, lb) * 64 * G.nch * 16384 < ((int64_t)1 << 31);
+            }
             G.steps = g_conv_steps;
             // int32 accumulation: a digit product is at most 2^14, summed over
-            // 64 nch inputs and at most min(la, lb) digit pairs per shift.
-            if ((int64_t)64 * G.nch * std::min(la, lb) * 16384 >= ((int64_t)1 << 31))
+            // 64 nch inputs and at most min(fa, lb) digit pairs per shift.
+            if ((int64_t)64 * G.nch * std::min(fa, lb) * 16384 >= ((int64_t)1 << 31))
                 return fail(NE_EUNSUP);
-            const int nplanes = mode == kChecksum ? u.M + 1 : u.M;
+            const int nplanes = G.nslots;
             // LDS: tap-digit planes | digit-plane rings (one per block, or
             // one per wave with a window of 256 + kp each) | raw int32
             // staging of one step (the prefetch, below). Layouts: 0 block
@@ -267,12 +282,12 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // when it costs no block.
             const int kclass = conv_class_of_mode(mode);
             const ConvKernel *ck = conv_kernel(kclass, G.nslots, la, lb);
-            if (!ck || !ck->launch[dc.sparse][0]) return fail(NE_EUNSUP);
+            if (!ck || !ck->launch[shape][0]) return fail(NE_EUNSUP);
             const size_t raw = (size_t)u.M * 4096;
             auto fit = [&](int layout, bool dma) {
                 const size_t b = ring_lds(layout) + (dma ? raw : 0);
                 if (b > kMaxLds) return (size_t)0;
-                return std::min<size_t>(register_blocks(ck, dc.sparse, layout), kMaxLds / b);
+                return std::min<size_t>(register_blocks(ck, shape, layout), kMaxLds / b);
             };
             auto use_dma = [&](int layout) {
                 return g_conv_steps > 1 && fit(layout, true) >= fit(layout, false);
@@ -301,7 +316,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             const size_t lds = ring_lds(layout) + (G.dma ? raw : 0);
             const int64_t strip = (int64_t)g_conv_steps * kConvTile;
             const int64_t nstrips = (n_out + strip - 1) / strip;
-            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 3) | (dc.sparse << 2) | layout,
+            auto key = std::make_tuple(1, ((kclass * 16 + G.nslots) << 4) | (shape << 2) | layout,
                                        la, lb);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
@@ -348,7 +363,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         b.la = std::get<2>(kv.first);
         b.lb = std::get<3>(kv.first);
         b.lds = b.conv > 0 ? bucket_lds[kv.first] : 0;
-        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 3) / 16, (b.cls >> 3) % 16, b.la, b.lb) : nullptr;
+        b.ck = b.conv > 0 ? conv_kernel((b.cls >> 4) / 16, (b.cls >> 4) % 16, b.la, b.lb) : nullptr;
         b.sk = b.conv == 0 ? stream_kernel(b.cls / 64, (b.cls / 16) % 4, b.cls % 16) : nullptr;
         b.first = (uint32_t)all_items.size();
         b.count = (uint32_t)kv.second.size();
@@ -486,7 +501,7 @@ static void launch_bucket(const ne_plan *plan, const Bucket &b, hipStream_t s)
     if (b.conv < 0)
         fused_interleave_launch(b.cls, plan->d_groups, plan->d_items + b.first, b.count, s);
     else if (b.conv)
-        b.ck->launch[(b.cls >> 2) & 1][b.cls & 3](plan->d_groups, plan->d_items + b.first, b.count,
+        b.ck->launch[(b.cls >> 2) & 3][b.cls & 3](plan->d_groups, plan->d_items + b.first, b.count,
                                                   plan->d_flags, b.lds, s);
     else
         b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);

@@ -32,10 +32,10 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
-           "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc")
+           "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc", "ne_stream_widen")
 
 FUSED_MAX_M = 8
-MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3}
+MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3, "checksum_same": 4}
 FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH, FLAG_PERM_INDEX = 1, 2, 4, 8
 
 
@@ -118,6 +118,7 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
+        "ne_stream_widen": (_i32, [_P, _i64, _P, _P]),
         "ne_chain_apply_noalloc": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P,
                                           _i64, _u32, _P]),
         "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P,
@@ -655,6 +656,18 @@ def chain_apply_noalloc(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence,
            load().ne_chain_apply_noalloc(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
                                          _ptr_array(delta), n, mask & 0xFFFFFFFF,
                                          _stream(stream)))
+
+
+def stream_widen(src, dst, stream=None):
+    """dst[i] = src[i] widened to int64: the HBM ceiling reference (4 bytes
+    read, 8 written per element, the fused convolution's mix)."""
+    import torch
+    _dtype([src], torch.int32, "src")
+    _dtype([dst], torch.int64, "dst")
+    _on_device("src and dst", [src, dst])
+    n = src.numel()
+    _lengths("dst", [dst], n, exact=False)
+    _check("ne_stream_widen", load().ne_stream_widen(_ptr(src), n, _ptr(dst), _stream(stream)))
 
 
 def gemm_workspace_size(mode: str, M: int, N: int, P: int, Q: int, in_bits: int) -> int:

@@ -118,6 +118,7 @@ class ServeReport:
     mean_batch: float
     peak_bytes: int
     lost_jobs: int
+    deferred_jobs: int   # jobs that waited for HBM footprint while a lane was free
     records: list = field(repr=False, default_factory=list)
 
     def as_dict(self) -> dict:
@@ -191,6 +192,7 @@ class Server:
         free = list(range(len(self.lanes)))
         in_use = peak = 0
         nbatches = nbatch_jobs = 0
+        deferred_jobs: set[int] = set()
         torch.cuda.synchronize()
         t0 = time.perf_counter() + start_delay
         done = 0
@@ -222,6 +224,7 @@ class Server:
                 while waiting and len(take) < self.max_batch:
                     f = self.footprint(jobs[waiting[0]])
                     if in_use + nbytes + f > self.budget:
+                        deferred_jobs.add(waiting[0])
                         break
                     take.append(waiting.popleft())
                     nbytes += f
@@ -247,7 +250,8 @@ class Server:
             max_ms=float(lat.max()), jobs_per_s=len(recs) / makespan,
             gout_per_s=samples / makespan / 1e9, batches=nbatches,
             mean_batch=nbatch_jobs / max(1, nbatches), peak_bytes=peak,
-            lost_jobs=sum(r.lost >= 0 for r in recs), records=recs)
+            lost_jobs=sum(r.lost >= 0 for r in recs), deferred_jobs=len(deferred_jobs),
+            records=recs)
 
     def _launch(self, lane, take, jobs, staged, recs, busy, nbytes, t0) -> bool:
         torch = self.torch

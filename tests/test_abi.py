@@ -178,7 +178,7 @@ def test_plan_rejects_misaligned_inputs(lib):
 
 
 @pytest.mark.parametrize("word_bits", [0, 32])
-@pytest.mark.parametrize("mode,m_lo", [(0, 3), (1, 1), (2, 1), (3, 2)])
+@pytest.mark.parametrize("mode,m_lo", [(0, 3), (1, 1), (2, 1), (3, 2), (4, 2)])
 def test_every_planned_convolution_has_a_kernel_variant(lib, mode, m_lo, word_bits):
     """The planner picks the digit counts of a convolution group from its
     declared input bits (and, for entangled and plain-same groups, the word
@@ -269,7 +269,7 @@ def test_word32_groups_check_the_narrower_range(lib):
     assert ws(3, 32, 12, 128) == 0        # 3 * 128 * 2^22 = 3 * 2^29
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("M", [3, 8])
 def test_paper_experiment_shapes_plan(lib, mode, M):
     """The paper's experiment (Sec. V) convolves M in {3, 8} streams of 10^6
@@ -487,3 +487,14 @@ def test_chain_noalloc_refuses_series_past_its_buffer(lib):
     # argument errors come first as well (a wrong n_out)
     st = lib.ne_chain_apply_noalloc(M, 100, fake, ne._chain_c(ops), len(ops), fake, 99, 7, None)
     assert st == -1
+
+
+def test_stream_widen_argument_checks(lib):
+    """Misaligned, overlapping or missing buffers are refused before any
+    launch (the addresses are never dereferenced)."""
+    assert lib.ne_stream_widen(FAKE, -1, FAKE + 4096, None) == -1
+    assert lib.ne_stream_widen(None, 0, None, None) == 0        # nothing to copy
+    assert lib.ne_stream_widen(None, 16, FAKE, None) == -1
+    assert lib.ne_stream_widen(FAKE + 4, 16, FAKE + 4096, None) == -1   # misaligned input
+    assert lib.ne_stream_widen(FAKE, 16, FAKE + 8, None) == -1          # misaligned output
+    assert lib.ne_stream_widen(FAKE, 16, FAKE + 32, None) == -1         # overlapping

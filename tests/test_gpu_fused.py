@@ -82,14 +82,14 @@ def test_small_config_every_loss_fused():
         assert np.array_equal(dg.result(), ref), lost
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("M", [3, 4, 5, 8])
 @pytest.mark.parametrize("n,K,bits", [(1, 1, 8), (5, 3, 12), (3001, 37, 12), (4096, 64, 12),
                                       (5000, 300, 10), (2049, 1024, 16), (1, 1024, 11)])
 def test_conv_modes(mode, M, n, K, bits):
     grp = make("conv", M, n, K, bits, seed=M * 1000 + n + K)
     ref = oracle.apply("conv", grp.c, grp.operand)
-    losses = [-1] + list(range(M)) if mode in ("entangled", "checksum") else [-1]
+    losses = [-1] + list(range(M)) if mode in ("entangled", "checksum", "checksum_same") else [-1]
     for lost in losses:
         for rw in (4, 1):  # one staging ring per block / per wave
             dg = DevGroup(grp, bits, lost, mode, ring_waves=rw)
@@ -102,14 +102,14 @@ def test_conv_modes(mode, M, n, K, bits):
             assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost, rw)
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("op", ["scale", "add", "inner", "perm"])
 @pytest.mark.parametrize("M", [3, 5, 8])
 def test_streaming_ops_modes(mode, op, M):
     for n in (1, 255, 4097, 70001):
         grp = make(op, M, n, 0, 10, seed=n * 13 + M + len(op))
         ref = oracle.apply(op, grp.c, grp.operand if op != "scale" else None, grp.scalar)
-        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum", "checksum_same") else [-1]
         for lost in losses:
             dg = DevGroup(grp, 10, lost, mode)
             _, flags = run([dg], mode)
@@ -234,19 +234,20 @@ def test_tuning_steps(steps, ring_waves):
 
 
 @pytest.mark.parametrize("mode,m_lo", [("entangled", 3), ("plain", 1), ("plain_same", 1),
-                                       ("checksum", 2)])
+                                       ("checksum", 2), ("checksum_same", 2)])
 def test_every_convolution_variant(mode, m_lo):
     """Every (M, digit-count) kernel variant the planner can pick for this
     mode, in each LDS layout (block ring with 4 or 1 tap copies, per-wave
     rings), on a short convolution with a ragged tail, with and without a
-    lost stream: inputs of 1, 2, 8, 9, 16, 17, 24, 25 and 31 bits."""
+    lost stream: inputs of 1, 2, 8, 9, 12, 15, 16, 17, 24, 25 and 31 bits
+    (words split into two fields at 1-15 bits for M = 3, at 1-8 for M = 4)."""
     ran = 0
     for M in range(m_lo, 9):
-        for bits in (1, 2, 8, 9, 16, 17, 24, 25, 31):
+        for bits in (1, 2, 8, 9, 12, 15, 16, 17, 24, 25, 31):
             grp = make("conv", M, 1500, 7, bits, seed=7000 + 100 * M + bits)
             ref = oracle.apply("conv", grp.c, grp.operand)
             for lost, rw, tc in ([(-1, 4, 4), (M - 1, 1, 0), (M - 1, 4, 1)]
-                                 if mode in ("entangled", "checksum")
+                                 if mode in ("entangled", "checksum", "checksum_same")
                                  else [(-1, 4, 4), (-1, 1, 0), (-1, 4, 1)]):
                 dg = DevGroup(grp, bits, lost, mode, ring_waves=rw, tap_copies=tc)
                 try:
@@ -292,7 +293,7 @@ def make_more(op, M, n, K, bits, seed):
     return wl.Group(op, c, operand, 0)
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("op", ["sub", "mul"])
 @pytest.mark.parametrize("M", [3, 5, 8])
 def test_more_streaming_ops_fused(mode, op, M):
@@ -302,7 +303,7 @@ def test_more_streaming_ops_fused(mode, op, M):
     for n in (1, 255, 4097, 70001):
         grp = make_more(op, M, n, 0, 10, seed=n * 17 + M + len(op))
         ref = oracle.apply(op, grp.c, grp.operand)
-        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+        losses = [-1, 0, M - 1] if mode in ("entangled", "checksum", "checksum_same") else [-1]
         for lost in losses:
             dg = DevGroup(grp, 10, lost, mode)
             _, flags = run([dg], mode)
@@ -310,7 +311,7 @@ def test_more_streaming_ops_fused(mode, op, M):
             assert np.array_equal(dg.result(), ref), (mode, op, M, n, lost)
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("M", [3, 5, 8])
 @pytest.mark.parametrize("n,K", [(1, 1), (5, 3), (1001, 1), (777, 13), (4097, 64), (3, 1500)])
 def test_outer_product_fused(mode, M, n, K):
@@ -319,7 +320,7 @@ def test_outer_product_fused(mode, M, n, K):
     mode and loss position; outputs equal the oracle's row-major product."""
     grp = make_more("outer", M, n, K, 10, seed=n * 7 + K + M)
     ref = oracle.apply("outer", grp.c, grp.operand)
-    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum", "checksum_same") else [-1]
     for lost in losses:
         dg = DevGroup(grp, 10, lost, mode)
         _, flags = run([dg], mode)
@@ -327,7 +328,7 @@ def test_outer_product_fused(mode, M, n, K):
         assert np.array_equal(dg.result(), ref), (mode, M, n, K, lost)
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("op", ["circ", "xcorr"])
 @pytest.mark.parametrize("M", [3, 8])
 @pytest.mark.parametrize("n,K,bits", [(1, 1, 8), (5, 3, 12), (3001, 37, 12), (700, 1500, 10),
@@ -338,7 +339,7 @@ def test_circular_and_cross_correlation_fused(mode, op, M, n, K, bits):
     LDS layout, every mode and loss position."""
     grp = make_more(op, M, n, K, bits, seed=M * 1000 + n + K + len(op))
     ref = oracle.apply(op, grp.c, grp.operand)
-    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum") else [-1]
+    losses = [-1, 0, M - 1] if mode in ("entangled", "checksum", "checksum_same") else [-1]
     for lost in losses:
         for rw, tc in ((4, 4), (1, 0), (4, 1)):
             dg = DevGroup(grp, bits, lost, mode, ring_waves=rw, tap_copies=tc)
@@ -385,3 +386,24 @@ def test_all_operators_in_one_captured_plan():
             for grp, d in specs:
                 assert np.array_equal(d.result(), d.reference()), (grp.op, grp.M, grp.n, rep)
     plan.close()
+
+
+def test_split_words_take_fewer_digit_planes():
+    """12-bit samples at M = 3 (the batched workload's range): entangled
+    words run on 2 + 2 digit planes (split at bit l) instead of 5, so the
+    matrix-core work issued is twice the plain convolution's (2 planes), not
+    2.5 times; plain-same issues what the entangled run does, the checksum
+    method on that datapath 4/3 of it (one more stream). Bit-exact in every
+    mode."""
+    grp = make("conv", 3, 20000, 64, 12, seed=4321)
+    ref = oracle.apply("conv", grp.c, grp.operand)
+    macs = {}
+    for mode in ("entangled", "plain", "plain_same", "checksum_same"):
+        dg = DevGroup(grp, 12, -1, mode)
+        plan, flags = run([dg], mode)
+        assert flags == 0 and np.array_equal(dg.result(), ref), mode
+        macs[mode] = plan.stats()["mfma_macs"]
+        plan.close()
+    assert macs["entangled"] == 2 * macs["plain"]
+    assert macs["plain_same"] == macs["entangled"]
+    assert 3 * macs["checksum_same"] == 4 * macs["entangled"]

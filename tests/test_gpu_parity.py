@@ -337,3 +337,17 @@ def test_plain_more_ops(op, n):
     ne.plain_apply(op, streams(c, torch.int32), dev(operand, torch.int32), d)
     got = np.stack([host(t) for t in d])
     assert np.array_equal(got, oracle.apply(op, c, operand)), (op, n)
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 4099, 1 << 20, (1 << 22) + 7])
+def test_stream_widen_copies_exactly(n):
+    """The bandwidth reference: every int32 widened to int64, ragged tails
+    included, nothing written past n."""
+    g = wl.rng(60 + n % 97)
+    src = torch.from_numpy(wl.uniform_i32(g, -(1 << 31), (1 << 31) - 1, n)).to(DEV)
+    dst = torch.full((n + 8,), POISON, dtype=torch.int64, device=DEV)
+    ne.stream_widen(src, dst)
+    torch.cuda.synchronize()
+    got = dst.cpu().numpy()
+    assert np.array_equal(got[:n], src.cpu().numpy().astype(np.int64))
+    assert (got[n:] == POISON).all()

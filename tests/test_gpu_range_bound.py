@@ -38,7 +38,7 @@ def limit(mode: str, M: int, w: int = 64) -> int:
     if mode == "entangled":
         return oracle.params(M, w)[2]
     lim = (1 << (w - 1)) - 1
-    return lim // M if mode == "checksum" else lim
+    return lim // M if mode in ("checksum", "checksum_same") else lim
 
 
 def extremes(pattern: int, n: int, b: int, g: np.random.Generator) -> np.ndarray:
@@ -70,7 +70,7 @@ def conv_cases(mode: str, M: int, w: int = 64):
 
 
 def losses(mode: str, M: int):
-    if mode not in ("entangled", "checksum"):
+    if mode not in ("entangled", "checksum", "checksum_same"):
         return [-1]
     return [-1] + (list(range(M)) if M <= 5 else [0, M // 2, M - 1])
 
@@ -93,7 +93,7 @@ def run_group(op, c, operand, scalar, lost, bits, mode, n_out, rw=0, tc=0, word_
 
 @pytest.mark.parametrize("word_bits", [0, 32])
 @pytest.mark.parametrize("mode,m_lo", [("entangled", 3), ("plain", 1), ("plain_same", 1),
-                                       ("checksum", 2)])
+                                       ("checksum", 2), ("checksum_same", 2)])
 def test_convolution_at_the_range_bound(mode, m_lo, word_bits):
     w = 32 if word_bits == 32 else 64
     g = wl.rng(4242 + m_lo + w)
@@ -126,7 +126,7 @@ def test_convolution_at_the_range_bound(mode, m_lo, word_bits):
     assert ran > 0
 
 
-@pytest.mark.parametrize("mode", ["entangled", "checksum", "plain"])
+@pytest.mark.parametrize("mode", ["entangled", "checksum", "checksum_same", "plain"])
 @pytest.mark.parametrize("M", [3, 8])
 def test_convolution_one_past_the_bound_is_refused(mode, M):
     """The plan refuses the next tap count past the bound (NE_ERANGE)."""
@@ -152,7 +152,7 @@ def elementwise_cases(op: str, mode: str, M: int, n: int):
     return [(b, 0)]
 
 
-@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum"])
+@pytest.mark.parametrize("mode", ["entangled", "plain", "plain_same", "checksum", "checksum_same"])
 @pytest.mark.parametrize("op", ["scale", "add", "sub", "mul", "inner", "outer", "perm"])
 @pytest.mark.parametrize("M", [3, 5, 8])
 def test_elementwise_at_the_range_bound(mode, op, M):
@@ -175,3 +175,45 @@ def test_elementwise_at_the_range_bound(mode, op, M):
                 got, flags = run_group(op, c, operand, s, lost, b, mode, n_out)
                 assert flags == 0, (op, mode, M, b, s, lost, flags)
                 assert np.array_equal(got, ref), (op, mode, M, b, s, tp, lost)
+
+
+def split_acc16_limit(mode: str, M: int, b: int) -> int:
+    """Most taps for which every field's whole digit sum of a split word fits
+    in int32: |field| K 2^(b-1) < 2^31, |field| = 2^(b-1) (M 2^(b-1) for the
+    checksum stream)."""
+    field = (1 << (b - 1)) * (M if mode == "checksum_same" else 1)
+    return ((1 << 31) - 1) // (field << (b - 1))
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain_same", "checksum_same"])
+@pytest.mark.parametrize("M,b", [(3, 12), (3, 15), (3, 8), (4, 8)])
+def test_split_words_at_their_limits(mode, M, b):
+    """Words split into two fields (12- and 15-bit samples at M = 3, 8-bit
+    at M = 3 and 4): every sample and tap at the ends of its range, with the
+    tap count on both sides of the 32-bit field sums (their largest K, and
+    one more), and the longest kernel of the paper's experiment at 15 bits,
+    under every loss and in every LDS layout."""
+    g = wl.rng(9100 + M * 31 + b)
+    k32 = split_acc16_limit(mode, M, b)
+    Ks = sorted({k for k in (k32, k32 + 1, 64, 4500 if b == 15 else 0) if 0 < k <= 4500})
+    n = 3000
+    ran = 0
+    for K in Ks:
+        assert (1 << (2 * b - 2)) * K <= limit(mode, M)
+        for tp in (0, 2, 3):
+            c = np.stack([extremes((m + tp) % 4, n, b, g) for m in range(M)])
+            k = extremes(tp, K, b, g)
+            ref = oracle.apply("conv", c, k)
+            for lost in losses(mode, M):
+                for rw, tc in LAYOUTS:
+                    if tp != 3 and (rw, tc) != LAYOUTS[0]:
+                        continue
+                    try:
+                        got, flags = run_group("conv", c, k, 0, lost, b, mode, n + K - 1, rw, tc)
+                    except ne.NeError as e:
+                        assert e.status == -4 and rw == 1, (mode, M, b, K, rw, e)
+                        continue
+                    assert flags == 0, (mode, M, b, K, tp, lost, rw, tc, flags)
+                    assert np.array_equal(got, ref), (mode, M, b, K, tp, lost, rw, tc)
+                    ran += 1
+    assert ran > 0

@@ -39,6 +39,32 @@ def test_serving_results_alone_equal_in_the_mix():
         solo = alone(job)
         for a, b in zip(mixed, solo):
             assert np.array_equal(a, b), r.index
-        if job.group.n <= 5000:
-            ref = oracle.apply("conv", job.group.c, job.group.operand)
+        g = job.group
+        if g.n <= 5000:
+            ref = oracle.apply("conv", g.c, g.operand)
             assert np.array_equal(np.stack(mixed), ref), r.index
+        else:  # every stream at both ends and 1000 seeded positions between
+            n_out = g.n + g.operand.size - 1
+            pos = np.unique(np.concatenate([
+                np.arange(64), np.arange(n_out - 64, n_out),
+                wl.rng(r.index).integers(0, n_out, 1000)]))
+            for m in range(g.M):
+                assert np.array_equal(mixed[m][pos], oracle.conv_at(g.c[m], g.operand, pos)), \
+                    (r.index, m)
+
+
+def test_serving_defers_by_footprint_and_batches():
+    """Under a load the device cannot absorb job by job (a burst of 60
+    jobs, one lane, a budget of a few jobs), the server forms batches of
+    several jobs and defers admissions on the HBM budget; every result is
+    still the oracle's."""
+    from paper_1509_03838_amd.serve import Server
+    jobs = wl.serving_jobs(seed=11, count=60, rate_hz=200_000.0, n_hi=1 << 14, drop_prob=0.1)
+    srv = Server(hbm_budget=4 << 20, lanes=1, max_batch=16, keep_outputs=True)
+    rep = srv.run(jobs)
+    assert rep.jobs == 60 and rep.peak_bytes <= 4 << 20
+    assert rep.mean_batch > 1 and rep.deferred_jobs > 0
+    torch.cuda.synchronize()
+    for r, job in zip(rep.records, jobs):
+        ref = oracle.apply("conv", job.group.c, job.group.operand)
+        assert np.array_equal(np.stack([t.cpu().numpy() for t in r.outputs]), ref), r.index
