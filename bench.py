@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     p.add_argument("--rounds", type=int, default=3,
                    help="interleaved timing rounds per mode (each of --steps launches)")
+    p.add_argument("--settle-ms", type=int, default=300,
+                   help="untimed launches of every mode for this long before timing")
     p.add_argument("--no-serving", action="store_true",
                    help="batched line: skip the short serving run")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -190,6 +192,16 @@ def main():
     # pairs of each mode's datapath times the Toeplitz padding
     plan_digits = {name_of(k): round(p.stats()["mfma_macs"] / max(1, p.stats()["macs"]), 3)
                    for k, p in plans.items()}
+    # The device is brought to its steady clock before anything is timed:
+    # untimed launches of every plan in turn for --settle-ms (a cold device
+    # runs the first tens of launches about 10% slower), then the W warm-up
+    # launches of each mode.
+    t_settle = time.perf_counter() + args.settle_ms / 1e3
+    with torch.cuda.stream(stream):
+        while time.perf_counter() < t_settle:
+            for p in plans.values():
+                p.launch(stream)
+            stream.synchronize()
     rounds = {k: [] for k in runs}
     walls = []
     out_ref = None
@@ -267,7 +279,8 @@ def main():
         "tuned_steps": tuned_summary(tuned, main_mode),
     }
     line["timing"] = (f"median of {args.rounds} rounds of {args.steps} captured launches per "
-                      "mode, the modes interleaved with a rotating order")
+                      f"mode, the modes interleaved with a rotating order, after {args.settle_ms} ms "
+                      f"of untimed launches of every mode and {args.warmup} warm-up launches each")
     if not args.only and not args.no_baselines:
         def pct(a, b):
             return round(100 * (results[a] / results[b] - 1), 2)
