@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--only", default=None,
                    choices=("entangled", "plain", "plain_same", "checksum", "checksum_same"),
                    help="time one mode only (profiling)")
+    p.add_argument("--mfma-probe", action="store_true",
+                   help="only launch the matrix-core reference with fixed and with random "
+                        "operands, twice each (for its counters), and exit")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only widen an int32 buffer of this many MiB into int64 a few times "
                         "(ne_stream_widen, a kernel of known traffic, to calibrate the HBM byte "
@@ -115,6 +118,17 @@ def main():
 
     from paper_1509_03838_amd import ne
     from paper_1509_03838_amd import workloads as wl
+
+    if args.mfma_probe:
+        # the matrix-core reference alone (profiling): fixed, then random
+        # operands, twice each
+        ne.load()
+        sink = torch.empty(4 * 2048, dtype=torch.int32, device="cuda:0")
+        for varied in (False, True, False, True):
+            ne.mfma_i8_peak(sink, 2048, 4096, varied)
+            torch.cuda.synchronize()
+        print(json.dumps({"kernel": "k_mfma_i8_peak", "launches": 4}))
+        return
 
     if args.copy_calibration:
         # a kernel of known traffic for the HBM byte counters: the library's
@@ -188,9 +202,9 @@ def main():
         plans[(mode, lost)] = make_plan(mode, lost)
     ent = plans[(main_mode, -1)]
     stats = ent.stats()
-    # i8 matrix-core multiply-adds issued per useful multiply-add: the digit
-    # pairs of each mode's datapath times the Toeplitz padding
-    plan_digits = {name_of(k): round(p.stats()["mfma_macs"] / max(1, p.stats()["macs"]), 3)
+    # digit pairs each useful multiply-add takes on the matrix cores, per mode
+    # (the datapath's cost; the Toeplitz padding comes on top)
+    plan_digits = {name_of(k): round(p.stats()["limb_macs"] / max(1, p.stats()["macs"]), 3)
                    for k, p in plans.items()}
     # The device is brought to its steady clock before anything is timed:
     # untimed launches of every plan in turn for --settle-ms (a cold device
@@ -237,7 +251,10 @@ def main():
     value = samples / (ms_ev * 1e-3) / 1e9
     alg_bytes = stats["in_bytes"] + stats["out_bytes"]
     achieved = alg_bytes / (ms_ev * 1e-3) / 1e9
-    mfma_tops = 2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12
+    # matrix-core rate on the useful digit products (no Toeplitz padding, no
+    # sparse top digit); the issued rate is reported beside it
+    mfma_tops = 2 * stats["limb_macs"] / (ms_ev * 1e-3) / 1e12
+    mfma_issued_tops = 2 * stats["mfma_macs"] / (ms_ev * 1e-3) / 1e12
     hbm_frac, mfma_frac = achieved / HBM_PEAK_GBS, mfma_tops / INT8_PEAK_TOPS
     traffic = read_traffic(args.config) if main_mode == "entangled" else None
 
@@ -257,6 +274,7 @@ def main():
         "alg_bytes_per_launch": alg_bytes,
         "hbm_GBps": round(achieved, 1), "hbm_frac": round(hbm_frac, 4),
         "mfma_i8_tops": round(mfma_tops, 1), "mfma_frac": round(mfma_frac, 4),
+        "mfma_i8_tops_issued": round(mfma_issued_tops, 1),
     })
     M0 = groups[0].M
     line = {
@@ -297,10 +315,12 @@ def main():
             "checksum_same_overhead_pct_vs_plain_same": pct("checksum_same", "plain_same"),
             "checksum_overhead_pct_vs_plain": pct("checksum", "plain"),
             "checksum_overhead_pct_vs_plain_same": pct("checksum", "plain_same"),
-            "mfma_macs_per_useful_mac": plan_digits,
+            "digit_pairs_per_mac": plan_digits,
         }
     if args.config == "batched" and not args.only:
         line["roofline"]["hbm_ceiling"] = hbm_ceiling(torch, ne, stream, stats, args, achieved)
+    if roof["bound"] == "mfma" and not args.only:
+        line["roofline"]["mfma_ceiling"] = mfma_ceiling(torch, ne, stream, mfma_tops)
 
     if not args.no_cpu and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(groups, np)
@@ -340,6 +360,34 @@ def hbm_ceiling(torch, ne, stream, stats, args, achieved):
     return {"kernel": "k_widen (ne_stream_widen)", "bytes_per_launch": 12 * n,
             "ms": round(ms, 4), "GBps": round(gbps, 1), "frac_of_peak": round(gbps / HBM_PEAK_GBS, 4),
             "conv_frac_of_ceiling": round(achieved / gbps, 4)}
+
+
+def mfma_ceiling(torch, ne, stream, achieved_tops):
+    """The measured i8 matrix-core rate: ne_mfma_i8_peak, 8 workgroups of 4
+    waves per compute unit issuing independent v_mfma_i32_16x16x64_i8, with
+    fixed operands and with pseudo-random operands that change every product
+    (as data digit planes do), each timed with HIP events (median of 3
+    launches after one warm-up)."""
+    blocks, iters = 256 * 8, 4096
+    sink = torch.empty(4 * blocks, dtype=torch.int32, device="cuda:0")
+    out = {"kernel": "k_mfma_i8_peak (ne_mfma_i8_peak)"}
+    for key, varied in (("fixed_operands", False), ("random_operands", True)):
+        times = []
+        with torch.cuda.stream(stream):
+            ops = ne.mfma_i8_peak(sink, blocks, iters, varied, stream=stream)
+            for _ in range(3):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ne.mfma_i8_peak(sink, blocks, iters, varied, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+        tops = ops / (sorted(times)[1] * 1e-3) / 1e12
+        out[key] = {"TOPs": round(tops, 1), "frac_of_peak": round(tops / INT8_PEAK_TOPS, 4)}
+    out["kernel_frac_of_random_operand_rate"] = round(
+        achieved_tops / out["random_operands"]["TOPs"], 4)
+    return out
 
 
 def serving_summary(args, wl):

@@ -244,6 +244,23 @@ ne_status ne_checksum_recover(int32_t M, int64_t n_out, const int64_t *const *d,
  */
 ne_status ne_stream_widen(const int32_t *in, int64_t n, int64_t *out, ne_stream stream);
 
+/*
+ * i8 matrix-core rate reference, none of the method's arithmetic: `blocks`
+ * workgroups of 4 waves each issue iters x 8 independent
+ * v_mfma_i32_16x16x64_i8 on register operands, the instruction the fused
+ * convolution and matrix product run. varied = 0: every product takes the
+ * same operands; varied = 1: every product another pair of pseudo-random
+ * operands (iters a multiple of 8), as products of data digit planes do --
+ * the matrix cores' sustained rate depends on how much their operands
+ * change. sink: device memory of 4 * blocks int32 (one folded word per
+ * wave, so no product is dropped); ops (host, may be NULL): the integer
+ * operations launched, 2 x 16 x 16 x 64 per instruction.
+ * Errors: NE_EINVAL (blocks < 1, iters < 1 or not a multiple of 8 when
+ * varied, NULL sink), NE_EHIP.
+ */
+ne_status ne_mfma_i8_peak(int32_t blocks, int64_t iters, int32_t varied, int32_t *sink,
+                          double *ops, ne_stream stream);
+
 /* ------------------------------------------------------------------------
  * The same per-step method in 32-bit entangled words, the paper's practical
  * instantiation (Sec. III-B; Table I's w = 32 column; l = 11, k = 10 for
@@ -553,6 +570,9 @@ typedef struct ne_plan_stats {
     int64_t macs;         /* useful multiply-adds of one run (conv and inner) */
     int64_t mfma_macs;    /* i8 multiply-adds issued on the matrix cores */
     int64_t lds_bytes;    /* largest dynamic LDS of a launch */
+    int64_t limb_macs;    /* useful convolution multiply-adds x the digit pairs each
+                             takes on the matrix cores (mfma_macs without the
+                             Toeplitz padding and the data-dependent sparse digit) */
 } ne_plan_stats;
 
 typedef struct ne_plan ne_plan;

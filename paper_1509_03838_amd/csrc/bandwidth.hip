@@ -1,7 +1,7 @@
-// The memory-bandwidth reference of the fused kernels (ne_stream_widen): a
-// copy with their read:write mix and access widths and none of the method's
-// arithmetic, so that its rate is the practical HBM ceiling a fused
-// convolution can be held to.
+// Measured ceilings of the fused kernels: the memory-bandwidth reference
+// (ne_stream_widen), a copy with their read:write mix and access widths and
+// none of the method's arithmetic, and the i8 matrix-core rate
+// (ne_mfma_i8_peak), back-to-back products with nothing else to wait for.
 #include "ne_internal.h"
 
 namespace {
@@ -11,6 +11,7 @@ constexpr int kWidenTile = 4 * kWidenBlock;  // elements per block step: 4 KiB i
 constexpr int kWidenTiles = 2;               // steps per block (their loads issued together)
 
 typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 typedef long v2l __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const v2i gcv2i_t;
 typedef __attribute__((address_space(1))) v2l gv2l_t;
@@ -47,7 +48,77 @@ __global__ __launch_bounds__(kWidenBlock) void k_widen(const int32_t *__restrict
         out[i] = in[i];
 }
 
+// Every wave issues `iters` rounds of kChains independent
+// v_mfma_i32_16x16x64_i8 on register operands; the accumulators are folded
+// into one word per wave at the end, so no product can be dropped. With
+// `varied` false the operands stay the same for every product; with it true
+// each product of a round takes another of kChains A and 2 B operands filled
+// with pseudo-random bytes (a different pair every product, as digit planes
+// of data are), which is what the matrix cores' power draw, and so their
+// sustained rate, depends on.
+constexpr int kChains = 8;
+__device__ __forceinline__ int hash_word(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return (int)x;
+}
+__global__ __launch_bounds__(256) void k_mfma_i8_peak(int64_t iters, int32_t varied,
+                                                      int32_t *__restrict__ sink)
+{
+    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+    v4i a[kChains], b[2];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            a[c][e] = varied ? hash_word(gid * 64u + c * 4u + e) : (int)(gid + c * 0x01010101u + e);
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            b[c][e] = varied ? hash_word(gid * 64u + 40u + c * 4u + e) : (int)(gid * 7u + 5u + e);
+    v4i acc[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc[c] = v4i{c, 0, 0, 0};
+    if (varied) {
+        // rounds in sets of 8 (iters is a multiple of 8): round r pairs chain c
+        // with A operand (c + r) mod 8, so consecutive products differ
+        for (int64_t i = 0; i < iters; i += 8) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int c = 0; c < kChains; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(c + r) & 7], b[(c + r) & 1],
+                                                                  acc[c], 0, 0, 0);
+        }
+    } else {
+        for (int64_t i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int c = 0; c < kChains; ++c)
+                acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[0], b[0], acc[c], 0, 0, 0);
+        }
+    }
+    int32_t t = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) t += acc[c].x + acc[c].y + acc[c].z + acc[c].w;
+    sink[blockIdx.x * 4 + (threadIdx.x >> 6)] = t;
+}
+
 }  // namespace
+
+extern "C" ne_status ne_mfma_i8_peak(int32_t blocks, int64_t iters, int32_t varied, int32_t *sink,
+                                     double *ops, ne_stream stream)
+{
+    if (blocks < 1 || iters < 1 || !sink || (varied && iters % 8)) return NE_EINVAL;
+    if (ops) *ops = 2.0 * 16 * 16 * 64 * (double)kChains * (double)iters * 4.0 * blocks;
+    hipLaunchKernelGGL(k_mfma_i8_peak, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       iters, varied, sink);
+    return ne::launch_status();
+}
 
 extern "C" ne_status ne_stream_widen(const int32_t *in, int64_t n, int64_t *out,
                                      ne_stream stream)

@@ -589,12 +589,18 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
             constexpr int SL = FS + LB - 1;
             constexpr int S = FS ? 2 * SL : ((LA + LB - 1) < 8 ? (LA + LB - 1) : 8);
             v4i acc[S];
-            int o = aoff;
+            // Byte offset of this lane's A row in the slot's digit planes:
+            // ring offsets here are multiples of 16, where plane_off(o) is
+            // o * LAP, so the offset advances by 64 LAP a chunk and wraps
+            // by one unsigned min (offset - ring LAP wraps above the offset
+            // exactly when the offset is below ring LAP).
+            uint32_t ob = (uint32_t)aoff * lap<LA>();
+            const uint32_t ringb = (uint32_t)ring * lap<LA>();
             using TW = TapWords<TC>;
             auto load = [&](int c, TW(&bf)[LBM], v4i(&af)[LA]) {
-                const unsigned char *pa = pbase + plane_off(o, lap<LA>());
-                o += 64;
-                o = o >= ring ? o - ring : o;
+                const unsigned char *pa = pbase + ob;
+                ob += 64 * lap<LA>();
+                ob = min(ob, ob - ringb);
 #pragma unroll
                 for (int b = 0; b < LBM; ++b) tap_load(b, c, bf[b]);
 #pragma unroll
@@ -678,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
                 auto top = [&](int c) {
                     int ot = aoff + 64 * c;
                     ot = ot >= ring ? ot - ring : ot;
-                    const unsigned char *pa = pbase + plane_off(ot, lap<LA>());
+                    const unsigned char *pa = pbase + (uint32_t)ot * lap<LA>();
                     TapWords<TC> tw;
                     tap_load(LB - 1, c, tw);
                     const v4i bt = tap_frag(tw);

@@ -326,6 +326,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // data-dependent part is not counted)
             st.mfma_macs += slots_run * nstrips * g_conv_steps * (int64_t)kConvTile * 64 * G.nch *
                             la * (lb - dc.sparse);
+            st.limb_macs += slots_run * (u.op == NE_OP_CIRC ? n_out : u.n) * u.n_operand * la *
+                            (lb - dc.sparse);
         } else {
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = g_stream_steps;

@@ -32,7 +32,8 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_chain_check", "ne_chain_workspace_size", "ne_chain_apply", "ne_gemm",
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
-           "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc", "ne_stream_widen")
+           "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc", "ne_stream_widen",
+           "ne_mfma_i8_peak")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3, "checksum_same": 4}
@@ -64,7 +65,7 @@ class TuningC(ctypes.Structure):
 class StatsC(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("groups", "items", "launches", "in_bytes",
                                                "out_bytes", "out_samples", "macs", "mfma_macs",
-                                               "lds_bytes")]
+                                               "lds_bytes", "limb_macs")]
 
 
 class NeError(RuntimeError):
@@ -119,6 +120,7 @@ def load() -> ctypes.CDLL:
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
         "ne_stream_widen": (_i32, [_P, _i64, _P, _P]),
+        "ne_mfma_i8_peak": (_i32, [_i32, _i64, _i32, _P, ctypes.POINTER(ctypes.c_double), _P]),
         "ne_chain_apply_noalloc": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P,
                                           _i64, _u32, _P]),
         "ne_gemm": (_i32, [_i32, _i32, _i64, _i64, _i64, _P, _P, _P, _i32, _i32, _P,
@@ -668,6 +670,21 @@ def stream_widen(src, dst, stream=None):
     n = src.numel()
     _lengths("dst", [dst], n, exact=False)
     _check("ne_stream_widen", load().ne_stream_widen(_ptr(src), n, _ptr(dst), _stream(stream)))
+
+
+def mfma_i8_peak(sink, blocks: int, iters: int, varied: bool = False, stream=None) -> float:
+    """Launches the i8 matrix-core rate reference (blocks x 4 waves, iters x 8
+    independent products each; varied: pseudo-random operands changing every
+    product) on `stream`; returns the integer operations launched. sink: an
+    int32 device tensor of at least 4 * blocks values."""
+    import torch
+    _dtype([sink], torch.int32, "sink")
+    _on_device("sink", [sink])
+    _lengths("sink", [sink], 4 * blocks, exact=False)
+    ops = ctypes.c_double()
+    _check("ne_mfma_i8_peak", load().ne_mfma_i8_peak(blocks, iters, int(bool(varied)), _ptr(sink),
+                                                     ctypes.byref(ops), _stream(stream)))
+    return ops.value
 
 
 def gemm_workspace_size(mode: str, M: int, N: int, P: int, Q: int, in_bits: int) -> int:

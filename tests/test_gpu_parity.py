@@ -351,3 +351,18 @@ def test_stream_widen_copies_exactly(n):
     got = dst.cpu().numpy()
     assert np.array_equal(got[:n], src.cpu().numpy().astype(np.int64))
     assert (got[n:] == POISON).all()
+
+
+def test_mfma_i8_peak_runs_and_reports_its_work():
+    """The matrix-core rate reference launches and reports 2 x 16 x 16 x 64 x
+    8 operations per wave and iteration; every wave writes its folded word."""
+    blocks, iters = 16, 8
+    for varied in (False, True):
+        sink = torch.full((4 * blocks + 4,), -7, dtype=torch.int32, device=DEV)
+        ops = ne.mfma_i8_peak(sink, blocks, iters, varied)
+        torch.cuda.synchronize()
+        assert ops == 2 * 16 * 16 * 64 * 8 * iters * 4 * blocks
+        s = sink.cpu().numpy()
+        assert (s[4 * blocks:] == -7).all()
+    with pytest.raises(ne.NeError):
+        ne.mfma_i8_peak(sink, blocks, 12, True)  # varied rounds come in sets of 8
