@@ -68,6 +68,8 @@ typedef int32_t ne_status;
 #define NE_ENOMEM (-6)    /* device allocation failed (plan creation only) */
 #define NE_ESCRATCH (-7)  /* needs more than the library's fixed scratch buffer
                              (ne_chain_apply_noalloc) */
+#define NE_ELATE (-8)     /* more than one stream missed the deadline
+                             (ne_wait_streams) */
 
 /* The LSB operations of eq. (2) that the library runs. */
 typedef enum ne_op {
@@ -260,6 +262,39 @@ ne_status ne_stream_widen(const int32_t *in, int64_t n, int64_t *out, ne_stream 
  */
 ne_status ne_mfma_i8_peak(int32_t blocks, int64_t iters, int32_t varied, int32_t *sink,
                           double *ops, ne_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Fail-stop identification by deadline (Sec. I: a failed core is
+ * unresponsive or late; Sec. III-B: recovery from the M-1 streams other than
+ * the unavailable one). Each entangled stream's operation runs as its own
+ * task -- ne_lsb_apply with only that stream's mask bit, on its own HIP
+ * stream -- followed by a completion event the caller records there.
+ *
+ * ne_wait_streams: waits on the host (polling, no device work) until every
+ * one of the M events has completed or deadline_us microseconds have passed
+ * since the call. events: host array of M hipEvent_t (as void*); a NULL
+ * entry is a stream that was never launched and counts as late. *lost
+ * receives the index of the one stream that had not completed by the
+ * deadline, or -1 if all did; the late stream's work is neither awaited nor
+ * cancelled, and recovery (ne_extract_recover with r = *lost) must not read
+ * its output. The caller orders the recovery after the other M-1 events.
+ * The tasks are independent failure domains only on independent hardware
+ * queues: HIP streams beyond the process's hardware queues
+ * (GPU_MAX_HW_QUEUES, 4 by default) share one, and a slow task then delays
+ * its queue-mates too.
+ * Errors: NE_EINVAL (M outside [1, NE_MAX_M], NULL arguments, negative
+ * deadline), NE_ELATE (two or more streams late: more failures than one
+ * redundant stream covers; *lost = -1), NE_EHIP (an event query failed).
+ *
+ * ne_stream_delay: enqueues a wait of `microseconds` (at most
+ * NE_MAX_DELAY_US) on `stream` -- one lane spinning on the device's
+ * real-time counter -- so that work enqueued behind it completes that much
+ * later: a slow core, for tests and demonstrations. Errors: NE_EINVAL
+ * (negative or above the limit), NE_EHIP.
+ */
+#define NE_MAX_DELAY_US 1000000
+ne_status ne_wait_streams(int32_t M, void *const *events, int64_t deadline_us, int32_t *lost);
+ne_status ne_stream_delay(int64_t microseconds, ne_stream stream);
 
 /* ------------------------------------------------------------------------
  * The same per-step method in 32-bit entangled words, the paper's practical

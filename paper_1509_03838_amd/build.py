@@ -13,7 +13,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "chain.hip", "fused.hip", "plan.hip",
-           "gemm.hip", "word32.hip", "bandwidth.hip"]
+           "gemm.hip", "word32.hip", "bandwidth.hip",
+           "failstop.hip"]
 
 # fused_conv.hip is compiled once per (kernel class, slot count), and
 # fused_stream.hip once per kernel class: entangled

@@ -128,6 +128,7 @@ const char *ne_strerror(ne_status s)
     case NE_EHIP: return "HIP runtime error";
     case NE_ENOMEM: return "device allocation failed";
     case NE_ESCRATCH: return "needs more than the library's fixed scratch buffer";
+    case NE_ELATE: return "more than one stream missed the deadline";
     default: return "unknown status";
     }
 }

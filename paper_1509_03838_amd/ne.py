@@ -33,7 +33,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_gemm_workspace_size", "ne_entangle32", "ne_entangle_operand32", "ne_lsb_apply32",
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
            "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc", "ne_stream_widen",
-           "ne_mfma_i8_peak")
+           "ne_mfma_i8_peak", "ne_wait_streams", "ne_stream_delay")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3, "checksum_same": 4}
@@ -120,6 +120,8 @@ def load() -> ctypes.CDLL:
         "ne_chain_apply": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P, _i64, _u32,
                                   _P, ctypes.c_size_t, _P]),
         "ne_stream_widen": (_i32, [_P, _i64, _P, _P]),
+        "ne_wait_streams": (_i32, [_i32, _P, _i64, ctypes.POINTER(_i32)]),
+        "ne_stream_delay": (_i32, [_i64, _P]),
         "ne_mfma_i8_peak": (_i32, [_i32, _i64, _i32, _P, ctypes.POINTER(ctypes.c_double), _P]),
         "ne_chain_apply_noalloc": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _P,
                                           _i64, _u32, _P]),
@@ -658,6 +660,24 @@ def chain_apply_noalloc(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence,
            load().ne_chain_apply_noalloc(M, n_in, _ptr_array(eps), _chain_c(ops), len(ops),
                                          _ptr_array(delta), n, mask & 0xFFFFFFFF,
                                          _stream(stream)))
+
+
+def wait_streams(events: Sequence, deadline_us: int) -> int:
+    """Fail-stop identification by deadline: waits until every stream's
+    completion event (torch.cuda.Event, or None for a stream never launched)
+    has completed or deadline_us has passed; returns the index of the one
+    late stream, or -1. Raises NeError (status -8) if two or more are late."""
+    arr = (ctypes.c_void_p * max(1, len(events)))(
+        *[None if e is None else e.cuda_event for e in events])
+    lost = _i32()
+    _check("ne_wait_streams", load().ne_wait_streams(len(events), arr, int(deadline_us),
+                                                     ctypes.byref(lost)))
+    return lost.value
+
+
+def stream_delay(microseconds: int, stream=None):
+    """Enqueues a bounded wait (a slow core) on `stream`."""
+    _check("ne_stream_delay", load().ne_stream_delay(int(microseconds), _stream(stream)))
 
 
 def stream_widen(src, dst, stream=None):

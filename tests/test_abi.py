@@ -498,3 +498,22 @@ def test_stream_widen_argument_checks(lib):
     assert lib.ne_stream_widen(FAKE + 4, 16, FAKE + 4096, None) == -1   # misaligned input
     assert lib.ne_stream_widen(FAKE, 16, FAKE + 8, None) == -1          # misaligned output
     assert lib.ne_stream_widen(FAKE, 16, FAKE + 32, None) == -1         # overlapping
+
+
+def test_wait_streams_and_delay_argument_checks(lib):
+    """Refused before any device or event access."""
+    import ctypes
+    lost = ctypes.c_int32(7)
+    ev = (ctypes.c_void_p * 3)(None, None, None)
+    assert lib.ne_wait_streams(0, ev, 10, ctypes.byref(lost)) == -1
+    assert lib.ne_wait_streams(3, None, 10, ctypes.byref(lost)) == -1
+    assert lib.ne_wait_streams(3, ev, -1, ctypes.byref(lost)) == -1
+    assert lib.ne_wait_streams(3, ev, 10, None) == -1
+    # no stream launched at all: every one is late
+    assert lib.ne_wait_streams(3, ev, 0, ctypes.byref(lost)) == -8 and lost.value == -1
+    one = (ctypes.c_void_p * 1)(None)
+    assert lib.ne_wait_streams(1, one, 0, ctypes.byref(lost)) == 0 and lost.value == 0
+    assert lib.ne_stream_delay(-1, None) == -1
+    assert lib.ne_stream_delay(1_000_001, None) == -1
+    assert lib.ne_stream_delay(0, None) == 0      # nothing enqueued
+    assert b"deadline" in lib.ne_strerror(-8)
