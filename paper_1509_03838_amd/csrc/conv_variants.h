@@ -191,4 +191,21 @@ constexpr bool digits_needed(int kclass, int slots, int la, int lb, int max_bits
     return false;
 }
 
+// Whether some matrix-product group of this kernel class and slot count,
+// with values of 1..max_bits bits, takes split words of la / 2 digits per
+// field and lb digits for the kernel matrix (entangled and plain-same).
+constexpr bool gemm_split_needed(int kclass, int slots, int la, int lb, int max_bits)
+{
+    for (int mode = 0; mode < 3; ++mode) {
+        if (conv_class_of_mode(mode) != kclass || mode == 1) continue;
+        const int M = slots;
+        if (M < (mode == 0 ? 3 : 1) || M > 8) continue;
+        for (int b = 1; b <= max_bits; ++b) {
+            const DigitCounts d = conv_digits(mode, M, b, 64, true);
+            if (d.split && d.la == la && d.lb == lb) return true;
+        }
+    }
+    return false;
+}
+
 }  // namespace ne

@@ -56,10 +56,12 @@ inline size_t gemm_split_bytes(int slots, int la, int lb, int64_t N, int64_t P, 
 using GemmLaunch = hipError_t (*)(const GemmArgs &a, hipStream_t s);
 using GemmSplitLaunch = hipError_t (*)(const GemmArgs &a, const GemmSplit &w, hipStream_t s);
 struct GemmKernel {
-    GemmLaunch fused;       // one pass, digits staged in LDS
-    GemmSplitLaunch split;  // two phases through workspace
+    GemmLaunch fused;              // one pass, digits staged in LDS
+    GemmSplitLaunch split;         // two phases through workspace
+    GemmSplitLaunch split_fields;  // two phases, words split into two fields of LA / 2 digits
 };
-// The variant for (kernel class, slots, LA, LB), or null if none is built.
+// The variant for (kernel class, slots, LA, LB), or null if none is built
+// (a variant may hold only the split-word phase 1).
 const GemmKernel *gemm_kernel(int kclass, int slots, int la, int lb);
 
 }  // namespace ne

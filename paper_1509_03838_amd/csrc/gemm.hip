@@ -62,12 +62,17 @@ __host__ __device__ constexpr size_t digits_lds(int la, int lb)
     return (size_t)2 * (la + lb) * kDigitPlane;
 }
 
-template <int LA, int LB>
+// FS > 0: the data planes hold split words (FS digits of the low field, then
+// FS of the high field, weights 256^a and 2^l 256^a): every pair accumulates
+// into its field's weight and y = lo-sum + 2^l hi-sum.
+template <int LA, int LB, int FS = 0>
 __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, const DigitJob job,
-                                                            int64_t N, int64_t Q)
+                                                            int64_t N, int64_t Q, int l)
 {
     static_assert(kGemmSplitRows == 64 && kGemmSplitCols == 64, "block tile");
-    constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+    static_assert(FS == 0 || 2 * FS == LA, "split words");
+    constexpr int SL = FS + LB - 1;
+    constexpr int S = FS ? 2 * SL : ((LA + LB - 1) < 8 ? (LA + LB - 1) : 8);
     constexpr int NP = LA + LB;  // staged planes per chunk: A digits, then B digits
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -136,9 +141,11 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
                 for (int b = 0; b < LB; ++b)
 #pragma unroll
                     for (int a = 0; a < LA; ++a)
-                        if (a + b < 8)
-                            acc[rt][ct][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                                af[rt][a], bf[ct][b], acc[rt][ct][a + b], 0, 0, 0);
+                        if (fk::pair_runs<FS>(a, b))
+                            acc[rt][ct][fk::acc_of<FS, LB>(a) + b] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                                    af[rt][a], bf[ct][b], acc[rt][ct][fk::acc_of<FS, LB>(a) + b],
+                                    0, 0, 0);
         // the other buffer was last read in the previous chunk, before the
         // barrier that ended it
         if (more) stage(nxt);
@@ -153,22 +160,36 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = R0 + wr + 16 * rt + 4 * fh + v;
-                uint64_t y = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
+                uint64_t y;
+                if constexpr (FS > 0) {
+                    uint64_t ylo = (uint64_t)(int64_t)acc[rt][ct][SL - 1][v];
+                    uint64_t yhi = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
 #pragma unroll
-                for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
+                    for (int s = SL - 2; s >= 0; --s) {
+                        ylo = (ylo << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
+                        yhi = (yhi << 8) + (uint64_t)(int64_t)acc[rt][ct][SL + s][v];
+                    }
+                    y = ylo + (yhi << l);
+                } else {
+                    y = (uint64_t)(int64_t)acc[rt][ct][S - 1][v];
+#pragma unroll
+                    for (int s = S - 2; s >= 0; --s)
+                        y = (y << 8) + (uint64_t)(int64_t)acc[rt][ct][s][v];
+                }
                 if (row < N && col < Q) store_nt(d + row * Q + col, (int64_t)y);
             }
         }
 }
 
 using DigitLaunch = void (*)(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N,
-                             int64_t Q, hipStream_t s);
+                             int64_t Q, int l, hipStream_t s);
 
-template <int LA, int LB>
-void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q,
+template <int LA, int LB, int FS = 0>
+void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q, int l,
                    hipStream_t s)
 {
-    void (*k)(const GemmSplit, const DigitJob, int64_t, int64_t) = &k_gemm_digits<LA, LB>;
+    void (*k)(const GemmSplit, const DigitJob, int64_t, int64_t, int) =
+        &k_gemm_digits<LA, LB, FS>;
     constexpr size_t lds = digits_lds(LA, LB);
     if (lds > 64 * 1024) {
         // raised once per variant; should it fail, the launch below fails
@@ -179,7 +200,7 @@ void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t 
     }
     const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows),
                     (unsigned)nslots);
-    hipLaunchKernelGGL(k, grid, dim3(fk::kBlock), lds, s, w, job, N, Q);
+    hipLaunchKernelGGL(k, grid, dim3(fk::kBlock), lds, s, w, job, N, Q, l);
 }
 
 #define NE_DIGITS_ROW(LA) {&launch_digits<LA, 1>, &launch_digits<LA, 2>, &launch_digits<LA, 3>}
@@ -187,6 +208,12 @@ const DigitLaunch kDigits[kLimbsA][3] = {NE_DIGITS_ROW(1), NE_DIGITS_ROW(2), NE_
                                          NE_DIGITS_ROW(4), NE_DIGITS_ROW(5), NE_DIGITS_ROW(6),
                                          NE_DIGITS_ROW(7), NE_DIGITS_ROW(8)};
 #undef NE_DIGITS_ROW
+// split words: FS = 1..4 digits per field (LA = 2 FS)
+#define NE_SPLIT_ROW(FS) \
+    {&launch_digits<2 * FS, 1, FS>, &launch_digits<2 * FS, 2, FS>, &launch_digits<2 * FS, 3, FS>}
+const DigitLaunch kDigitsSplit[4][3] = {NE_SPLIT_ROW(1), NE_SPLIT_ROW(2), NE_SPLIT_ROW(3),
+                                        NE_SPLIT_ROW(4)};
+#undef NE_SPLIT_ROW
 
 }  // namespace
 }  // namespace ne
@@ -196,8 +223,10 @@ using namespace ne;
 namespace {
 
 // Argument checks and digit counts shared by the size query and the call.
+// dc: digits of the one-launch form; ds: of the two-phase form, which
+// splits words into two fields where that takes fewer planes.
 ne_status gemm_shape(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q, int32_t in_bits,
-                     DigitCounts *dc)
+                     DigitCounts *dc, DigitCounts *ds)
 {
     if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
     const int minM = mode == kEntangled ? 3 : (mode == kChecksum ? 2 : 1);
@@ -207,6 +236,7 @@ ne_status gemm_shape(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q, i
     if (N > (int64_t)kGemmTile * 65535 || Q > ((int64_t)1 << 26) || P > ((int64_t)1 << 24))
         return NE_EUNSUP;
     *dc = conv_digits(mode, M, in_bits);
+    *ds = mode == kEntangled || mode == kPlainSame ? conv_digits(mode, M, in_bits, 64, true) : *dc;
     return NE_OK;
 }
 
@@ -216,11 +246,11 @@ extern "C" ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, 
                                             int64_t Q, int32_t in_bits, size_t *bytes)
 {
     if (!bytes) return NE_EINVAL;
-    DigitCounts dc{};
-    const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc);
+    DigitCounts dc{}, ds{};
+    const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc, &ds);
     if (st != NE_OK) return st;
     const int nslots = mode == kChecksum ? M + 1 : M;
-    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q,
+    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, ds.la, ds.lb, N, P, Q,
                                                        mode == kChecksum);
     return NE_OK;
 }
@@ -230,8 +260,8 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
                              int32_t lost, int32_t in_bits, void *workspace,
                              size_t workspace_bytes, uint32_t *flags, ne_stream stream)
 {
-    DigitCounts dc0{};
-    const ne_status st0 = gemm_shape(mode, M, N, P, Q, in_bits, &dc0);
+    DigitCounts dc0{}, ds{};
+    const ne_status st0 = gemm_shape(mode, M, N, P, Q, in_bits, &dc0, &ds);
     if (st0 != NE_OK) return st0;
     if (!c || !out) return NE_EINVAL;
     if (lost < -1 || lost >= M) return NE_EFAILIDX;
@@ -255,14 +285,18 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)M : bound;
         if (chk > (((unsigned __int128)1 << 63) - 1)) return NE_ERANGE;
     }
-    const DigitCounts dc = dc0;
+    // the two-phase form runs split words where the digit rule takes them
+    const DigitCounts dc = workspace ? ds : dc0;
+    const int fs = dc.split ? dc.la / 2 : 0;
     // int32 accumulation: a digit product is at most 2^14, summed over the
-    // padded inner dimension and at most min(la, lb) pairs per weight.
+    // padded inner dimension and at most min(digits of a field, lb) pairs per weight.
     const int64_t pp = (P + kGemmK - 1) / kGemmK * kGemmK;
-    if (pp * std::min(dc.la, dc.lb) * 16384 >= ((int64_t)1 << 31)) return NE_EUNSUP;
+    if (pp * std::min(fs ? fs : dc.la, dc.lb) * 16384 >= ((int64_t)1 << 31)) return NE_EUNSUP;
     const int nslots = mode == kChecksum ? M + 1 : M;
     const GemmKernel *kern = gemm_kernel(conv_class_of_mode(mode), nslots, dc.la, dc.lb);
-    if (!kern) return NE_EUNSUP;
+    if (!kern || (fs ? !kern->split_fields : !kern->fused)) return NE_EUNSUP;
+    if (fs && (fs > 4 || dc.lb > 3)) return NE_EUNSUP;
+    if (fs) l = dc.l;  // the field boundary (plain-same groups too)
     const size_t need = gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q, mode == kChecksum);
     if (workspace && (workspace_bytes < need || (uintptr_t)workspace % 256)) return NE_EINVAL;
 
@@ -304,7 +338,7 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         w.e = (int64_t *)(w.b + gemm_round((int64_t)dc.lb * w.Qp * w.Pp, 256));
         if (w.Qp / kGemmSplitCols > 0x7fffffff || w.Np / kGemmSplitRows > 65535) return NE_EUNSUP;
         hipStream_t s = (hipStream_t)stream;
-        e = kern->split(a, w, s);
+        e = fs ? kern->split_fields(a, w, s) : kern->split(a, w, s);
         if (e != hipSuccess) return hip_fail(e);
         // every computed slot's product, one z slice each
         DigitJob job{};
@@ -316,7 +350,10 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
             job.d[nj] = t < M ? G.out[t] : w.e;
             ++nj;
         }
-        kDigits[dc.la - 1][dc.lb - 1](w, job, nj, N, Q, s);
+        if (fs)
+            kDigitsSplit[fs - 1][dc.lb - 1](w, job, nj, N, Q, l, s);
+        else
+            kDigits[dc.la - 1][dc.lb - 1](w, job, nj, N, Q, l, s);
         // recovery in place
         const int64_t n = N * Q;
         if (mode == kEntangled) {

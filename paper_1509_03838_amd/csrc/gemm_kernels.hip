@@ -51,16 +51,16 @@ __device__ __forceinline__ void load_row8(const int32_t *src, bool full, bool ve
 
 // 8 values into L digit planes: plane a receives the 8 digit bytes of
 // weight 256^a at dst + a * stride (two aligned words).
+// u[i]: the L digit bytes of value i plus 0x80 each (value + digit offset,
+// or the packed fields of a split word).
 template <int L>
-__device__ __forceinline__ void put_digits8(const int64_t (&x)[8], unsigned char *dst, size_t stride)
+__device__ __forceinline__ void put_bytes8(const uint64_t (&u)[8], unsigned char *dst, size_t stride)
 {
-    constexpr uint64_t C = digit_offset<L>();
     uint32_t lo[8], hi[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const uint64_t u = (uint64_t)x[i] + C;
-        lo[i] = (uint32_t)u;
-        hi[i] = (uint32_t)(u >> 32);
+        lo[i] = (uint32_t)u[i];
+        hi[i] = (uint32_t)(u[i] >> 32);
     }
     uint32_t w0[8], w1[8];
     transpose4(lo, w0);
@@ -76,6 +76,38 @@ __device__ __forceinline__ void put_digits8(const int64_t (&x)[8], unsigned char
         w.y = w1[a] ^ 0x80808080u;
         *reinterpret_cast<uint2 *>(dst + a * stride) = w;
     }
+}
+
+template <int L>
+__device__ __forceinline__ void put_digits8(const int64_t (&x)[8], unsigned char *dst, size_t stride)
+{
+    constexpr uint64_t C = digit_offset<L>();
+    uint64_t u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) u[i] = (uint64_t)x[i] + C;
+    put_bytes8<L>(u, dst, stride);
+}
+
+// Split words (FS digits per field): the fields of c + 2^l c' (c' = 0 for
+// raw values) without forming the word -- lo = c's low l bits sign-extended,
+// hi = c' + (c - lo) / 2^l -- cut into FS digits each (planes 0 .. FS-1 the
+// low field, FS .. 2 FS - 1 the high one).
+template <int FS>
+__device__ __forceinline__ void put_fields8(const int32_t (&cur)[8], const int32_t (&prev)[8],
+                                            bool entangled, int l, unsigned char *dst,
+                                            size_t stride)
+{
+    constexpr uint32_t CF = (uint32_t)digit_offset<FS>();
+    uint64_t u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int32_t lo = __builtin_amdgcn_sbfe(cur[i], 0, l);
+        const int32_t cp = entangled ? prev[i] : 0;
+        const int32_t hi = (int32_t)((uint32_t)cp +
+                                     (uint32_t)((int32_t)((uint32_t)cur[i] - (uint32_t)lo) >> l));
+        u[i] = pack_fields<FS>((uint32_t)lo + CF, (uint32_t)hi + CF);
+    }
+    put_bytes8<2 * FS>(u, dst, stride);
 }
 
 template <int LA, int LB, int NS, int KCLASS>
@@ -222,9 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
 // Phase 1: the digit planes of every slot's value (entangled, plain, or the
 // checksum sum) for all Np x Pp positions (zero outside the matrix); the
 // lost slot's planes are not written (never read).
-template <int LA, int NS, int KCLASS>
+template <int LA, int NS, int KCLASS, int FS = 0>
 __global__ __launch_bounds__(kBlock) void k_gemm_split_a(const GemmArgs args, GemmSplit w)
 {
+    static_assert(FS == 0 || (2 * FS == LA && KCLASS != 2), "split words");
     constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
     constexpr int M = KCLASS == 2 ? NS - 1 : NS;
     const GroupDev *G = &args.g;
@@ -250,10 +283,16 @@ __global__ __launch_bounds__(kBlock) void k_gemm_split_a(const GemmArgs args, Ge
 #pragma unroll
             for (int i = 0; i < 8; i += 2) bd.add2(cur[i], cur[i + 1]);
             if (t != skip) {
-                int64_t x[8];
+                unsigned char *dst = w.a + (size_t)t * LA * plane + row * Pp + k0;
+                if constexpr (FS > 0) {
+                    put_fields8<FS>(cur, prev, mode == kEntangled, l, dst, plane);
+                } else {
+                    int64_t x[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) x[i] = mode == kEntangled ? ent(cur[i], prev[i], l) : cur[i];
-                put_digits8<LA>(x, w.a + (size_t)t * LA * plane + row * Pp + k0, plane);
+                    for (int i = 0; i < 8; ++i)
+                        x[i] = mode == kEntangled ? ent(cur[i], prev[i], l) : cur[i];
+                    put_digits8<LA>(x, dst, plane);
+                }
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -307,10 +346,10 @@ unsigned grid_of(int64_t items)
 }
 
 // Phase 1 of the two-phase form: the digit planes of every slot and of G.
-template <int LA, int LB, int NS>
+template <int LA, int LB, int NS, int FS = 0>
 hipError_t launch_split(const GemmArgs &a, const GemmSplit &w, hipStream_t s)
 {
-    hipLaunchKernelGGL((fk::k_gemm_split_a<LA, NS, NE_KCLASS>), dim3(grid_of(w.Np * (w.Pp / 8))),
+    hipLaunchKernelGGL((fk::k_gemm_split_a<LA, NS, NE_KCLASS, FS>), dim3(grid_of(w.Np * (w.Pp / 8))),
                        dim3(fk::kBlock), 0, s, a, w);
     hipLaunchKernelGGL((fk::k_gemm_split_b<LB>), dim3(grid_of(w.Qp * (w.Pp / 8))), dim3(fk::kBlock),
                        0, s, a, w);
@@ -336,11 +375,15 @@ hipError_t launch_one(const GemmArgs &a, hipStream_t s)
 template <int LA, int LB, int NS>
 constexpr GemmKernel launcher()
 {
-    if constexpr (digits_needed(NE_KCLASS, NS, LA, LB, kGemmMaxBits) &&
-                  gemm_lds(NS, LA, LB) <= 160 * 1024)
-        return GemmKernel{&launch_one<LA, LB, NS>, &launch_split<LA, LB, NS>};
+    constexpr bool conv = digits_needed(NE_KCLASS, NS, LA, LB, kGemmMaxBits) &&
+                          gemm_lds(NS, LA, LB) <= 160 * 1024;
+    constexpr bool split = LA % 2 == 0 && gemm_split_needed(NE_KCLASS, NS, LA, LB, kGemmMaxBits);
+    GemmSplitLaunch sf = nullptr;
+    if constexpr (split) sf = &launch_split<LA, LB, NS, LA / 2>;
+    if constexpr (conv)
+        return GemmKernel{&launch_one<LA, LB, NS>, &launch_split<LA, LB, NS>, sf};
     else
-        return GemmKernel{nullptr, nullptr};
+        return GemmKernel{nullptr, nullptr, sf};
 }
 
 template <int NS>
@@ -376,7 +419,7 @@ const GemmKernel *pick(int la, int lb)
 {
     static constexpr Row<NS> r = row<NS>();
     const GemmKernel *k = &r.f[la - 1][lb - 1];
-    return k->fused ? k : nullptr;
+    return (k->fused || k->split_fields) ? k : nullptr;
 }
 
 }  // namespace
