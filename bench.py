@@ -634,7 +634,8 @@ def chain_line(args, wl):
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": "series: 3 streams x 2^22 int32 samples in [-2^9,2^9), add -> "
                                "scale -> conv (64 taps) -> perm -> add, operands in the same range; "
-                               "entangle once, extract once; per-step kernels",
+                               "entangle once, extract once; element-wise runs fused into "
+                               "segment passes",
                    "w": 64, "l": l, "worst_case_bound": bound},
         "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,

@@ -1,10 +1,13 @@
 // Series of LSB operations on entangled streams (ne_chain_*): the shape and
 // range bookkeeping of the series (host) and its execution as one launch
-// per operation over ping-pong buffers in the caller's workspace (or, for
+// per stage over ping-pong buffers in the caller's workspace (or, for
 // ne_chain_apply_noalloc, in a fixed device buffer of the library's own).
-// The operations are the per-step kernels of ne_lsb_apply.
+// A stage is one operation on the per-step kernels of ne_lsb_apply, or a
+// run of element-wise operations (led, optionally, by a permutation) fused
+// into one pass over the entangled words.
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "ne_internal.h"
 
@@ -164,6 +167,76 @@ unsigned char *scratch_address(ne_status *st)
     return addr[dev];
 }
 
+// ------------------------------------------------ fused element-wise runs
+
+// A run of consecutive element-wise operations of a series (scale, add, sub,
+// mul), optionally led by a permutation, applied in one pass over the
+// entangled words: out[i] = op_k( ... op_1(in[p[i]] or in[i]) ...).
+constexpr int kMaxSegmentOps = 8;
+struct SegmentOp {
+    int32_t op;
+    int32_t pad_;
+    const void *g;  // NE_OP_ADD / NE_OP_SUB: words of the stream width; NE_OP_MUL: int32
+    int64_t s;      // NE_OP_SCALE
+};
+struct Segment {
+    int32_t nops;
+    int32_t perm;          // 1: gather at p[i] first
+    const int32_t *p;
+    SegmentOp ops[kMaxSegmentOps];
+};
+
+inline bool elementwise(int32_t op)
+{
+    return op == NE_OP_SCALE || op == NE_OP_ADD || op == NE_OP_SUB || op == NE_OP_MUL;
+}
+
+// blockIdx.y picks the stream; W is the word (int64_t or int32_t), arithmetic
+// wraps modulo 2^(8 sizeof W). A permutation index outside [0, n) reads
+// nothing (the word is 0) and raises NE_FLAG_PERM_INDEX.
+template <typename W, typename In, typename Out>
+__global__ __launch_bounds__(256) void k_segment(In x, Out y, int64_t n, Segment seg,
+                                                 uint32_t *err)
+{
+    using U = typename std::make_unsigned<W>::type;
+    const W *xs = x.p[blockIdx.y];
+    W *ys = y.p[blockIdx.y];
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        U v;
+        if (seg.perm) {
+            const int64_t src = seg.p[i];
+            const bool ok = src >= 0 && src < n;
+            bad |= !ok;
+            v = ok ? (U)xs[src] : (U)0;
+        } else {
+            v = (U)xs[i];
+        }
+        for (int k = 0; k < seg.nops; ++k) {
+            const SegmentOp &o = seg.ops[k];
+            switch (o.op) {
+            case NE_OP_SCALE: v = v * (U)o.s; break;
+            case NE_OP_ADD: v = v + (U)((const W *)o.g)[i]; break;
+            case NE_OP_SUB: v = v - (U)((const W *)o.g)[i]; break;
+            default: v = v * (U)(W)((const int32_t *)o.g)[i]; break;  // NE_OP_MUL
+            }
+        }
+        ys[i] = (W)v;
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
+template <typename W, typename In, typename Out>
+void launch_segment(int count, int64_t n, const In &x, const Out &y, const Segment &seg,
+                    hipStream_t s)
+{
+    int64_t g = (n + 255) / 256;
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    hipLaunchKernelGGL((k_segment<W, In, Out>), dim3((unsigned)g, count), dim3(256), 0, s, x, y, n,
+                       seg, device_flag_word());
+}
+
 // Word-width traits of the series' execution: the stream tables and the
 // launch of one operation.
 struct Words64 {
@@ -201,6 +274,12 @@ struct Words64 {
         }
         return launch_status();
     }
+    static ne_status segment(const Segment &seg, int count, int64_t n, const In &cur,
+                             const Out &dst, hipStream_t s)
+    {
+        launch_segment<W>(count, n, cur, dst, seg, s);
+        return launch_status();
+    }
 };
 
 struct Words32 {
@@ -212,6 +291,12 @@ struct Words32 {
     {
         launch_op32(o.op, count, n, cur, (const int32_t *)o.operand, o.n_operand, o.scalar, dst,
                     m, s);
+        return launch_status();
+    }
+    static ne_status segment(const Segment &seg, int count, int64_t n, const In &cur,
+                             const Out &dst, hipStream_t s)
+    {
+        launch_segment<W>(count, n, cur, dst, seg, s);
         return launch_status();
     }
 };
@@ -264,22 +349,45 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
     hipStream_t s = (hipStream_t)stream;
     unsigned char *ws = (unsigned char *)workspace;
     int64_t n = n_in;
-    for (int32_t i = 0; i < n_ops; ++i) {
+    // Stages: a run of element-wise operations (led, optionally, by a
+    // permutation) is one pass; every other operation is a pass of its own.
+    // Stage k writes workspace buffer (k & 1), the last one delta.
+    int stage = 0;
+    for (int32_t i = 0; i < n_ops;) {
         const ne_chain_op &o = ops[i];
-        const int64_t m = stage_out(o, n);
+        int32_t j = i + 1;  // the stage is ops [i, j)
+        if (o.op == NE_OP_PERM || elementwise(o.op))
+            while (j < n_ops && j - i < kMaxSegmentOps && elementwise(ops[j].op)) ++j;
+        int64_t m = n;
+        for (int32_t k = i; k < j; ++k) m = stage_out(ops[k], m);
         typename T::Out dst{};
-        if (i + 1 == n_ops) {
+        if (j == n_ops) {
             dst = fin;
         } else {
             for (int t = 0; t < count; ++t)
-                dst.p[t] = (W *)(ws + ((size_t)(i & 1) * M + t) * plane);
+                dst.p[t] = (W *)(ws + ((size_t)(stage & 1) * M + t) * plane);
         }
         if (m > 0) {
-            st = T::launch(o, count, n, cur, dst, m, s);
+            if (j - i == 1 && !(o.op == NE_OP_PERM || elementwise(o.op))) {
+                st = T::launch(o, count, n, cur, dst, m, s);
+            } else {
+                Segment seg{};
+                seg.perm = o.op == NE_OP_PERM;
+                seg.p = seg.perm ? (const int32_t *)o.operand : nullptr;
+                for (int32_t k = i + seg.perm; k < j; ++k) {
+                    SegmentOp &so = seg.ops[seg.nops++];
+                    so.op = ops[k].op;
+                    so.g = ops[k].operand;
+                    so.s = ops[k].scalar;
+                }
+                st = T::segment(seg, count, n, cur, dst, s);
+            }
             if (st != NE_OK) return st;
         }
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
         n = m;
+        i = j;
+        ++stage;
     }
     return NE_OK;
 }

@@ -461,10 +461,14 @@ def test_gemm_workspace_size_and_checks(lib):
     """Digit planes of every slot (rows padded to 32, the inner dimension to
     64) and of G (columns padded to 64); a short or misaligned workspace is
     refused before anything is launched."""
-    # entangled M = 3, 12-bit values: 5 digits per word, 2 per kernel value
+    # entangled M = 3, 12-bit values: each word split at bit l = 22 into two
+    # fields of 2 digits (4 planes instead of 5 for the whole word), 2 digits
+    # per kernel value
     size = ne.gemm_workspace_size("entangled", 3, 100, 70, 90, 12)
     up = lambda x, m: (x + m - 1) // m * m
-    assert size == up(3 * 5 * 128 * 128, 256) + 2 * 128 * 128
+    assert size == up(3 * 4 * 128 * 128, 256) + 2 * 128 * 128
+    # plain: 12-bit values need 2 digits, no split
+    assert ne.gemm_workspace_size("plain", 3, 100, 70, 90, 12) == up(3 * 2 * 128 * 128, 256) + 2 * 128 * 128
     assert ne.gemm_workspace_size("entangled", 3, 0, 70, 90, 12) == 0
     c = ne._ptr_array([FAKE + 4096 * m for m in range(3)])
     out = ne._ptr_array([FAKE + (1 << 20) + 4096 * m for m in range(3)])
