@@ -44,6 +44,20 @@ def class_key(spec: ne.GroupSpec, mode: str) -> str:
     return f"{mode}|{spec.op}|M{'<=4' if len(spec.c) <= 4 else '>4'}|n{nb}"
 
 
+def _fits(spec, mode: str) -> bool:
+    """Whether the planner accepts a spec as set. A per-wave ring's LDS
+    window grows with the exact tap count, so a choice timed on one member
+    of a power-of-two K bucket may not fit a longer one (sizing only: no
+    device is touched)."""
+    if not isinstance(spec, ne.GroupSpec):
+        return True
+    try:
+        ne.workspace_size([spec], mode)
+        return True
+    except ne.NeError:
+        return False
+
+
 def _choice(v):
     """A cached choice: [steps, ring_waves] (a bare int: steps)."""
     if isinstance(v, int):
@@ -142,4 +156,7 @@ class Tuner:
             self.save()
         for key, members in classes.items():
             self._apply(members, self.cache[key])
+            for s in members:
+                if s.ring_waves == 1 and not _fits(s, mode):
+                    s.ring_waves = 0  # the planner takes the layout that fits
         return {k: self.cache[k] for k in classes}

@@ -46,6 +46,29 @@ def test_cache_round_trip(tmp_path):
     assert all(s.steps == 8 and s.ring_waves == 1 for s in sp)
 
 
+def test_cached_per_wave_ring_falls_back_where_it_does_not_fit(tmp_path, monkeypatch):
+    """A per-wave ring chosen on one member of a K bucket can exceed LDS on
+    a longer member: that member goes back to the planner's own layout
+    choice; the members it fits keep the cached choice."""
+    from paper_1509_03838_amd import ne
+    limit = 2100  # M = 3, 12-bit samples: the planner refuses per-wave rings at K = 2200
+
+    def fake_size(groups, mode="entangled", *a, **k):
+        (g,) = groups
+        if g.ring_waves == 1 and g.operand.numel() > limit:
+            raise ne.NeError("ne_plan_workspace_size", -4, "unsupported")
+        return 0
+
+    monkeypatch.setattr(ne, "workspace_size", fake_size)
+    path = str(tmp_path / "t.json")
+    t = tune.Tuner(path)
+    t.cache = {"entangled|conv|M3|b12|K11|n10": (4, 1)}
+    sp = [ne.GroupSpec("conv", [FakeTensor(1 << 20)] * 3, FakeTensor(K), [], 0, -1, 12)
+          for K in (2048, 2200)]
+    t.tune(sp, "entangled")
+    assert [(s.steps, s.ring_waves) for s in sp] == [(4, 1), (4, 0)]
+
+
 def test_cache_reads_bare_step_counts(tmp_path):
     path = tmp_path / "old.json"
     path.write_text(json.dumps({"steps": {"entangled|scale|M<=4|n6": 4}}))
