@@ -61,6 +61,8 @@ def parse():
                    help="interleaved timing rounds per mode (each of --steps launches)")
     p.add_argument("--settle-ms", type=int, default=300,
                    help="untimed launches of every mode for this long before timing")
+    p.add_argument("--single-launch", action="store_true",
+                   help="the timed mode runs as one persistent launch (ne_tuning.single_launch)")
     p.add_argument("--no-serving", action="store_true",
                    help="batched line: skip the short serving run")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -177,11 +179,15 @@ def main():
     tuned = {}
 
     def make_plan(mode, lost=-1):
+        # "<mode>@single": the mode as one persistent launch
+        mode, _, how = mode.partition("@")
+        single = how == "single" or (args.single_launch and mode == main_mode)
         specs = [ne.GroupSpec(g.op, c_dev[i], k_dev[i], out[i], g.scalar, lost, in_bits)
                  for i, g in enumerate(groups)]
         if tuner is not None:
             tuned.update(tuner.tune(specs, mode))
-        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps)
+        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps,
+                       single_launch=single)
         plan.capture(stream)
         return plan
 
@@ -197,6 +203,8 @@ def main():
     if not args.no_baselines and not args.only:
         runs += [("plain", -1), ("plain_same", -1), ("checksum", -1), ("checksum_same", -1),
                  ("entangled", 1), ("checksum", 1)]
+        if args.config == "uneven" and not args.single_launch:
+            runs += [("entangled@single", -1)]  # the whole batch in one persistent launch
     plans = {}
     for mode, lost in runs:
         plans[(mode, lost)] = make_plan(mode, lost)
@@ -296,6 +304,8 @@ def main():
         "wall_ms_per_step": round(ms_wall, 4),
         "tuned_steps": tuned_summary(tuned, main_mode),
     }
+    if args.single_launch:
+        line["config"]["single_launch"] = True
     line["timing"] = (f"median of {args.rounds} rounds of {args.steps} captured launches per "
                       f"mode, the modes interleaved with a rotating order, after {args.settle_ms} ms "
                       f"of untimed launches of every mode and {args.warmup} warm-up launches each")
@@ -317,6 +327,9 @@ def main():
             "checksum_overhead_pct_vs_plain_same": pct("checksum", "plain_same"),
             "digit_pairs_per_mac": plan_digits,
         }
+        if "entangled_single_launch" in results:
+            line["baselines"]["single_launch_pct_vs_per_variant_launches"] = pct(
+                "entangled_single_launch", main_mode)
     if args.config == "batched" and not args.only:
         line["roofline"]["hbm_ceiling"] = hbm_ceiling(torch, ne, stream, stats, args, achieved)
     if roof["bound"] == "mfma" and not args.only:
@@ -331,6 +344,7 @@ def main():
 
 def name_of(key):
     mode, lost = key
+    mode = mode.replace("@single", "_single_launch")
     return mode if lost < 0 else f"{mode}_one_lost"
 
 

@@ -547,6 +547,9 @@ typedef enum ne_mode {
 #define NE_FLAG_PERM_INDEX 8u  /* a permutation index outside [0, n): that
                                   output is undefined (ne_plan_flags) or 0
                                   (the per-step calls, ne_device_flags) */
+#define NE_FLAG_STALL 16u      /* single launch: a permutation's gathers waited
+                                  past their bound for its layout pass; its
+                                  outputs are undefined */
 
 /* One group: M streams of n int32 samples sharing one operand. */
 typedef struct ne_group {
@@ -595,6 +598,23 @@ typedef struct ne_tuning {
     int32_t conv_steps;   /* 1024-output steps per convolution block; 0: 4 */
     int32_t stream_steps; /* steps of 256 lanes x 4 (M <= 4) or x 2 positions
                              per element-wise block; 0: 4 */
+    int32_t single_launch; /* 0: one launch per kernel variant (a captured run
+                             spreads them over parallel graph branches);
+                             1: the whole run is one persistent launch whose
+                             blocks take the plan's work items from a device
+                             queue: permutation layout passes first, then
+                             the convolutions (longest first) interleaved
+                             with the permutation gathers, then the other
+                             element-wise items; each item at least 4 tile
+                             steps long.
+                             Its menu: conv, circ and xcorr groups of 3..8
+                             data streams with in_bits 9..12 (the digit counts
+                             those take), scale, add, inner and perm groups of
+                             3..8 data streams; any other group makes plan
+                             creation fail with NE_EUNSUP. The queue and the
+                             per-group counters return to zero within each
+                             run: a run that did not complete leaves the plan
+                             unusable (destroy it and build it again). */
 } ne_tuning;
 
 typedef struct ne_plan_stats {

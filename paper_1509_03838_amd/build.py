@@ -17,7 +17,8 @@ SOURCES = ["api.hip", "stream_kernels.hip", "conv_valu.hip", "chain.hip", "fused
            "failstop.hip"]
 
 # fused_conv.hip is compiled once per (kernel class, slot count), and
-# fused_stream.hip once per kernel class: entangled
+# fused_stream.hip and fused_single.hip (the single-launch kernel) once per
+# kernel class: entangled
 # groups of 3..8 streams, plain groups of 1..8, checksum groups of 2..8 data
 # streams (3..9 slots).
 CONV_VARIANTS = ([(0, n) for n in range(3, 9)] + [(1, n) for n in range(1, 9)] +
@@ -39,6 +40,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
               for k, n in CONV_VARIANTS]
     units += [("fused_stream.hip", f"fused_stream_{k}.o", [f"-DNE_KCLASS={k}"]) for k in range(3)]
     units += [("gemm_kernels.hip", f"gemm_kernels_{k}.o", [f"-DNE_KCLASS={k}"]) for k in range(3)]
+    # the single-launch units compile longest: started first
+    units = [("fused_single.hip", f"fused_single_{k}.o", [f"-DNE_KCLASS={k}", "-DNE_SINGLE_LAUNCH"])
+             for k in range(3)] + units
     objs = []
     pending = list(units)
     running = []

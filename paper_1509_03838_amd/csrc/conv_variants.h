@@ -208,4 +208,31 @@ constexpr bool gemm_split_needed(int kclass, int slots, int la, int lb, int max_
     return false;
 }
 
+// The single-launch executor (one persistent kernel per kernel class) holds
+// a fixed menu of kernel bodies: the element-wise operations scale, add,
+// inner product and permutation, and the convolution variants (linear,
+// circular, cross-correlation) that groups of 3..8 data streams with
+// samples and taps of 9..12 bits take, in the block-ring and per-wave-ring
+// layouts. A plan whose groups fall outside the menu runs as separate
+// launches.
+constexpr int kSingleBitsLo = 9, kSingleBitsHi = 12;
+
+constexpr bool single_conv_in_menu(int kclass, int slots, int la, int lb, int shape)
+{
+    for (int mode = 0; mode < kConvModes; ++mode) {
+        if (conv_class_of_mode(mode) != kclass) continue;
+        const int M = conv_checksum_mode(mode) ? slots - 1 : slots;
+        if (M < 3 || M > 8) continue;
+        for (int b = kSingleBitsLo; b <= kSingleBitsHi; ++b) {
+            const DigitCounts d = conv_digits(mode, M, b, 64, true);
+            if (d.la == la && d.lb == lb && conv_shape(d) == shape) return true;
+        }
+    }
+    return false;
+}
+
+// Slot counts of the menu's kernel bodies: 3..8 data streams, + the checksum.
+constexpr int single_slots_lo(int kclass) { return kclass == 2 ? 4 : 3; }
+constexpr int single_slots_hi(int kclass) { return kclass == 2 ? 9 : 8; }
+
 }  // namespace ne

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ne.h"
+
 namespace ne {
 
 constexpr int kFusedMaxM = 8;       // data streams per group in the fused kernels
@@ -35,7 +37,8 @@ enum Flag : uint32_t {
     kFlagInputRange = 1u,   // an input or operand value outside the declared bits
     kFlagLimbs = 2u,        // reserved: digit counts follow the declared (checked) range
     kFlagMismatch = 4u,     // the redundant stream disagreed with the recovered outputs
-    kFlagPermIndex = 8u     // a permutation index outside [0, n)
+    kFlagPermIndex = 8u,    // a permutation index outside [0, n)
+    kFlagStall = 16u        // single launch: a wait for another work item exceeded its bound
 };
 
 struct GroupDev {
@@ -73,6 +76,12 @@ struct GroupDev {
     uint64_t *acc;    // inner product: kMaxSlots accumulators
     int32_t *rows;    // permutation: the streams interleaved, one row of 4 (<= 4 slots)
                       // or 8 int32 per position, in the plan's workspace
+    // Single launch: completion counters of this group's work items, zero
+    // between runs ([0]: layout items of a permutation, or the items of an
+    // inner product; [1]: the gather items of a permutation), and the
+    // counts they reach.
+    uint32_t *sync;
+    int32_t nsync[2];
 };
 
 // Bytes of one copy of one tap-digit plane of the convolution kernel: the
@@ -120,6 +129,39 @@ struct ConvKernel {
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built.
 const ConvKernel *conv_kernel(int kclass, int slots, int la, int lb);
+
+// A work item of the single launch: what to run (kind) on which strip of
+// which group. kind: bits 0-1 category (0 convolution, 1 element-wise,
+// 2 permutation layout pass), 2-5 slots, 6-9 operation, 10-13 LA, 14-16 LB,
+// 17-18 shape, 19-20 LDS layout. steps: a layout item's 1024-position steps.
+struct alignas(16) Task {
+    uint32_t kind, g, strip, steps;
+};
+constexpr int kSingleLayoutSteps = 64;  // 64K positions per layout item of the single launch
+constexpr int kSingleMinSteps = 4;      // shortest strip of a single-launch item, in steps
+// Positions per lane and step of an element-wise item of the single launch:
+// gathers and inner products take twice the per-variant kernel's.
+__host__ __device__ constexpr int single_stream_positions(int op, int slots)
+{
+    return stream_positions(slots) * ((op == NE_OP_INNER || op == NE_OP_PERM) ? 2 : 1);
+}
+enum TaskCategory : uint32_t { kTaskConv = 0, kTaskStream = 1, kTaskLayout = 2 };
+__host__ __device__ constexpr uint32_t task_kind(uint32_t cat, int slots, int op, int la, int lb,
+                                                 int shape, int layout)
+{
+    return cat | (uint32_t)slots << 2 | (uint32_t)op << 6 | (uint32_t)la << 10 |
+           (uint32_t)lb << 14 | (uint32_t)shape << 17 | (uint32_t)layout << 19;
+}
+
+// The single-launch kernel of one kernel class (fused_single.hip).
+struct SingleKernel {
+    void (*launch)(const GroupDev *g, const Task *tasks, uint32_t ntasks, uint32_t *queue,
+                   uint32_t *flags, uint32_t grid, size_t lds, hipStream_t s);
+    hipError_t (*prepare)(size_t lds);                   // raises the LDS limit
+    hipError_t (*blocks_per_cu)(size_t lds, int *blocks);  // resident blocks per CU
+};
+// Null if the class has no single-launch kernel.
+const SingleKernel *single_kernel(int kclass);
 
 // One element-wise kernel variant (fused_stream.hip, compiled once per kernel
 // class): operation x slot count.

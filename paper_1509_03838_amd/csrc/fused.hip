@@ -72,6 +72,22 @@ StreamLaunch stream_kernel(int op, int kclass, int slots)
     }
 }
 
+// Single-launch kernels built by fused_single.hip (one translation unit per
+// kernel class).
+const SingleKernel *single_kernel_0();
+const SingleKernel *single_kernel_1();
+const SingleKernel *single_kernel_2();
+
+const SingleKernel *single_kernel(int kclass)
+{
+    switch (kclass) {
+    case 0: return single_kernel_0();
+    case 1: return single_kernel_1();
+    case 2: return single_kernel_2();
+    default: return nullptr;
+    }
+}
+
 void fused_interleave_launch(int cls, const GroupDev *g, const Item *items, uint32_t nitems,
                              hipStream_t s)
 {

@@ -47,6 +47,20 @@ __device__ __forceinline__ uint32_t item_index(uint32_t nitems)
     return (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
 }
 
+// The thread's index in its block, as a work item's body reads it. The
+// single-launch kernel runs every body inside one loop over work items:
+// there each body takes the index afresh (an empty asm the optimizer cannot
+// move), so that the values a body derives from it are computed inside that
+// body instead of being hoisted out of the loop and kept live across all.
+__device__ __forceinline__ int item_tid()
+{
+    int t = (int)threadIdx.x;
+#if defined(NE_SINGLE_LAUNCH)
+    asm volatile("" : "+v"(t));
+#endif
+    return t;
+}
+
 __device__ __forceinline__ int64_t ent(int64_t cur, int64_t prev, int l)
 {
     return (int64_t)((uint64_t)cur + ((uint64_t)prev << l));
@@ -401,10 +415,11 @@ __device__ __forceinline__ constexpr bool pair_first(int a, int b)
 // positions per wave instead of per block.
 // TC: copies of each tap-digit plane (4, or 1 with GW = 4, below).
 // FS: digits per field of words split at bit l (0: not split; LA = 2 FS).
+// conv_item runs one work item (a strip of one group); k_conv_fused is one
+// launch over a bucket of items of this variant.
 template <int LA, int LB, int NS, int KCLASS, int GW, int SP, int TC, int FS = 0>
-__global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
-                                                       const Item *__restrict__ items,
-                                                       uint32_t nitems, uint32_t *flags)
+__device__ __forceinline__ void conv_item(const GroupDev *__restrict__ groups, const Item it,
+                                          uint32_t *flags)
 {
     constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
     constexpr int M = KCLASS == 2 ? NS - 1 : NS;  // data streams
@@ -418,9 +433,6 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     constexpr int SPAN = 256 * GW;   // positions a ring advances per step
     constexpr int GT = 64 * GW;      // threads staging one ring
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const uint32_t ii = item_index(nitems);
-    if (ii >= nitems) return;
-    const Item it = items[ii];
     const GroupDev *G = groups + it.g;
     const int skip = G->skip, l = G->l;
     const int nch = G->nch, kp = G->kp;
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     const int steps = G->steps, acc16 = G->acc16, use_dma = G->dma;
     const int64_t n = G->n, K = G->K, n_out = G->n_out;
     const int32_t *__restrict__ g = G->operand;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = item_tid(), lane = tid & 63, wave = tid >> 6;
     const int grp = wave / GW, wg = wave % GW, gt = tid % GT;  // ring, wave and thread in it
     uint32_t flag = 0;
     Bounds bd;
@@ -791,13 +803,29 @@ __global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restric
     if (flag) atomicOr(flags, flag);
 }
 
+template <int LA, int LB, int NS, int KCLASS, int GW, int SP, int TC, int FS = 0>
+__global__ __launch_bounds__(kBlock) void k_conv_fused(const GroupDev *__restrict__ groups,
+                                                       const Item *__restrict__ items,
+                                                       uint32_t nitems, uint32_t *flags)
+{
+    const uint32_t ii = item_index(nitems);
+    if (ii >= nitems) return;
+    conv_item<LA, LB, NS, KCLASS, GW, SP, TC, FS>(groups, items[ii], flags);
+}
+
 // ------------------------------------------------ element-wise operations
 
-// V consecutive int32 values (V = 2: one 8-byte load, V = 4: one 16-byte load).
+// V consecutive int32 values (V = 2: one 8-byte load, V = 4: one 16-byte
+// load, V = 8: two).
 template <int V, typename T>
 __device__ __forceinline__ void load_vec(const int32_t *src, T (&x)[V])
 {
-    if constexpr (V == 4) {
+    if constexpr (V == 8) {
+        const int4 w = *reinterpret_cast<const int4 *>(src);
+        const int4 u = *reinterpret_cast<const int4 *>(src + 4);
+        x[0] = w.x; x[1] = w.y; x[2] = w.z; x[3] = w.w;
+        x[4] = u.x; x[5] = u.y; x[6] = u.z; x[7] = u.w;
+    } else if constexpr (V == 4) {
         const int4 w = *reinterpret_cast<const int4 *>(src);
         x[0] = w.x; x[1] = w.y; x[2] = w.z; x[3] = w.w;
     } else {
@@ -869,21 +897,19 @@ __device__ __forceinline__ void recover_inplace(int mode, int M, int skip, int l
 // workspace: a row holds every stream's sample of one position, so that the
 // gather at pi[i] reads one 16- or 32-byte row instead of M scattered words.
 // A layout change only; no arithmetic. 4 positions per lane per step.
+// steps: 1024-position steps per work item (strip it.strip of that length).
 template <int RW>
-__global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restrict__ groups,
-                                                       const Item *__restrict__ items,
-                                                       uint32_t nitems)
+__device__ __forceinline__ void interleave_item(const GroupDev *__restrict__ groups, const Item it,
+                                                int steps)
 {
-    const uint32_t ii = blockIdx.x;
-    if (ii >= nitems) return;
-    const Item it = items[ii];
     const GroupDev *G = groups + it.g;
-    const int M = G->M, steps = G->steps;
+    const int M = G->M;
     const int64_t n = G->n;
+    const int tid = item_tid();
     int32_t *__restrict__ rows = G->rows;
     const int64_t strip0 = (int64_t)it.strip * steps * kBlock * 4;
     for (int q = 0; q < steps; ++q) {
-        const int64_t p = strip0 + (int64_t)q * kBlock * 4 + 4 * threadIdx.x;
+        const int64_t p = strip0 + (int64_t)q * kBlock * 4 + 4 * tid;
         if (p >= n) break;
         const bool full = p + 4 <= n;
         int32_t x[RW][4];
@@ -913,6 +939,17 @@ __global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restric
     }
 }
 
+template <int RW>
+__global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restrict__ groups,
+                                                       const Item *__restrict__ items,
+                                                       uint32_t nitems)
+{
+    const uint32_t ii = blockIdx.x;
+    if (ii >= nitems) return;
+    const Item it = items[ii];
+    interleave_item<RW>(groups, it, groups[it.g].steps);
+}
+
 // Scale, add, permutation and inner product: V consecutive positions per
 // lane per step (8- or 16-byte loads, 16-byte stores), all M streams of the group at
 // once (entangle -> op -> recover in registers). The descriptor holds the
@@ -926,21 +963,20 @@ __global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restric
 // Items are taken in plain block order (no per-XCD runs): neighbouring
 // blocks then work on the same group at the same time, so a permutation's
 // random gathers fall into a working set the memory-side cache holds.
-template <int OP, int KCLASS, int NS>
-__global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
-                                                         const Item *__restrict__ items,
-                                                         uint32_t nitems, uint32_t *flags)
+// VX: a multiple of the positions per lane (the single launch gives its
+// gathers and inner products twice as many, for more loads in flight).
+template <int OP, int KCLASS, int NS, int VX = 1>
+__device__ __forceinline__ void stream_item(const GroupDev *__restrict__ groups, const Item it,
+                                            uint32_t *flags)
 {
-    constexpr int V = stream_positions(NS);
+    constexpr int V = stream_positions(NS) * VX;
     constexpr int op = OP;
     constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
     constexpr int M = KCLASS == 2 ? NS - 1 : NS;
     constexpr int nslots = NS;
-    static_assert(V == 2 || V == 4, "2 or 4 positions per lane");
-    const uint32_t ii = blockIdx.x;
-    if (ii >= nitems) return;
-    const Item it = items[ii];
+    static_assert(V == 2 || V == 4 || V == 8, "2, 4 or 8 positions per lane");
     const GroupDev *G = groups + it.g;
+    const int tid = item_tid();
     const int skip = G->skip, l = G->l;
     const int steps = G->steps;
     // the outer product iterates over its n K outputs: output o takes input
@@ -957,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     for (int q = 0; q < steps; ++q) {
         const int64_t pb = strip0 + (int64_t)q * kBlock * V;
         if (pb >= n) break;
-        const int64_t p = pb + V * threadIdx.x;
+        const int64_t p = pb + V * tid;
         const bool full = p + V <= n;
         int64_t src[V];
         int64_t gj[V];
@@ -1106,11 +1142,15 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
             if (G->out32) {
                 int32_t *o = (int32_t *)G->out[t] + p;
                 if (full) {
-                    if constexpr (V == 4)
-                        *reinterpret_cast<v4i *>(o) = v4i{(int32_t)dl[t][0], (int32_t)dl[t][1],
-                                                          (int32_t)dl[t][2], (int32_t)dl[t][3]};
-                    else
+                    if constexpr (V >= 4) {
+#pragma unroll
+                        for (int v = 0; v < V; v += 4)
+                            *reinterpret_cast<v4i *>(o + v) =
+                                v4i{(int32_t)dl[t][v], (int32_t)dl[t][v + 1], (int32_t)dl[t][v + 2],
+                                    (int32_t)dl[t][v + 3]};
+                    } else {
                         *reinterpret_cast<int2 *>(o) = int2{(int32_t)dl[t][0], (int32_t)dl[t][1]};
+                    }
                 } else {
 #pragma unroll
                     for (int v = 0; v < V; ++v)
@@ -1138,14 +1178,14 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1)
                 v += (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
-            if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][t] = v;
+            if ((tid & 63) == 0) part[tid >> 6][t] = v;
         }
         __syncthreads();
-        if (threadIdx.x < NS && (int)threadIdx.x < nslots) {
+        if (tid < NS && tid < nslots) {
             uint64_t s = 0;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) s += part[w][threadIdx.x];
-            atomicAdd(reinterpret_cast<unsigned long long *>(G->acc + threadIdx.x),
+            for (int w = 0; w < kBlock / 64; ++w) s += part[w][tid];
+            atomicAdd(reinterpret_cast<unsigned long long *>(G->acc + tid),
                       (unsigned long long)s);
         }
     }
@@ -1153,8 +1193,42 @@ __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restr
     if (flag) atomicOr(flags, flag);
 }
 
-// Recovery of inner products (one output per stream) after all partial
-// sums have landed; also clears the accumulators for the next run.
+template <int OP, int KCLASS, int NS>
+__global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
+                                                         const Item *__restrict__ items,
+                                                         uint32_t nitems, uint32_t *flags)
+{
+    const uint32_t ii = blockIdx.x;
+    if (ii >= nitems) return;
+    stream_item<OP, KCLASS, NS>(groups, items[ii], flags);
+}
+
+// Recovery of one group's inner products (one output per stream) from its
+// accumulated partial sums; also clears the accumulators for the next run.
+// ATOMIC: read and clear each accumulator with one device-scope exchange
+// (when the partial sums came from other blocks of the same launch).
+template <int NS, bool ATOMIC = false>
+__device__ __forceinline__ void inner_finalize_group(const GroupDev *__restrict__ G,
+                                                     uint32_t *flags)
+{
+    uint32_t flag = 0;
+    int64_t dl[NS][1];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        if constexpr (ATOMIC) {
+            dl[t][0] = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(G->acc + t), 0ull);
+        } else {
+            dl[t][0] = (int64_t)G->acc[t];
+            G->acc[t] = 0;
+        }
+    }
+    const int loc[1] = {0};
+    epilogue<NS, 1>(G, G->mode, G->M, G->skip, G->l, 0, 1, loc, dl, flag);
+    if (flag) atomicOr(flags, flag);
+}
+
+// Recovery of inner products after all partial sums have landed (a launch
+// of its own, after the element-wise launches).
 template <int NS>
 __global__ __launch_bounds__(64) void k_inner_finalize(const GroupDev *__restrict__ groups,
                                                        const uint32_t *__restrict__ gidx,
@@ -1162,17 +1236,7 @@ __global__ __launch_bounds__(64) void k_inner_finalize(const GroupDev *__restric
 {
     const uint32_t i = blockIdx.x * 64 + threadIdx.x;
     if (i >= count) return;
-    const GroupDev *G = groups + gidx[i];
-    uint32_t flag = 0;
-    int64_t dl[NS][1];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        dl[t][0] = (int64_t)G->acc[t];
-        G->acc[t] = 0;
-    }
-    const int loc[1] = {0};
-    epilogue<NS, 1>(G, G->mode, G->M, G->skip, G->l, 0, 1, loc, dl, flag);
-    if (flag) atomicOr(flags, flag);
+    inner_finalize_group<NS>(groups + gidx[i], flags);
 }
 
 }  // namespace fk

@@ -32,8 +32,10 @@ struct ne_plan {
     std::vector<Bucket> buckets;
     std::vector<Item> items;
     std::vector<uint32_t> inner;
+    std::vector<Task> tasks;           // single launch: the work queue, in order
     std::vector<unsigned char> image;  // host copy of the device tables, uploaded verbatim
     size_t sz_groups = 0, sz_items = 0, sz_inner = 0, sz_acc = 0, sz_flags = 0, sz_rows = 0;
+    size_t sz_tasks = 0, sz_sync = 0;
     std::vector<std::pair<uint32_t, size_t>> rows;  // permutation groups: (group, row offset)
     bool owns_arena = false;
     unsigned char *arena = nullptr;  // device: groups | items | inner idx | acc | flags
@@ -42,6 +44,14 @@ struct ne_plan {
     uint32_t *d_inner = nullptr;
     uint32_t n_inner = 0;
     uint32_t *d_flags = nullptr;
+    // single launch: its kernel, grid and LDS, the tasks, the queue (head,
+    // blocks done) and the per-group counters
+    const SingleKernel *single = nullptr;
+    uint32_t single_grid = 0;
+    size_t single_lds = 0;
+    Task *d_tasks = nullptr;
+    uint32_t *d_queue = nullptr;
+    uint32_t *d_sync = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipStream_t> branch;  // streams of the graph's parallel branches (capture only)
@@ -85,8 +95,23 @@ int register_blocks(const ConvKernel *ck, int shape, int layout)
 
 // Kernel variants whose LDS exceeds the default limit get it raised (once per
 // plan creation; the plan tables are host-only until then).
-static hipError_t plan_prepare(const ne_plan *plan)
+static hipError_t plan_prepare(ne_plan *plan)
 {
+    if (plan->single) {
+        // one launch of as many blocks as stay resident at once
+        if (plan->single_lds > 64 * 1024) {
+            const hipError_t e = plan->single->prepare(plan->single_lds);
+            if (e != hipSuccess) return e;
+        }
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = plan->single->blocks_per_cu(plan->single_lds, &per_cu);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+        plan->single_grid = (uint32_t)(per_cu * cus);
+        return hipSuccess;
+    }
     for (const Bucket &b : plan->buckets) {
         if (b.conv <= 0 || b.lds <= 64 * 1024) continue;
         const hipError_t e = b.ck->prepare[(b.cls >> 2) & 3][b.cls & 3](b.lds);
@@ -108,6 +133,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     const int stream_steps =
         (tuning && tuning->stream_steps > 0) ? tuning->stream_steps : kStreamStepsDefault;
     if (conv_steps > 4096 || stream_steps > 4096) return NE_EINVAL;
+    const int single_launch = tuning ? tuning->single_launch : 0;
+    if (single_launch != 0 && single_launch != 1) return NE_EINVAL;
+    const int kclass = conv_class_of_mode(mode);
+    const SingleKernel *sk = single_launch ? single_kernel(kclass) : nullptr;
+    if (single_launch && !sk) return NE_EUNSUP;
 
     ne_plan *plan = new (std::nothrow) ne_plan;
     if (!plan) return NE_ENOMEM;
@@ -119,6 +149,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     std::map<std::tuple<int, int, int, int>, size_t> bucket_lds;
     std::vector<uint32_t> inner_groups;
     size_t rows_bytes = 0;
+    // single launch: tasks by queue section (layout passes; convolutions,
+    // with their groups' work per strip for the longest-first order;
+    // element-wise items; permutation gathers)
+    std::vector<Task> t_layout, t_stream, t_perm;
+    std::vector<std::pair<int64_t, std::vector<Task>>> t_conv;
     ne_plan_stats st{};
     st.groups = n_groups;
 
@@ -140,8 +175,11 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         if (u.tap_copies == 1 && u.ring_waves == 1) return fail(NE_EINVAL);
         if (u.word_bits != 0 && u.word_bits != 32 && u.word_bits != 64) return fail(NE_EINVAL);
         const int w = u.word_bits == 32 ? 32 : 64;
-        const int g_conv_steps = u.steps > 0 ? u.steps : conv_steps;
-        const int g_stream_steps = u.steps > 0 ? u.steps : stream_steps;
+        // the single launch balances its load through the queue: its items
+        // are at least kSingleMinSteps long (each pays a claim and barriers)
+        const int min_steps = sk ? kSingleMinSteps : 1;
+        const int g_conv_steps = std::max(u.steps > 0 ? u.steps : conv_steps, min_steps);
+        const int g_stream_steps = std::max(u.steps > 0 ? u.steps : stream_steps, min_steps);
         if (u.op < NE_OP_CONV || u.op > NE_OP_OUTER) return fail(NE_EUNSUP);
         const bool convlike = u.op == NE_OP_CONV || u.op == NE_OP_CIRC || u.op == NE_OP_XCORR;
         for (int m = 0; m < u.M; ++m) {
@@ -280,7 +318,6 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             // Blocks of this variant that can share a CU (bound by LDS and
             // by registers), with the raw-input prefetch buffer (M x 4 KiB)
             // when it costs no block.
-            const int kclass = conv_class_of_mode(mode);
             const ConvKernel *ck = conv_kernel(kclass, G.nslots, la, lb);
             if (!ck || !ck->launch[shape][0]) return fail(NE_EUNSUP);
             const size_t raw = (size_t)u.M * 4096;
@@ -321,6 +358,14 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
             bucket_lds[key] = std::max(bucket_lds[key], lds);
+            if (sk) {
+                if (layout > 1 || !single_conv_in_menu(kclass, G.nslots, la, lb, shape))
+                    return fail(NE_EUNSUP);
+                const uint32_t kind = task_kind(kTaskConv, G.nslots, u.op, la, lb, shape, layout);
+                std::vector<Task> ts;
+                for (int64_t s = 0; s < nstrips; ++s) ts.push_back(Task{kind, (uint32_t)gi, (uint32_t)s, 0});
+                t_conv.emplace_back(strip * 64 * G.nch * la * lb, std::move(ts));
+            }
             const int64_t slots_run = G.nslots - G.lost;
             // (a sparse top tap digit runs only where the taps need it: that
             // data-dependent part is not counted)
@@ -336,8 +381,24 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
             const int64_t nit = u.op == NE_OP_OUTER ? n_out : u.n;
             const int64_t nstrips = (nit + strip - 1) / strip;
             if (nstrips > ((int64_t)1 << 24)) return fail(NE_EUNSUP);  // work-item table size
-            const int kclass = conv_class_of_mode(mode);
             if (!stream_kernel(u.op, kclass, G.nslots)) return fail(NE_EUNSUP);
+            if (sk) {
+                if ((u.op != NE_OP_SCALE && u.op != NE_OP_ADD && u.op != NE_OP_INNER &&
+                     u.op != NE_OP_PERM) ||
+                    G.nslots < single_slots_lo(kclass) || G.nslots > single_slots_hi(kclass))
+                    return fail(NE_EUNSUP);
+                // strips of the single launch's positions per lane; an inner
+                // product's last item recovers it: at least one item
+                const int64_t sstrip =
+                    (int64_t)g_stream_steps * 256 * single_stream_positions(u.op, G.nslots);
+                const int64_t sn = (nit + sstrip - 1) / sstrip;
+                const int64_t nt = u.op == NE_OP_INNER ? std::max<int64_t>(sn, 1) : sn;
+                const uint32_t kind = task_kind(kTaskStream, G.nslots, u.op, 0, 0, 0, 0);
+                auto &dst = u.op == NE_OP_PERM ? t_perm : t_stream;
+                for (int64_t s = 0; s < nt; ++s) dst.push_back(Task{kind, (uint32_t)gi, (uint32_t)s, 0});
+                if (u.op == NE_OP_INNER) G.nsync[0] = (int32_t)nt;
+                if (u.op == NE_OP_PERM) G.nsync[1] = (int32_t)nt;
+            }
             auto key = std::make_tuple(0, (u.op * 4 + kclass) * 16 + G.nslots, 0, 0);
             auto &v = bucket_items[key];
             for (int64_t s = 0; s < nstrips; ++s) v.push_back(Item{(uint32_t)gi, (uint32_t)s});
@@ -350,8 +411,19 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
                 rows_bytes += ((size_t)u.n * rw * 4 + 255) & ~(size_t)255;
                 const int64_t istrip = (int64_t)g_stream_steps * kInterleaveStep;
                 auto &iv = bucket_items[std::make_tuple(-1, cls, 0, 0)];
-                for (int64_t s = 0; s < (u.n + istrip - 1) / istrip; ++s)
+                const int64_t nlayout = (u.n + istrip - 1) / istrip;
+                for (int64_t s = 0; s < nlayout; ++s)
                     iv.push_back(Item{(uint32_t)gi, (uint32_t)s});
+                if (sk) {
+                    // larger layout items: each ends with an L2 write-back
+                    const uint32_t kind = task_kind(kTaskLayout, G.nslots, u.op, 0, 0, 0, 0);
+                    const int64_t lstrip = (int64_t)kSingleLayoutSteps * kInterleaveStep;
+                    const int64_t nl = (u.n + lstrip - 1) / lstrip;
+                    for (int64_t s = 0; s < nl; ++s)
+                        t_layout.push_back(
+                            Task{kind, (uint32_t)gi, (uint32_t)s, (uint32_t)kSingleLayoutSteps});
+                    G.nsync[0] = (int32_t)nl;
+                }
             }
         }
     }
@@ -376,6 +448,35 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     plan->n_inner = (uint32_t)inner_groups.size();
     st.items = (int64_t)all_items.size();
     st.launches = (int64_t)plan->buckets.size() + (plan->n_inner ? 1 : 0);
+    if (sk) {
+        // The queue: layout passes; then the convolutions (most work per
+        // strip first, a group's strips together) interleaved evenly with
+        // the permutation gathers, so that the matrix-core work overlaps the
+        // gathers' memory latency; then the other element-wise items.
+        std::stable_sort(t_conv.begin(), t_conv.end(),
+                         [](const auto &a, const auto &b) { return a.first > b.first; });
+        std::vector<Task> conv;
+        for (auto &c : t_conv) conv.insert(conv.end(), c.second.begin(), c.second.end());
+        std::vector<Task> &q = plan->tasks;
+        q = std::move(t_layout);
+        size_t ic = 0, ip = 0;
+        while (ic < conv.size() || ip < t_perm.size()) {
+            // take from the list that is further behind its share
+            const bool take_conv =
+                ip >= t_perm.size() ||
+                (ic < conv.size() && (double)ic * t_perm.size() <= (double)ip * conv.size());
+            q.push_back(take_conv ? conv[ic++] : t_perm[ip++]);
+        }
+        q.insert(q.end(), t_stream.begin(), t_stream.end());
+        if (q.size() > ((size_t)1 << 31)) {
+            delete plan;
+            return NE_EUNSUP;
+        }
+        plan->single = sk;
+        for (const Bucket &b : plan->buckets) plan->single_lds = std::max(plan->single_lds, b.lds);
+        st.items = (int64_t)q.size();
+        st.launches = q.empty() ? 0 : 1;
+    }
 
     // One device arena: groups | items | inner index | accumulators | flags.
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -385,6 +486,10 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
     plan->sz_acc = up(sizeof(uint64_t) * kMaxSlots * std::max<size_t>(1, inner_groups.size()));
     plan->sz_flags = 256;
     plan->sz_rows = rows_bytes;
+    if (sk) {
+        plan->sz_tasks = up(sizeof(Task) * std::max<size_t>(1, plan->tasks.size()));
+        plan->sz_sync = up(256 + sizeof(uint32_t) * 2 * std::max(1, n_groups));
+    }
     plan->items = std::move(all_items);
     plan->inner = std::move(inner_groups);
     plan->stats = st;
@@ -396,7 +501,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
 // tables, then the permutation rows, which the layout pass writes).
 static size_t table_bytes(const ne_plan *p)
 {
-    return p->sz_groups + p->sz_items + p->sz_inner + p->sz_acc + p->sz_flags;
+    return p->sz_groups + p->sz_items + p->sz_inner + p->sz_acc + p->sz_flags + p->sz_tasks +
+           p->sz_sync;
 }
 
 static size_t plan_bytes(const ne_plan *p) { return table_bytes(p) + p->sz_rows; }
@@ -417,6 +523,16 @@ static void plan_place(ne_plan *plan, unsigned char *arena)
     p += plan->sz_acc;
     plan->d_flags = (uint32_t *)p;
     p += plan->sz_flags;
+    if (plan->single) {
+        // tasks | queue (head, blocks done; 256 bytes) | two counters per group
+        plan->d_tasks = (Task *)p;
+        p += plan->sz_tasks;
+        plan->d_queue = (uint32_t *)p;
+        plan->d_sync = (uint32_t *)(p + 256);
+        p += plan->sz_sync;
+        for (size_t gi = 0; gi < plan->host_groups.size(); ++gi)
+            plan->host_groups[gi].sync = plan->d_sync + 2 * gi;
+    }
     for (const auto &r : plan->rows) plan->host_groups[r.first].rows = (int32_t *)(p + r.second);
     for (size_t i = 0; i < plan->inner.size(); ++i)
         plan->host_groups[plan->inner[i]].acc = d_acc + kMaxSlots * i;
@@ -426,6 +542,9 @@ static void plan_place(ne_plan *plan, unsigned char *arena)
     memcpy(h + plan->sz_groups, plan->items.data(), sizeof(Item) * plan->items.size());
     memcpy(h + plan->sz_groups + plan->sz_items, plan->inner.data(),
            sizeof(uint32_t) * plan->inner.size());
+    if (plan->single)
+        memcpy(h + plan->sz_groups + plan->sz_items + plan->sz_inner + plan->sz_acc + plan->sz_flags,
+               plan->tasks.data(), sizeof(Task) * plan->tasks.size());
 }
 
 ne_status ne_plan_create(const ne_group *groups, int32_t n_groups, int32_t mode,
@@ -509,10 +628,21 @@ static void launch_bucket(const ne_plan *plan, const Bucket &b, hipStream_t s)
         b.sk(plan->d_groups, plan->d_items + b.first, b.count, plan->d_flags, s);
 }
 
+static void launch_single(const ne_plan *plan, hipStream_t s)
+{
+    if (plan->tasks.empty()) return;
+    plan->single->launch(plan->d_groups, plan->d_tasks, (uint32_t)plan->tasks.size(),
+                         plan->d_queue, plan->d_flags, plan->single_grid, plan->single_lds, s);
+}
+
 ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
 {
     if (!plan) return NE_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (plan->single) {
+        launch_single(plan, s);
+        return launch_status();
+    }
     for (const Bucket &b : plan->buckets) launch_bucket(plan, b, s);
     if (plan->n_inner)
         fused_inner_finalize(plan->d_groups, plan->d_inner, plan->n_inner, plan->d_flags, s);
@@ -526,6 +656,10 @@ ne_status ne_plan_run(ne_plan *plan, ne_stream stream)
 // its rows form one chain on one branch.
 static ne_status capture_branches(ne_plan *plan, hipStream_t s)
 {
+    if (plan->single) {
+        launch_single(plan, s);
+        return launch_status();
+    }
     std::vector<std::vector<const Bucket *>> chains;
     int chain_of_cls[2] = {-1, -1};
     for (const Bucket &b : plan->buckets) {  // layout passes sort first
@@ -595,7 +729,8 @@ ne_status ne_plan_capture(ne_plan *plan, ne_stream stream)
     }
     // branch streams and their events, created before the capture begins
     size_t nwork = 0;
-    for (const Bucket &b : plan->buckets) nwork += b.count > 0;
+    if (!plan->single)
+        for (const Bucket &b : plan->buckets) nwork += b.count > 0;
     hipError_t e = hipSuccess;
     if (nwork > 1) {
         while (plan->branch.size() < kBranches && e == hipSuccess) {

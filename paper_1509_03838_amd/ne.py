@@ -37,7 +37,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3, "checksum_same": 4}
-FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH, FLAG_PERM_INDEX = 1, 2, 4, 8
+FLAG_INPUT_RANGE, FLAG_LIMBS, FLAG_MISMATCH, FLAG_PERM_INDEX, FLAG_STALL = 1, 2, 4, 8, 16
 
 
 class GroupC(ctypes.Structure):
@@ -59,7 +59,8 @@ class ChainOpC(ctypes.Structure):
 
 
 class TuningC(ctypes.Structure):
-    _fields_ = [("conv_steps", ctypes.c_int32), ("stream_steps", ctypes.c_int32)]
+    _fields_ = [("conv_steps", ctypes.c_int32), ("stream_steps", ctypes.c_int32),
+                ("single_launch", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
@@ -489,11 +490,11 @@ class GroupSpec:
 
 
 def workspace_size(groups: Sequence[GroupSpec], mode: str = "entangled", conv_steps: int = 0,
-                   stream_steps: int = 0) -> int:
+                   stream_steps: int = 0, single_launch: bool = False) -> int:
     arr = (GroupC * max(1, len(groups)))()
     for i, g in enumerate(groups):
         arr[i] = g.to_c()
-    tun = TuningC(conv_steps, stream_steps)
+    tun = TuningC(conv_steps, stream_steps, int(single_launch))
     size = ctypes.c_size_t()
     _check("ne_plan_workspace_size", load().ne_plan_workspace_size(
         arr, len(groups), MODES[mode], ctypes.byref(tun), ctypes.byref(size)))
@@ -503,10 +504,11 @@ def workspace_size(groups: Sequence[GroupSpec], mode: str = "entangled", conv_st
 class Plan:
     """A batched run of many groups (ne_plan_*). With `workspace` (a device
     uint8 tensor of at least workspace_size() bytes) and `stream`, the plan
-    allocates nothing and uploads its tables asynchronously on that stream."""
+    allocates nothing and uploads its tables asynchronously on that stream.
+    single_launch: the whole run is one persistent launch (ne_tuning)."""
 
     def __init__(self, groups: Sequence[GroupSpec], mode: str = "entangled", conv_steps: int = 0,
-                 stream_steps: int = 0, workspace=None, stream=None):
+                 stream_steps: int = 0, workspace=None, stream=None, single_launch: bool = False):
         L = load()
         self._groups = list(groups)  # keeps the tensors alive
         self._ws = workspace
@@ -515,7 +517,7 @@ class Plan:
         arr = (GroupC * max(1, len(self._groups)))()
         for i, g in enumerate(self._groups):
             arr[i] = g.to_c()
-        tun = TuningC(conv_steps, stream_steps)
+        tun = TuningC(conv_steps, stream_steps, int(single_launch))
         h = ctypes.c_void_p()
         if workspace is None:
             _check("ne_plan_create", L.ne_plan_create(arr, len(self._groups), MODES[mode],

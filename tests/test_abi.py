@@ -521,3 +521,45 @@ def test_wait_streams_and_delay_argument_checks(lib):
     assert lib.ne_stream_delay(1_000_001, None) == -1
     assert lib.ne_stream_delay(0, None) == 0      # nothing enqueued
     assert b"deadline" in lib.ne_strerror(-8)
+
+
+def _gm(**kw):
+    """_group with a stream and an output pointer for each of M streams."""
+    g = _group(**kw)
+    for m in range(g.M):
+        g.c[m] = FAKE + 256 * m
+        g.out[m] = FAKE + 4096 + 1024 * m
+    return g
+
+
+def _ws_single(lib, groups, mode=0, single=1):
+    size = ctypes.c_size_t()
+    tun = ne.TuningC(0, 0, single)
+    st = lib.ne_plan_workspace_size((ne.GroupC * len(groups))(*groups), len(groups), mode,
+                                    ctypes.byref(tun), ctypes.byref(size))
+    return st, size.value
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
+def test_single_launch_menu(lib, mode):
+    """The single launch takes convolutions of 9..12-bit samples and scale,
+    add, inner and perm groups of 3..8 data streams in every mode; 16-bit
+    convolutions, other operations, the one-copy tap layout and more or fewer
+    streams are refused (NE_EUNSUP) before anything touches a device, and
+    single_launch must be 0 or 1."""
+    ok = [_gm(in_bits=b, M=M) for b in (9, 10, 11, 12) for M in (3, 5, 8)]
+    ok += [_gm(op=op, n_operand=0 if op == 1 else 100, in_bits=10, M=M)
+           for op in (1, 2, 3, 4) for M in (3, 8)]  # scale, add, inner, perm
+    for g in ok:
+        assert _ws_single(lib, [g], mode)[0] == 0
+    st, both = _ws_single(lib, ok, mode)
+    assert st == 0
+    st, multi = _ws_single(lib, ok, mode, single=0)
+    # the queue (16 bytes a task), 8 bytes of counters a group and the queue head
+    assert st == 0 and both > multi
+    for bad in (_gm(in_bits=16), _gm(in_bits=8), _gm(op=9, n_operand=4),
+                _gm(op=5, n_operand=100, in_bits=10), _gm(tap_copies=1, ring_waves=4)):
+        assert _ws_single(lib, [bad], mode)[0] == -4
+    if mode in (1, 2):  # plain groups may hold 1 or 2 streams, outside the menu
+        assert _ws_single(lib, [_gm(M=2, op=1, n_operand=0, in_bits=10)], mode)[0] == -4
+    assert _ws_single(lib, ok[:1], mode, single=2)[0] == -1
