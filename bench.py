@@ -203,7 +203,7 @@ def main():
     if not args.no_baselines and not args.only:
         runs += [("plain", -1), ("plain_same", -1), ("checksum", -1), ("checksum_same", -1),
                  ("entangled", 1), ("checksum", 1)]
-        if args.config == "uneven" and not args.single_launch:
+        if args.config in ("uneven", "batched") and not args.single_launch:
             runs += [("entangled@single", -1)]  # the whole batch in one persistent launch
     plans = {}
     for mode, lost in runs:
