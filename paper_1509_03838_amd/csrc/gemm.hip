@@ -46,21 +46,30 @@ __device__ __forceinline__ void store_nt(int64_t *p, int64_t v)
 }
 
 // Phase 2: slot blockIdx.z's product. The block stages each 64-deep chunk
-// of its 64 A rows and 64 B columns (all digit planes) in LDS once -- 16-byte
-// loads into registers one chunk ahead, written to the other of two LDS
-// buffers, one barrier per chunk -- and every wave reads its fragments from
-// there (rows of 80 bytes: conflict-free 16-byte reads): every digit pair
-// of 16 x 64 A and 64 x 16 B fragments goes into the accumulator of its
-// weight, each wave a 32 x 32 tile (2 x 2 matrix-core tiles). The entangled
-// (or plain) int64 products y = sum_s 256^s acc_s (mod 2^64) go to the
-// slot's output buffer.
-constexpr int kDigitRow = 80;                        // LDS bytes per staged row (64 + 16)
+// of its 64 A rows and 64 B columns (all digit planes) in LDS once, by direct
+// HBM-to-LDS loads (no staging registers: 154 instead of 206 VGPRs for the
+// split-word variant) into two buffers, the next chunk's loads in flight
+// while this chunk's products run, one barrier per chunk (three buffers,
+// two chunks ahead, measured 5-8% slower: 72 KB of LDS admit 2 blocks per
+// CU, 48 KB admit 3); every wave reads its fragments
+// from there: every digit pair of 16 x 64 A and 64 x 16 B fragments goes
+// into the accumulator of its weight, each wave a 32 x 32 tile (2 x 2
+// matrix-core tiles). The entangled (or plain) int64 products
+// y = sum_s 256^s acc_s (mod 2^64) go to the slot's output buffer.
+//
+// LDS rows are 64 bytes, unpadded (a direct load fills 1 KB contiguously):
+// row r keeps its 16-byte segment s at position s ^ swz(r), so that the
+// fragment reads of 16 consecutive rows fall on distinct bank groups.
+constexpr int kDigitRow = 64;                            // LDS bytes per staged row
 constexpr int kDigitPlane = kGemmSplitRows * kDigitRow;  // one digit plane of a chunk
+constexpr int kDigitBuffers = 2;  // loads run kDigitBuffers - 1 chunks ahead
 
 __host__ __device__ constexpr size_t digits_lds(int la, int lb)
 {
-    return (size_t)2 * (la + lb) * kDigitPlane;
+    return (size_t)kDigitBuffers * (la + lb) * kDigitPlane;
 }
+
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
 // FS > 0: the data planes hold split words (FS digits of the low field, then
 // FS of the high field, weights 256^a and 2^l 256^a): every pair accumulates
@@ -81,27 +90,35 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
     const int64_t R0 = (int64_t)blockIdx.y * kGemmSplitRows, C0 = (int64_t)blockIdx.x * kGemmSplitCols;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
-    // staging: thread tid copies 16 bytes (segment sg) of row / column sr of every plane.
-    // The 16 lanes of one LDS write pass take rows 4 apart (j = 4k + i -> row
-    // (k & 3) + 4 i + 16 (k >> 2)): with 80-byte rows their 16-byte pieces
-    // then fall on 16 distinct groups of 4 banks.
-    const int sj = tid >> 2, sk = sj >> 2;
-    const int sr = (sk & 3) + 4 * (sj & 3) + 16 * (sk >> 2), sg = (tid & 3) * 16;
-    const unsigned char *ga = job.a[blockIdx.z] + (R0 + sr) * Pp + sg;
-    const unsigned char *gb = w.b + (C0 + sr) * Pp + sg;
-    const int soff = sr * kDigitRow + sg;
-    fk::v4i st[NP];
-    auto fetch = [&](int64_t kc) {
+    // Staging: wave v fills rows 16 v .. 16 v + 15 of every plane, one 1 KB
+    // direct load per plane; its lane i lands at LDS position i of that
+    // kilobyte (row 16 v + i / 4, position i % 4) and so fetches segment
+    // (i % 4) ^ swz(row) of that row.
+    const int sr = 16 * wave + (lane >> 2);
+    const int sseg = 16 * ((lane & 3) ^ swz(sr));
+    const unsigned char *ga = job.a[blockIdx.z] + (R0 + sr) * Pp + sseg;
+    const unsigned char *gb = w.b + (C0 + sr) * Pp + sseg;
+    typedef __attribute__((address_space(3))) void lds_t;
+    auto issue = [&](int64_t c) {
+        unsigned char *buf = smem + (c % kDigitBuffers) * NP * kDigitPlane + wave * 1024;
+        const int64_t kc = c * kGemmK;
 #pragma unroll
-        for (int a = 0; a < LA; ++a) st[a] = *(gcv4i_t *)(ga + a * aplane + kc);
+        for (int a = 0; a < LA; ++a)
+            __builtin_amdgcn_global_load_lds((const void *)(ga + a * aplane + kc),
+                                             (lds_t *)(buf + a * kDigitPlane), 16, 0, 0);
 #pragma unroll
-        for (int b = 0; b < LB; ++b) st[LA + b] = *(gcv4i_t *)(gb + b * bplane + kc);
+        for (int b = 0; b < LB; ++b)
+            __builtin_amdgcn_global_load_lds((const void *)(gb + b * bplane + kc),
+                                             (lds_t *)(buf + (LA + b) * kDigitPlane), 16, 0, 0);
     };
-    auto stage = [&](unsigned char *buf) {
+    // this lane's fragment offsets within a plane (row * 64 + swizzled segment)
+    int aoff[2], boff[2];
 #pragma unroll
-        for (int q = 0; q < NP; ++q)
-            *reinterpret_cast<fk::v4i *>(buf + q * kDigitPlane + soff) = st[q];
-    };
+    for (int t = 0; t < 2; ++t) {
+        const int ra = wr + 16 * t + fi, rb = wc + 16 * t + fi;
+        aoff[t] = ra * kDigitRow + 16 * (fh ^ swz(ra));
+        boff[t] = rb * kDigitRow + 16 * (fh ^ swz(rb));
+    }
     fk::v4i acc[2][2][S];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
@@ -110,29 +127,39 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
 #pragma unroll
             for (int s = 0; s < S; ++s) acc[rt][ct][s] = fk::v4i{0, 0, 0, 0};
     const int64_t nc = Pp / kGemmK;
-    if (nc > 0) {
-        fetch(0);
-        stage(smem);
-        __syncthreads();
-    }
+    constexpr int D = kDigitBuffers - 1;  // chunks in flight ahead
+    static_assert(D == 1 || D == 2, "prefetch depth");
+    if (nc > 0) issue(0);
+    if (D == 2 && nc > 1) issue(1);
     for (int64_t c = 0; c < nc; ++c) {
-        unsigned char *cur = smem + (c & 1) * NP * kDigitPlane;
-        unsigned char *nxt = smem + ((c + 1) & 1) * NP * kDigitPlane;
-        const bool more = c + 1 < nc;
-        if (more) fetch((c + 1) * kGemmK);  // in flight while this chunk's products run
+        // this wave's loads of chunk c have landed (with D = 2 those of chunk
+        // c + 1 may still be in flight: NP of them), then every wave's
+        if (D == 2 && c + 1 < nc)
+            __builtin_amdgcn_s_waitcnt(0xF70 | NP);  // vmcnt(NP), other counters untouched
+        else
+            __builtin_amdgcn_s_waitcnt(0xF70);       // vmcnt(0)
+        // Then the block barrier: every wave's chunk c is in LDS, and every
+        // wave is done reading buffer (c + D) % (D + 1) (chunk c - 1: its reads
+        // completed before its products, which precede the barrier). A bare
+        // barrier: the fence of __syncthreads would also wait for chunk
+        // c + 1's loads (direct loads count as pending LDS writes). The empty
+        // asm statements keep the compiler from moving LDS accesses across it.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (c + D < nc) issue(c + D);
+        const unsigned char *cur = smem + (c % kDigitBuffers) * NP * kDigitPlane;
         fk::v4i af[2][LA], bf[2][LB];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
             for (int a = 0; a < LA; ++a)
-                af[rt][a] = *reinterpret_cast<const fk::v4i *>(
-                    cur + a * kDigitPlane + (wr + 16 * rt + fi) * kDigitRow + 16 * fh);
+                af[rt][a] = *reinterpret_cast<const fk::v4i *>(cur + a * kDigitPlane + aoff[rt]);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int b = 0; b < LB; ++b)
-                bf[ct][b] = *reinterpret_cast<const fk::v4i *>(
-                    cur + (LA + b) * kDigitPlane + (wc + 16 * ct + fi) * kDigitRow + 16 * fh);
+                bf[ct][b] = *reinterpret_cast<const fk::v4i *>(cur + (LA + b) * kDigitPlane + boff[ct]);
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -146,10 +173,6 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
                                 __builtin_amdgcn_mfma_i32_16x16x64_i8(
                                     af[rt][a], bf[ct][b], acc[rt][ct][fk::acc_of<FS, LB>(a) + b],
                                     0, 0, 0);
-        // the other buffer was last read in the previous chunk, before the
-        // barrier that ended it
-        if (more) stage(nxt);
-        __syncthreads();
     }
     int64_t *d = job.d[blockIdx.z];
 #pragma unroll
