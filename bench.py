@@ -335,6 +335,7 @@ def main():
     if roof["bound"] == "mfma" and not args.only:
         line["roofline"]["mfma_ceiling"] = mfma_ceiling(torch, ne, stream, mfma_tops)
 
+    line["gpu"] = gpu_info(torch)
     if not args.no_cpu and args.config == "batched":
         line["cpu_baseline"] = cpu_baseline(groups, np)
     if args.config == "batched" and not args.only and not args.no_serving:
@@ -1061,6 +1062,24 @@ def _long(wl, args):
 
 
 CONFIGS = {"batched": _batched, "small": _small, "uneven": _uneven, "long": _long}
+
+
+def gpu_info(torch) -> dict:
+    """The device the line was measured on: name, architecture, compute units,
+    memory, and its clocks as rocm-smi reports them (if it is there)."""
+    import subprocess
+    p = torch.cuda.get_device_properties(0)
+    info = {"name": p.name, "arch": getattr(p, "gcnArchName", ""),
+            "compute_units": p.multi_processor_count, "memory_GiB": round(p.total_memory / 2**30, 1)}
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        card = next(iter(json.loads(r.stdout).values()))
+        info["clocks_rocm_smi"] = {k: v for k, v in card.items()
+                                   if any(c in k for c in ("sclk", "mclk", "fclk", "socclk"))}
+    except Exception:  # no rocm-smi, or output it cannot parse: the clocks stay out
+        pass
+    return info
 
 
 def cpu_model() -> str:

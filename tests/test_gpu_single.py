@@ -216,3 +216,34 @@ def test_single_launch_replay_reads_new_inputs():
         assert plan.flags() == 0
         check(devs)
     plan.close()
+
+
+@pytest.mark.parametrize("mode", ["entangled", "plain", "checksum"])
+def test_single_launch_32_bit_words(mode):
+    """Element-wise groups with 32-bit entangled words (int32 outputs) in one
+    launch: the gathers and inner products take 8 or 4 positions per lane
+    there (int32 stores of 16 bytes), every loss of a group of 3, and ragged
+    lengths; all equal the oracle."""
+    bits = 7
+    # (inner products short enough for D of w = 32: 64 * 64 * n <= D)
+    cases = [("perm", 3, 70001), ("perm", 4, 4097), ("perm", 6, 40003), ("inner", 3, 255),
+             ("inner", 8, 20001), ("scale", 3, 5001), ("add", 5, 3003)]
+    for lost in ((-1, 0, 1, 2) if mode != "plain" else (-1,)):
+        devs, refs = [], []
+        for i, (op, M, n) in enumerate(cases):
+            grp = group(op, M, n, 0, bits, seed=7600 + i)
+            c = [dev32(row) for row in grp.c]
+            operand = None if op == "scale" else dev32(grp.operand)
+            n_out = ne.n_out(op, n, 0 if grp.operand is None else grp.operand.size)
+            out = [torch.full((n_out,), 0x3C3C3C3C, dtype=torch.int32, device=DEV) for _ in range(M)]
+            r = lost if lost < M else -1
+            devs.append((ne.GroupSpec(op, c, operand, out, grp.scalar, r, bits, word_bits=32), out))
+            refs.append(oracle.apply(op, grp.c, grp.operand if op != "scale" else None, grp.scalar))
+        plan = ne.Plan([d[0] for d in devs], mode, single_launch=True)
+        plan.run()
+        torch.cuda.synchronize()
+        assert plan.flags() == 0
+        for (spec, out), ref, case in zip(devs, refs, cases):
+            got = np.stack([t.cpu().numpy() for t in out]).astype(np.int64)
+            assert np.array_equal(got, ref), (mode, lost, case)
+        plan.close()
