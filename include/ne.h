@@ -664,7 +664,10 @@ ne_status ne_plan_workspace_size(const ne_group *groups, int32_t n_groups, int32
 ne_status ne_plan_create_in(const ne_group *groups, int32_t n_groups, int32_t mode,
                             const ne_tuning *tuning, void *workspace, size_t workspace_bytes,
                             ne_stream stream, ne_plan **plan);
-/* Enqueue one run of the whole batch on `stream`. Allocates nothing. */
+/* Enqueue one run of the whole batch on `stream`. Allocates nothing. Runs of
+ * one plan must not overlap in time (issue them on one stream, or order them
+ * with events): they share the plan's accumulators, permutation rows and, with
+ * single_launch, its work queue and counters. Different plans are independent. */
 ne_status ne_plan_run(ne_plan *plan, ne_stream stream);
 /* Record one run into a hipGraph (by stream capture on `stream`); later
  * ne_plan_launch calls replay it as one graph launch. */
