@@ -280,8 +280,9 @@ ne_status ne_mfma_i8_peak(int32_t blocks, int64_t iters, int32_t varied, int32_t
  * its output. The caller orders the recovery after the other M-1 events.
  * The tasks are independent failure domains only on independent hardware
  * queues: HIP streams beyond the process's hardware queues
- * (GPU_MAX_HW_QUEUES, 4 by default) share one, and a slow task then delays
- * its queue-mates too.
+ * (GPU_MAX_HW_QUEUES, 4 by default, read when the runtime starts) share one,
+ * and a slow task then delays its queue-mates too; a process that sets it to
+ * at least M before its first HIP call gives every stream its own.
  * Errors: NE_EINVAL (M outside [1, NE_MAX_M], NULL arguments, negative
  * deadline), NE_ELATE (two or more streams late: more failures than one
  * redundant stream covers; *lost = -1), NE_EHIP (an event query failed).

@@ -3,6 +3,10 @@ runs as its own task on its own HIP stream; a stream delayed past the
 deadline (a slow core) is named lost by ne_wait_streams and recovery from
 the other M - 1 streams equals the CPU oracle. Every delay is bounded, and
 each test synchronizes before it ends."""
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 
@@ -94,3 +98,33 @@ def test_two_late_streams_exceed_what_one_redundant_stream_covers():
     k = wl.uniform_i32(g, -(1 << 9), 1 << 9, 9)
     status, got = run_tasks(c, k, slow=(0, 3))
     assert status == -8 and got is None
+
+
+# A child process whose runtime has one hardware queue per stream
+# (GPU_MAX_HW_QUEUES is read when the runtime starts): then a slow stream
+# delays no other, and the late one is named for M = 6 and 8 too.
+@pytest.mark.parametrize("M", [6, 8])
+def test_late_stream_is_identified_with_a_queue_per_stream(M):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GPU_MAX_HW_QUEUES=str(M),
+               PYTHONPATH=os.pathsep.join(p for p in (root, os.environ.get("PYTHONPATH")) if p))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), str(M)], env=env, cwd=root,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert f"M={M} ok" in r.stdout
+
+
+if __name__ == "__main__":
+    # the child of the test above: every stream slow in turn, and none
+    M = int(sys.argv[1])
+    g = wl.rng(8400 + M)
+    c = wl.uniform_i32(g, -(1 << 9), 1 << 9, (M, 20_011))
+    k = wl.uniform_i32(g, -(1 << 9), 1 << 9, 29)
+    ref = oracle.apply("conv", c, k)
+    for slow in list(range(M)) + [None]:
+        lost, got = run_tasks(c, k, slow=() if slow is None else (slow,))
+        expect = -1 if slow is None else slow
+        if lost != expect or not np.array_equal(got, ref):
+            print(f"M={M} slow={slow}: named {lost}", flush=True)
+            sys.exit(1)
+    print(f"M={M} ok", flush=True)
