@@ -59,6 +59,7 @@ struct GemmKernel {
     GemmLaunch fused;              // one pass, digits staged in LDS
     GemmSplitLaunch split;         // two phases through workspace
     GemmSplitLaunch split_fields;  // two phases, words split into two fields of LA / 2 digits
+    GemmLaunch fused_fields;       // one pass, words split into two fields of LA / 2 digits
 };
 // The variant for (kernel class, slots, LA, LB), or null if none is built
 // (a variant may hold only the split-word phase 1).

@@ -246,10 +246,10 @@ using namespace ne;
 namespace {
 
 // Argument checks and digit counts shared by the size query and the call.
-// dc: digits of the one-launch form; ds: of the two-phase form, which
-// splits words into two fields where that takes fewer planes.
+// Both forms split words into two fields where that takes fewer planes
+// (entangled and plain-same).
 ne_status gemm_shape(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q, int32_t in_bits,
-                     DigitCounts *dc, DigitCounts *ds)
+                     DigitCounts *dc)
 {
     if (mode < kEntangled || mode > kChecksum) return NE_EINVAL;
     const int minM = mode == kEntangled ? 3 : (mode == kChecksum ? 2 : 1);
@@ -258,8 +258,7 @@ ne_status gemm_shape(int32_t mode, int32_t M, int64_t N, int64_t P, int64_t Q, i
     if (in_bits > kGemmMaxBits) return NE_EUNSUP;
     if (N > (int64_t)kGemmTile * 65535 || Q > ((int64_t)1 << 26) || P > ((int64_t)1 << 24))
         return NE_EUNSUP;
-    *dc = conv_digits(mode, M, in_bits);
-    *ds = mode == kEntangled || mode == kPlainSame ? conv_digits(mode, M, in_bits, 64, true) : *dc;
+    *dc = conv_digits(mode, M, in_bits, 64, mode == kEntangled || mode == kPlainSame);
     return NE_OK;
 }
 
@@ -269,11 +268,11 @@ extern "C" ne_status ne_gemm_workspace_size(int32_t mode, int32_t M, int64_t N, 
                                             int64_t Q, int32_t in_bits, size_t *bytes)
 {
     if (!bytes) return NE_EINVAL;
-    DigitCounts dc{}, ds{};
-    const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc, &ds);
+    DigitCounts dc{};
+    const ne_status st = gemm_shape(mode, M, N, P, Q, in_bits, &dc);
     if (st != NE_OK) return st;
     const int nslots = mode == kChecksum ? M + 1 : M;
-    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, ds.la, ds.lb, N, P, Q,
+    *bytes = (N == 0 || Q == 0) ? 0 : gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q,
                                                        mode == kChecksum);
     return NE_OK;
 }
@@ -283,8 +282,8 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
                              int32_t lost, int32_t in_bits, void *workspace,
                              size_t workspace_bytes, uint32_t *flags, ne_stream stream)
 {
-    DigitCounts dc0{}, ds{};
-    const ne_status st0 = gemm_shape(mode, M, N, P, Q, in_bits, &dc0, &ds);
+    DigitCounts dc{};
+    const ne_status st0 = gemm_shape(mode, M, N, P, Q, in_bits, &dc);
     if (st0 != NE_OK) return st0;
     if (!c || !out) return NE_EINVAL;
     if (lost < -1 || lost >= M) return NE_EFAILIDX;
@@ -308,8 +307,6 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         const unsigned __int128 chk = mode == kChecksum ? bound * (unsigned)M : bound;
         if (chk > (((unsigned __int128)1 << 63) - 1)) return NE_ERANGE;
     }
-    // the two-phase form runs split words where the digit rule takes them
-    const DigitCounts dc = workspace ? ds : dc0;
     const int fs = dc.split ? dc.la / 2 : 0;
     // int32 accumulation: a digit product is at most 2^14, summed over the
     // padded inner dimension and at most min(digits of a field, lb) pairs per weight.
@@ -317,7 +314,10 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
     if (pp * std::min(fs ? fs : dc.la, dc.lb) * 16384 >= ((int64_t)1 << 31)) return NE_EUNSUP;
     const int nslots = mode == kChecksum ? M + 1 : M;
     const GemmKernel *kern = gemm_kernel(conv_class_of_mode(mode), nslots, dc.la, dc.lb);
-    if (!kern || (fs ? !kern->split_fields : !kern->fused)) return NE_EUNSUP;
+    if (!kern) return NE_EUNSUP;
+    const bool have = fs ? (workspace ? kern->split_fields != nullptr : kern->fused_fields != nullptr)
+                         : kern->fused != nullptr;
+    if (!have) return NE_EUNSUP;
     if (fs && (fs > 4 || dc.lb > 3)) return NE_EUNSUP;
     if (fs) l = dc.l;  // the field boundary (plain-same groups too)
     const size_t need = gemm_split_bytes(nslots, dc.la, dc.lb, N, P, Q, mode == kChecksum);
@@ -396,7 +396,7 @@ extern "C" ne_status ne_gemm(int32_t mode, int32_t M, int64_t N, int64_t P, int6
         }
         e = hipGetLastError();
     } else {
-        e = kern->fused(a, (hipStream_t)stream);
+        e = fs ? kern->fused_fields(a, (hipStream_t)stream) : kern->fused(a, (hipStream_t)stream);
     }
     return e == hipSuccess ? NE_OK : hip_fail(e);
 }

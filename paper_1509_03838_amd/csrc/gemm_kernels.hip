@@ -110,12 +110,18 @@ __device__ __forceinline__ void put_fields8(const int32_t (&cur)[8], const int32
     put_bytes8<2 * FS>(u, dst, stride);
 }
 
-template <int LA, int LB, int NS, int KCLASS>
+// FS > 0: words split at bit l into two fields of FS digits (LA = 2 FS;
+// entangled and plain-same classes): planes 0 .. FS-1 hold the low field,
+// FS .. LA-1 the high one, and every pair accumulates into its field's
+// weight; y = lo-sum + 2^l hi-sum.
+template <int LA, int LB, int NS, int KCLASS, int FS = 0>
 __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
 {
     constexpr int mode = KCLASS == 0 ? kEntangled : (KCLASS == 2 ? kChecksum : kPlain);
     constexpr int M = KCLASS == 2 ? NS - 1 : NS;  // data blocks
-    constexpr int S = (LA + LB - 1) < 8 ? (LA + LB - 1) : 8;
+    static_assert(FS == 0 || (2 * FS == LA && KCLASS != 2), "split words");
+    constexpr int SL = FS + LB - 1;
+    constexpr int S = FS ? 2 * SL : ((LA + LB - 1) < 8 ? (LA + LB - 1) : 8);
     constexpr int T = kGemmTile, R = kGemmRow;
     constexpr int PLANE = T * R;  // bytes of one digit plane of the tile
     static_assert(M >= 1 && M <= kFusedMaxM, "slot count");
@@ -164,7 +170,11 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
                 load_row8(G->c[t] + arow * P + kc + ak, full, vec, arow_ok, kleft, cur);
 #pragma unroll
                 for (int i = 0; i < 8; i += 2) bd.add2(cur[i], cur[i + 1]);
-                if (t != skip || mode == kEntangled) {
+                if constexpr (FS > 0) {
+                    if (t != skip)
+                        put_fields8<FS>(cur, prev, mode == kEntangled, l,
+                                        sa + ((size_t)t * LA * T + ar) * R + ak, PLANE);
+                } else if (t != skip || mode == kEntangled) {
                     int64_t x[8];
 #pragma unroll
                     for (int i = 0; i < 8; ++i) {
@@ -220,9 +230,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
             for (int b = 0; b < LB; ++b)
 #pragma unroll
                 for (int a = 0; a < LA; ++a)
-                    if (a + b < 8)
-                        acc[t][a + b] =
-                            __builtin_amdgcn_mfma_i32_16x16x64_i8(af[a], bf[b], acc[t][a + b], 0, 0, 0);
+                    if (pair_runs<FS>(a, b))
+                        acc[t][acc_of<FS, LB>(a) + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            af[a], bf[b], acc[t][acc_of<FS, LB>(a) + b], 0, 0, 0);
         }
     }
 
@@ -233,10 +243,21 @@ __global__ __launch_bounds__(kBlock) void k_gemm_fused(const GemmArgs args)
     for (int t = 0; t < NS; ++t) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            uint64_t y = (uint64_t)(int64_t)acc[t][S - 1][v];
+            if constexpr (FS > 0) {
+                uint64_t ylo = (uint64_t)(int64_t)acc[t][SL - 1][v];
+                uint64_t yhi = (uint64_t)(int64_t)acc[t][S - 1][v];
 #pragma unroll
-            for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[t][s][v];
-            dl[t][v] = (int64_t)y;
+                for (int s = SL - 2; s >= 0; --s) {
+                    ylo = (ylo << 8) + (uint64_t)(int64_t)acc[t][s][v];
+                    yhi = (yhi << 8) + (uint64_t)(int64_t)acc[t][SL + s][v];
+                }
+                dl[t][v] = (int64_t)(ylo + (yhi << l));
+            } else {
+                uint64_t y = (uint64_t)(int64_t)acc[t][S - 1][v];
+#pragma unroll
+                for (int s = S - 2; s >= 0; --s) y = (y << 8) + (uint64_t)(int64_t)acc[t][s][v];
+                dl[t][v] = (int64_t)y;
+            }
         }
     }
     const int64_t orow = r0 + wr + 4 * fh, ocol = c0 + wc + fi;
@@ -356,10 +377,10 @@ hipError_t launch_split(const GemmArgs &a, const GemmSplit &w, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int LA, int LB, int NS>
+template <int LA, int LB, int NS, int FS = 0>
 hipError_t launch_one(const GemmArgs &a, hipStream_t s)
 {
-    void (*k)(const GemmArgs) = &fk::k_gemm_fused<LA, LB, NS, NE_KCLASS>;
+    void (*k)(const GemmArgs) = &fk::k_gemm_fused<LA, LB, NS, NE_KCLASS, FS>;
     const size_t lds = gemm_lds(NS, LA, LB);
     if (lds > 64 * 1024) {
         static const hipError_t e = hipFuncSetAttribute(
@@ -379,11 +400,15 @@ constexpr GemmKernel launcher()
                           gemm_lds(NS, LA, LB) <= 160 * 1024;
     constexpr bool split = LA % 2 == 0 && gemm_split_needed(NE_KCLASS, NS, LA, LB, kGemmMaxBits);
     GemmSplitLaunch sf = nullptr;
-    if constexpr (split) sf = &launch_split<LA, LB, NS, LA / 2>;
+    GemmLaunch ff = nullptr;
+    if constexpr (split) {
+        sf = &launch_split<LA, LB, NS, LA / 2>;
+        if constexpr (gemm_lds(NS, LA, LB) <= 160 * 1024) ff = &launch_one<LA, LB, NS, LA / 2>;
+    }
     if constexpr (conv)
-        return GemmKernel{&launch_one<LA, LB, NS>, &launch_split<LA, LB, NS>, sf};
+        return GemmKernel{&launch_one<LA, LB, NS>, &launch_split<LA, LB, NS>, sf, ff};
     else
-        return GemmKernel{nullptr, nullptr, sf};
+        return GemmKernel{nullptr, nullptr, sf, ff};
 }
 
 template <int NS>
@@ -419,7 +444,7 @@ const GemmKernel *pick(int la, int lb)
 {
     static constexpr Row<NS> r = row<NS>();
     const GemmKernel *k = &r.f[la - 1][lb - 1];
-    return (k->fused || k->split_fields) ? k : nullptr;
+    return (k->fused || k->split_fields || k->fused_fields) ? k : nullptr;
 }
 
 }  // namespace
