@@ -139,9 +139,10 @@ struct alignas(16) Task {
 };
 constexpr int kSingleLayoutSteps = 64;  // 64K positions per layout item of the single launch
 constexpr int kSingleMinSteps = 4;      // shortest strip of a single-launch item, in steps
-// Positions per lane and step of an element-wise item of the single launch:
-// gathers and inner products take twice the per-variant kernel's.
-__host__ __device__ constexpr int single_stream_positions(int op, int slots)
+// Positions per lane and step of the element-wise kernel of an operation:
+// gathers and inner products take twice stream_positions (more loads in
+// flight: their loads are random rows, or they accumulate instead of store).
+__host__ __device__ constexpr int stream_positions_of(int op, int slots)
 {
     return stream_positions(slots) * ((op == NE_OP_INNER || op == NE_OP_PERM) ? 2 : 1);
 }

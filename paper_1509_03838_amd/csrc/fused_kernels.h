@@ -963,8 +963,8 @@ __global__ __launch_bounds__(kBlock) void k_interleave(const GroupDev *__restric
 // Items are taken in plain block order (no per-XCD runs): neighbouring
 // blocks then work on the same group at the same time, so a permutation's
 // random gathers fall into a working set the memory-side cache holds.
-// VX: a multiple of the positions per lane (the single launch gives its
-// gathers and inner products twice as many, for more loads in flight).
+// VX: a multiple of stream_positions(NS) per lane (stream_positions_of: 2
+// for gathers and inner products, for more loads in flight).
 template <int OP, int KCLASS, int NS, int VX = 1>
 __device__ __forceinline__ void stream_item(const GroupDev *__restrict__ groups, const Item it,
                                             uint32_t *flags)
@@ -1193,14 +1193,14 @@ __device__ __forceinline__ void stream_item(const GroupDev *__restrict__ groups,
     if (flag) atomicOr(flags, flag);
 }
 
-template <int OP, int KCLASS, int NS>
+template <int OP, int KCLASS, int NS, int VX = 1>
 __global__ __launch_bounds__(kBlock) void k_stream_fused(const GroupDev *__restrict__ groups,
                                                          const Item *__restrict__ items,
                                                          uint32_t nitems, uint32_t *flags)
 {
     const uint32_t ii = blockIdx.x;
     if (ii >= nitems) return;
-    stream_item<OP, KCLASS, NS>(groups, items[ii], flags);
+    stream_item<OP, KCLASS, NS, VX>(groups, items[ii], flags);
 }
 
 // Recovery of one group's inner products (one output per stream) from its

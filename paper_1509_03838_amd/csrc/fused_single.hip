@@ -137,8 +137,7 @@ __device__ __forceinline__ void stream_body(const GroupDev *groups, const Item i
             }
             __syncthreads();
         }
-        // gathers and inner products: twice the positions per lane
-        constexpr int VX = (OP == NE_OP_PERM || OP == NE_OP_INNER) ? 2 : 1;
+        constexpr int VX = stream_positions_of(OP, NS) / stream_positions(NS);
         fk::stream_item<OP, NE_KCLASS, NS, VX>(groups, it, flags);
         if constexpr (OP == NE_OP_PERM) {
             __syncthreads();  // every wave's gathers are done

@@ -22,8 +22,9 @@ template <int OP, int NS>
 void launch_one(const GroupDev *g, const Item *items, uint32_t nitems, uint32_t *flags,
                 hipStream_t s)
 {
-    hipLaunchKernelGGL((fk::k_stream_fused<OP, NE_KCLASS, NS>), dim3(nitems), dim3(fk::kBlock), 0,
-                       s, g, items, nitems, flags);
+    constexpr int VX = stream_positions_of(OP, NS) / stream_positions(NS);
+    hipLaunchKernelGGL((fk::k_stream_fused<OP, NE_KCLASS, NS, VX>), dim3(nitems), dim3(fk::kBlock),
+                       0, s, g, items, nitems, flags);
 }
 
 template <int OP, int NS>

@@ -376,7 +376,7 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
         } else {
             // element-wise kernel: kStreamV* positions per lane, `stream_steps` steps
             G.steps = g_stream_steps;
-            const int64_t strip = (int64_t)g_stream_steps * 256 * stream_positions(G.nslots);
+            const int64_t strip = (int64_t)g_stream_steps * 256 * stream_positions_of(u.op, G.nslots);
             // (the outer product's lanes run over its n K outputs)
             const int64_t nit = u.op == NE_OP_OUTER ? n_out : u.n;
             const int64_t nstrips = (nit + strip - 1) / strip;
@@ -387,12 +387,8 @@ static ne_status plan_build(const ne_group *groups, int32_t n_groups, int32_t mo
                      u.op != NE_OP_PERM) ||
                     G.nslots < single_slots_lo(kclass) || G.nslots > single_slots_hi(kclass))
                     return fail(NE_EUNSUP);
-                // strips of the single launch's positions per lane; an inner
-                // product's last item recovers it: at least one item
-                const int64_t sstrip =
-                    (int64_t)g_stream_steps * 256 * single_stream_positions(u.op, G.nslots);
-                const int64_t sn = (nit + sstrip - 1) / sstrip;
-                const int64_t nt = u.op == NE_OP_INNER ? std::max<int64_t>(sn, 1) : sn;
+                // an inner product's last item recovers it: at least one item
+                const int64_t nt = u.op == NE_OP_INNER ? std::max<int64_t>(nstrips, 1) : nstrips;
                 const uint32_t kind = task_kind(kTaskStream, G.nslots, u.op, 0, 0, 0, 0);
                 auto &dst = u.op == NE_OP_PERM ? t_perm : t_stream;
                 for (int64_t s = 0; s < nt; ++s) dst.push_back(Task{kind, (uint32_t)gi, (uint32_t)s, 0});
