@@ -1021,13 +1021,18 @@ def serve_line(args, wl):
 def tuned_summary(tuned, mode):
     """The autotuner's choices for the timed mode: the table itself when it
     is short, else a histogram {steps: classes}."""
-    mine = {k: v for k, v in tuned.items() if k.startswith(mode + "|")}
+    mine = {k: v for k, v in tuned.items() if k.startswith(mode + "|") and "|plan|" not in k}
+    whole = [v for k, v in tuned.items() if k.startswith(mode + "|plan|")]
     if len(mine) <= 8:
-        return mine
-    hist = {}
-    for v in mine.values():
-        hist[str(v)] = hist.get(str(v), 0) + 1
-    return {"classes": len(mine), "steps_histogram": hist}
+        out = dict(mine)
+    else:
+        hist = {}
+        for v in mine.values():
+            hist[str(v)] = hist.get(str(v), 0) + 1
+        out = {"classes": len(mine), "steps_histogram": hist}
+    if whole:
+        out["whole_plan"] = whole[-1]  # tuned choices kept, or the planner's defaults
+    return out
 
 
 def stats_kernel_name(stats, groups, mode):

@@ -15,9 +15,16 @@ later processes) reuse the choice without timing.
 Class key: convolution (mode, M, in_bits, 32-bit words or not, K bucket, n bucket); element-wise
 (mode, op, M <= 4 or not, n bucket); K buckets are powers of two, n buckets
 powers of four.
+
+A batch of several classes is then checked whole: classes timed alone do
+not share the device, and a batch's launches do (on parallel graph
+branches), so the tuned choices are kept only if the whole plan runs faster
+with them than with the planner's defaults; the verdict is cached under the
+batch's set of classes.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Sequence
@@ -56,6 +63,12 @@ def _fits(spec, mode: str) -> bool:
         return True
     except ne.NeError:
         return False
+
+
+def plan_key(classes, mode: str) -> str:
+    """Cache key of a batch's whole-plan verdict: its set of class keys."""
+    h = hashlib.sha256("\n".join(sorted(classes)).encode()).hexdigest()[:16]
+    return f"{mode}|plan|{h}"
 
 
 def _choice(v):
@@ -100,9 +113,12 @@ class Tuner:
         for sp in specs:
             sp.steps, sp.ring_waves = choice
 
-    def _time(self, specs: Sequence[ne.GroupSpec], mode: str, choice) -> float:
+    def _time(self, specs: Sequence[ne.GroupSpec], mode: str, choice=None) -> float:
+        """Milliseconds per run of a plan over specs, with choice applied to
+        all of them first (None: as they are set)."""
         import torch
-        self._apply(specs, choice)
+        if choice is not None:
+            self._apply(specs, choice)
         try:
             plan = ne.Plan(specs, mode)
         except ne.NeError:
@@ -124,7 +140,8 @@ class Tuner:
     def tune(self, specs: Sequence[ne.GroupSpec], mode: str = "entangled") -> dict:
         """Sets `steps` (and, for convolutions, `ring_waves`) on every spec,
         timing the classes not cached yet, and returns the class -> choice
-        table used."""
+        table used (with several classes, also the whole-plan verdict under
+        plan_key: "tuned" or "planner defaults")."""
         classes: dict[str, list[ne.GroupSpec]] = {}
         for sp in specs:
             classes.setdefault(class_key(sp, mode), []).append(sp)
@@ -152,11 +169,27 @@ class Tuner:
                 s.steps, s.ring_waves = v
             self.cache[key] = min(times, key=times.get)
             changed = True
-        if changed:
-            self.save()
         for key, members in classes.items():
             self._apply(members, self.cache[key])
             for s in members:
                 if s.ring_waves == 1 and not _fits(s, mode):
                     s.ring_waves = 0  # the planner takes the layout that fits
-        return {k: self.cache[k] for k in classes}
+        if len(classes) > 1:
+            # the whole batch: tuned choices against the planner's defaults
+            pkey = plan_key(classes, mode)
+            if pkey not in self.cache:
+                tuned = [(s.steps, s.ring_waves) for s in specs]
+                t_tuned = min(self._time(specs, mode) for _ in range(self.rounds))
+                t_default = min(self._time(specs, mode, (0, 0)) for _ in range(self.rounds))
+                for s, v in zip(specs, tuned):
+                    s.steps, s.ring_waves = v
+                self.cache[pkey] = (1 if t_default < 0.99 * t_tuned else 0, 0)
+                changed = True
+            if self.cache[pkey][0] == 1:
+                self._apply(specs, (0, 0))
+        if changed:
+            self.save()
+        table = {k: self.cache[k] for k in classes}
+        if len(classes) > 1:
+            table[pkey] = "planner defaults" if self.cache[pkey][0] == 1 else "tuned"
+        return table

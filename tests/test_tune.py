@@ -69,6 +69,22 @@ def test_cached_per_wave_ring_falls_back_where_it_does_not_fit(tmp_path, monkeyp
     assert [(s.steps, s.ring_waves) for s in sp] == [(4, 1), (4, 0)]
 
 
+@pytest.mark.parametrize("verdict", [0, 1])
+def test_whole_plan_verdict_from_the_cache(tmp_path, verdict):
+    """A batch of several classes: the cached whole-plan verdict keeps the
+    classes' choices (0) or gives every group the planner's defaults (1)."""
+    sp = [spec("conv", 3, 1 << 20, 64), spec("scale", 5, 4096)]
+    keys = [tune.class_key(s, "entangled") for s in sp]
+    t = tune.Tuner(str(tmp_path / "t.json"))
+    t.cache = {keys[0]: (8, 1), keys[1]: (2, 0),
+               tune.plan_key(dict.fromkeys(keys), "entangled"): (verdict, 0)}
+    table = t.tune(sp, "entangled")
+    want = [(0, 0), (0, 0)] if verdict else [(8, 1), (2, 0)]
+    assert [(s.steps, s.ring_waves) for s in sp] == want
+    assert table[tune.plan_key(dict.fromkeys(keys), "entangled")] == (
+        "planner defaults" if verdict else "tuned")
+
+
 def test_cache_reads_bare_step_counts(tmp_path):
     path = tmp_path / "old.json"
     path.write_text(json.dumps({"steps": {"entangled|scale|M<=4|n6": 4}}))
@@ -100,7 +116,10 @@ def test_tuned_plan_is_bit_identical(tmp_path):
     ne.Plan(s1).run()
     s2 = specs(o2)
     table = tune.Tuner(str(tmp_path / "c.json")).tune(s2)
-    assert all(v in tune.CONV_CANDIDATES + tune.STREAM_CANDIDATES for v in table.values())
+    verdicts = {k: v for k, v in table.items() if "|plan|" in k}
+    assert list(verdicts.values()) in (["tuned"], ["planner defaults"])  # several classes
+    assert all(v in tune.CONV_CANDIDATES + tune.STREAM_CANDIDATES
+               for k, v in table.items() if k not in verdicts)
     ne.Plan(s2).run()
     torch.cuda.synchronize()
     for a, b in zip(o1, o2):
