@@ -410,6 +410,35 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
                          size_t workspace_bytes, ne_stream stream);
 
 /*
+ * The whole method on a series (Sec. II: entangle once, the operators one
+ * after another, extract once): entangle the M int32 streams c with l of
+ * ne_params(M, 64), run the series on every stream but `lost` (-1: none
+ * lost, every stream runs), extract and recover all M outputs into dhat
+ * (int64, n_out each):
+ *     dhat[m] = (...((c[m] op_0 g_0) op_1 g_1) ...) op_{n_ops-1} g_{n_ops-1}.
+ * Stages as in ne_chain_apply; in addition the entanglement is done on load
+ * by the first stage when it is a run of element-wise operations (or a
+ * permutation), and the recovery by the last stage when it is one (the
+ * whole series in one pass when it is a single such run); otherwise they
+ * are passes of their own. Operands as for ne_chain_apply (add and sub:
+ * entangled int64 words, ne_entangle_operand). The range is the caller's
+ * promise (ne_chain_check). Workspace: ne_chain_run_workspace_size bytes,
+ * 256-byte aligned device memory (NULL when that size is 0). dhat must not
+ * overlap c, the operands or the workspace. Launches on `stream` only, no
+ * allocation; a permutation index outside [0, n) raises NE_FLAG_PERM_INDEX
+ * (ne_device_flags) and reads nothing.
+ * Errors: NE_EINVAL (M outside [3, NE_MAX_M], a wrong n_out, NULL pointers,
+ * a missing, small or misaligned workspace, and as ne_chain_workspace_size),
+ * NE_EFAILIDX (lost outside [-1, M)), NE_EUNSUP (unknown op), NE_ERANGE (no
+ * admissible l for M at w = 64).
+ */
+ne_status ne_chain_run_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                      int32_t n_ops, size_t *bytes);
+ne_status ne_chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
+                       int32_t n_ops, int32_t lost, int64_t *const *dhat, int64_t n_out,
+                       void *workspace, size_t workspace_bytes, ne_stream stream);
+
+/*
  * For callers that cannot allocate device memory (code under hipGraph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * series as ne_chain_apply, with the intermediates in a fixed buffer that

@@ -4,7 +4,9 @@
 // ne_chain_apply_noalloc, in a fixed device buffer of the library's own).
 // A stage is one operation on the per-step kernels of ne_lsb_apply, or a
 // run of element-wise operations (led, optionally, by a permutation) fused
-// into one pass over the entangled words.
+// into one pass over the entangled words. ne_chain_run adds the
+// entanglement and the recovery, fused into the first and the last run of
+// element-wise operations where the series begins or ends with one.
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
@@ -169,23 +171,6 @@ unsigned char *scratch_address(ne_status *st)
 
 // ------------------------------------------------ fused element-wise runs
 
-// A run of consecutive element-wise operations of a series (scale, add, sub,
-// mul), optionally led by a permutation, applied in one pass over the
-// entangled words: out[i] = op_k( ... op_1(in[p[i]] or in[i]) ...).
-constexpr int kMaxSegmentOps = 8;
-struct SegmentOp {
-    int32_t op;
-    int32_t pad_;
-    const void *g;  // NE_OP_ADD / NE_OP_SUB: words of the stream width; NE_OP_MUL: int32
-    int64_t s;      // NE_OP_SCALE
-};
-struct Segment {
-    int32_t nops;
-    int32_t perm;          // 1: gather at p[i] first
-    const int32_t *p;
-    SegmentOp ops[kMaxSegmentOps];
-};
-
 inline bool elementwise(int32_t op)
 {
     return op == NE_OP_SCALE || op == NE_OP_ADD || op == NE_OP_SUB || op == NE_OP_MUL;
@@ -198,31 +183,48 @@ template <typename W, typename In, typename Out>
 __global__ __launch_bounds__(256) void k_segment(In x, Out y, int64_t n, Segment seg,
                                                  uint32_t *err)
 {
-    using U = typename std::make_unsigned<W>::type;
     const W *xs = x.p[blockIdx.y];
     W *ys = y.p[blockIdx.y];
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * 256) {
-        U v;
+        W v = 0;
         if (seg.perm) {
             const int64_t src = seg.p[i];
             const bool ok = src >= 0 && src < n;
             bad |= !ok;
-            v = ok ? (U)xs[src] : (U)0;
+            if (ok) v = xs[src];
         } else {
-            v = (U)xs[i];
+            v = xs[i];
         }
-        for (int k = 0; k < seg.nops; ++k) {
-            const SegmentOp &o = seg.ops[k];
-            switch (o.op) {
-            case NE_OP_SCALE: v = v * (U)o.s; break;
-            case NE_OP_ADD: v = v + (U)((const W *)o.g)[i]; break;
-            case NE_OP_SUB: v = v - (U)((const W *)o.g)[i]; break;
-            default: v = v * (U)(W)((const int32_t *)o.g)[i]; break;  // NE_OP_MUL
+        ys[i] = segment_ops<W>(v, seg, i);
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
+// The first run of a series with the entanglement on load: stream y's words
+// are c_m + 2^l c_{m-1} (cc.p[y], cp.p[y]) from the int32 inputs.
+__global__ __launch_bounds__(256) void k_segment_entangle(PtrsI32 cc, PtrsI32 cp, PtrsI64 y,
+                                                          int64_t n, Segment seg, int l,
+                                                          uint32_t *err)
+{
+    const int32_t *xc = cc.p[blockIdx.y], *xp = cp.p[blockIdx.y];
+    int64_t *ys = y.p[blockIdx.y];
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        int64_t src = i;
+        if (seg.perm) {
+            src = seg.p[i];
+            if (src < 0 || src >= n) {
+                bad = true;
+                src = -1;
             }
         }
-        ys[i] = (W)v;
+        const int64_t v = src < 0 ? 0
+                                  : (int64_t)((uint64_t)(int64_t)xc[src] +
+                                              ((uint64_t)(int64_t)xp[src] << l));
+        ys[i] = segment_ops<int64_t>(v, seg, i);
     }
     if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
 }
@@ -301,6 +303,48 @@ struct Words32 {
     }
 };
 
+// The stages of a series: a run of element-wise operations (led, optionally,
+// by a permutation; at most kMaxSegmentOps) is one stage, every other
+// operation a stage of its own. Stage k is ops [i, j) on n_in samples.
+struct Stage {
+    int32_t i, j;
+    bool seg;
+    int64_t n_in, n_out;
+};
+
+int split_stages(const ne_chain_op *ops, int32_t n_ops, int64_t n_in, Stage *out)
+{
+    int ns = 0;
+    int64_t n = n_in;
+    for (int32_t i = 0; i < n_ops;) {
+        const ne_chain_op &o = ops[i];
+        int32_t j = i + 1;
+        const bool seg = o.op == NE_OP_PERM || elementwise(o.op);
+        if (seg)
+            while (j < n_ops && j - i < kMaxSegmentOps && elementwise(ops[j].op)) ++j;
+        int64_t m = n;
+        for (int32_t k = i; k < j; ++k) m = stage_out(ops[k], m);
+        out[ns++] = Stage{i, j, seg, n, m};
+        n = m;
+        i = j;
+    }
+    return ns;
+}
+
+Segment make_segment(const ne_chain_op *ops, const Stage &g)
+{
+    Segment seg{};
+    seg.perm = ops[g.i].op == NE_OP_PERM;
+    seg.p = seg.perm ? (const int32_t *)ops[g.i].operand : nullptr;
+    for (int32_t k = g.i + seg.perm; k < g.j; ++k) {
+        SegmentOp &so = seg.ops[seg.nops++];
+        so.op = ops[k].op;
+        so.g = ops[k].operand;
+        so.s = ops[k].scalar;
+    }
+    return seg;
+}
+
 template <typename T>
 ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
                   const ne_chain_op *ops, int32_t n_ops, typename T::W *const *delta,
@@ -348,48 +392,142 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
     }
     hipStream_t s = (hipStream_t)stream;
     unsigned char *ws = (unsigned char *)workspace;
-    int64_t n = n_in;
-    // Stages: a run of element-wise operations (led, optionally, by a
-    // permutation) is one pass; every other operation is a pass of its own.
     // Stage k writes workspace buffer (k & 1), the last one delta.
-    int stage = 0;
-    for (int32_t i = 0; i < n_ops;) {
-        const ne_chain_op &o = ops[i];
-        int32_t j = i + 1;  // the stage is ops [i, j)
-        if (o.op == NE_OP_PERM || elementwise(o.op))
-            while (j < n_ops && j - i < kMaxSegmentOps && elementwise(ops[j].op)) ++j;
-        int64_t m = n;
-        for (int32_t k = i; k < j; ++k) m = stage_out(ops[k], m);
+    Stage stages[kMaxChainOps];
+    const int ns = split_stages(ops, n_ops, n_in, stages);
+    for (int k = 0; k < ns; ++k) {
+        const Stage &g = stages[k];
         typename T::Out dst{};
-        if (j == n_ops) {
+        if (k == ns - 1) {
             dst = fin;
         } else {
             for (int t = 0; t < count; ++t)
-                dst.p[t] = (W *)(ws + ((size_t)(stage & 1) * M + t) * plane);
+                dst.p[t] = (W *)(ws + ((size_t)(k & 1) * M + t) * plane);
         }
-        if (m > 0) {
-            if (j - i == 1 && !(o.op == NE_OP_PERM || elementwise(o.op))) {
-                st = T::launch(o, count, n, cur, dst, m, s);
-            } else {
-                Segment seg{};
-                seg.perm = o.op == NE_OP_PERM;
-                seg.p = seg.perm ? (const int32_t *)o.operand : nullptr;
-                for (int32_t k = i + seg.perm; k < j; ++k) {
-                    SegmentOp &so = seg.ops[seg.nops++];
-                    so.op = ops[k].op;
-                    so.g = ops[k].operand;
-                    so.s = ops[k].scalar;
-                }
-                st = T::segment(seg, count, n, cur, dst, s);
-            }
+        if (g.n_out > 0) {
+            if (g.seg)
+                st = T::segment(make_segment(ops, g), count, g.n_in, cur, dst, s);
+            else
+                st = T::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
             if (st != NE_OK) return st;
         }
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
-        n = m;
-        i = j;
-        ++stage;
     }
     return NE_OK;
+}
+
+// ------------------------------------------------ the whole method on a series
+
+// Workspace of ne_chain_run: two buffers of M planes, each as long as the
+// longest intermediate -- every stage's output but the last, and the
+// entangled inputs when the first stage cannot entangle them on load -- or
+// nothing when the series is one run of element-wise operations.
+ne_status run_workspace(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
+                        size_t *bytes)
+{
+    int64_t longest = 0;
+    const ne_status st = walk(n_in, ops, n_ops, nullptr, &longest);
+    if (st != NE_OK) return st;
+    Stage stages[kMaxChainOps];
+    const int ns = split_stages(ops, n_ops, n_in, stages);
+    if (!stages[0].seg) longest = std::max(longest, n_in);
+    const bool need = ns > 1 || !stages[0].seg;
+    *bytes = need ? 2 * (size_t)M * align_up((size_t)longest * sizeof(int64_t)) : 0;
+    return NE_OK;
+}
+
+// Entangle, run the series on every computed stream, extract and recover.
+// Computed streams in slot order: slot t is stream (r + 1 + t) mod M, the
+// order recovery reads (slot M - 1, stream r, only when nothing was lost).
+ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
+                    int32_t n_ops, int32_t lost, int64_t *const *dhat, int64_t n_out,
+                    void *workspace, size_t workspace_bytes, ne_stream stream)
+{
+    if (M < 3 || M > kMaxM || !c || !dhat) return NE_EINVAL;
+    if (lost < -1 || lost >= M) return NE_EFAILIDX;
+    int64_t want = 0;
+    ne_status st = walk(n_in, ops, n_ops, &want, nullptr);
+    if (st != NE_OK) return st;
+    if (n_out != want) return NE_EINVAL;
+    for (int32_t i = 0; i < n_ops; ++i) {
+        const ne_chain_op &o = ops[i];
+        const bool needs = o.op == NE_OP_CONV || (o.op != NE_OP_SCALE && o.n_operand > 0);
+        if (needs && !o.operand) return NE_EINVAL;
+    }
+    for (int m = 0; m < M; ++m)
+        if ((!c[m] && n_in > 0) || (!dhat[m] && n_out > 0)) return NE_EINVAL;
+    int32_t l = 0;
+    if (ne_params(M, 64, &l, nullptr, nullptr) != NE_OK) return NE_ERANGE;
+    size_t need = 0;
+    st = run_workspace(M, n_in, ops, n_ops, &need);
+    if (st != NE_OK) return st;
+    if (need > 0 && (!workspace || workspace_bytes < need || (uintptr_t)workspace % kWsAlign))
+        return NE_EINVAL;
+    if (n_out == 0) return NE_OK;
+
+    Stage stages[kMaxChainOps];
+    const int ns = split_stages(ops, n_ops, n_in, stages);
+    const int r = lost >= 0 ? lost : 0;
+    const int count = lost >= 0 ? M - 1 : M;  // computed streams
+    PtrsI32 cc{}, cp{};
+    PtrsI64 out{};
+    for (int t = 0; t < M; ++t) {
+        const int m = (r + 1 + t) % M;
+        cc.p[t] = c[m];
+        cp.p[t] = c[(m + M - 1) % M];
+        out.p[t] = dhat[m];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *err = device_flag_word();
+    const size_t plane = need / (2 * (size_t)M);
+    unsigned char *ws = (unsigned char *)workspace;
+    auto buffer = [&](int b) {
+        PtrsI64 p{};
+        for (int t = 0; t < count; ++t) p.p[t] = (int64_t *)(ws + ((size_t)b * M + t) * plane);
+        return p;
+    };
+    auto grid = [](int64_t n) {
+        const int64_t g = (n + 255) / 256;
+        return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+    };
+    PtrsCI64 cur{};
+    if (!stages[0].seg) {
+        // a first stage that cannot entangle on load: the entangled words
+        // first, into buffer 1 (stage 0 writes buffer 0)
+        const PtrsI64 e = buffer(1);
+        hipLaunchKernelGGL(k_segment_entangle, dim3(grid(n_in), count), dim3(256), 0, s, cc, cp, e,
+                           n_in, Segment{}, l, err);
+        for (int t = 0; t < count; ++t) cur.p[t] = e.p[t];
+    }
+    for (int k = 0; k < ns; ++k) {
+        const Stage &g = stages[k];
+        const bool first = k == 0, last = k == ns - 1;
+        if (last && g.seg) {
+            // the last run with the recovery (and, as the only stage, the
+            // entanglement) in the same pass
+            launch_segment_extract(M, l, g.n_in, first, cur, cc, cp, make_segment(ops, g), out,
+                                   err, s);
+            return launch_status();
+        }
+        PtrsI64 dst = last ? out : buffer(k & 1);
+        if (g.n_out > 0) {
+            if (first && g.seg)
+                hipLaunchKernelGGL(k_segment_entangle, dim3(grid(g.n_in), count), dim3(256), 0, s,
+                                   cc, cp, dst, g.n_in, make_segment(ops, g), l, err);
+            else if (g.seg)
+                launch_segment<int64_t>(count, g.n_in, cur, dst, make_segment(ops, g), s);
+            else
+                Words64::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
+            st = launch_status();
+            if (st != NE_OK) return st;
+        }
+        for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
+    }
+    // the last stage wrote the computed streams' words into dhat: recover in place
+    PtrsCI64 in{};
+    for (int t = 0; t < M - 1; ++t) in.p[t] = out.p[t];
+    launch_extract(M, l, n_out, in, out, s);
+    return launch_status();
 }
 
 }  // namespace
@@ -415,6 +553,21 @@ ne_status ne_chain_apply(int32_t M, int64_t n_in, const int64_t *const *eps,
 {
     return apply_w<Words64>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, workspace,
                             workspace_bytes, stream);
+}
+
+ne_status ne_chain_run_workspace_size(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                      int32_t n_ops, size_t *bytes)
+{
+    if (M < 3 || M > kMaxM || !bytes) return NE_EINVAL;
+    return run_workspace(M, n_in, ops, n_ops, bytes);
+}
+
+ne_status ne_chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
+                       int32_t n_ops, int32_t lost, int64_t *const *dhat, int64_t n_out,
+                       void *workspace, size_t workspace_bytes, ne_stream stream)
+{
+    return chain_run(M, n_in, c, ops, n_ops, lost, dhat, n_out, workspace, workspace_bytes,
+                     stream);
 }
 
 ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *eps,

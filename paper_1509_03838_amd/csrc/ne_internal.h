@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ne.h"
 
 namespace ne {
@@ -41,6 +43,42 @@ uint32_t *device_flag_word();
 ne_status check_op_shape(int32_t op, int64_t n_in, const void *operand, int64_t n_operand,
                          int64_t n_out);
 
+// A run of consecutive element-wise operations of a series (scale, add, sub,
+// mul), optionally led by a permutation, applied in one pass over the
+// entangled words: out[i] = op_k( ... op_1(in[p[i]] or in[i]) ...).
+constexpr int kMaxSegmentOps = 8;
+struct SegmentOp {
+    int32_t op;
+    int32_t pad_;
+    const void *g;  // NE_OP_ADD / NE_OP_SUB: words of the stream width; NE_OP_MUL: int32
+    int64_t s;      // NE_OP_SCALE
+};
+struct Segment {
+    int32_t nops;
+    int32_t perm;          // 1: gather at p[i] first
+    const int32_t *p;
+    SegmentOp ops[kMaxSegmentOps];
+};
+
+// The run's operations on the word v of output position i (wrapping modulo
+// 2^(8 sizeof W)).
+template <typename W>
+__device__ __forceinline__ W segment_ops(W v0, const Segment &seg, int64_t i)
+{
+    using U = typename std::make_unsigned<W>::type;
+    U v = (U)v0;
+    for (int k = 0; k < seg.nops; ++k) {
+        const SegmentOp &o = seg.ops[k];
+        switch (o.op) {
+        case NE_OP_SCALE: v = v * (U)o.s; break;
+        case NE_OP_ADD: v = v + (U)((const W *)o.g)[i]; break;
+        case NE_OP_SUB: v = v - (U)((const W *)o.g)[i]; break;
+        default: v = v * (U)(W)((const int32_t *)o.g)[i]; break;  // NE_OP_MUL
+        }
+    }
+    return (W)v;
+}
+
 // ------------------------------------------------------------- launchers
 // All launchers assume validated arguments (the C-ABI layer checks them).
 
@@ -56,6 +94,15 @@ void launch_entangle_operand(int l, int64_t n, const int32_t *g, int64_t *g_ent,
 // d_{r+1}, ..., d_{r+M-1}, d_r in that order.
 void launch_extract(int M, int l, int64_t n, const PtrsCI64 &in, const PtrsI64 &out,
                     hipStream_t s);
+// Recovery fused into the last run of a series: slot t (t < M - 1) takes the
+// words of stream r+1+t -- in.p[t], or, with entangle, entangled on load from
+// the int32 streams cc.p[t] + 2^l cp.p[t] -- applies the run, and the M
+// outputs are recovered and written as launch_extract writes them. A
+// permutation index outside [0, n) reads nothing (the word is 0) and raises
+// NE_FLAG_PERM_INDEX in err.
+void launch_segment_extract(int M, int l, int64_t n, bool entangle, const PtrsCI64 &in,
+                            const PtrsI32 &cc, const PtrsI32 &cp, const Segment &seg,
+                            const PtrsI64 &out, uint32_t *err, hipStream_t s);
 
 // Element-wise LSB operations on `count` int64 streams (already compacted to
 // the active ones).

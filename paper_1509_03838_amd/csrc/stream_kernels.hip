@@ -172,6 +172,44 @@ __global__ __launch_bounds__(kBlock) void k_extract_v2(PtrsCI64 in, PtrsI64 out,
     }
 }
 
+// Recovery fused into a series' last run of element-wise operations (see
+// launch_segment_extract).
+template <int M, bool ENT>
+__global__ __launch_bounds__(kBlock) void k_segment_extract(PtrsCI64 in, PtrsI32 cc, PtrsI32 cp,
+                                                            Segment seg, PtrsI64 out, int64_t n,
+                                                            int l, uint32_t *err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        int64_t src = i;
+        if (seg.perm) {
+            src = seg.p[i];
+            if (src < 0 || src >= n) {
+                bad = true;
+                src = -1;
+            }
+        }
+        int64_t a[M - 1], oa[M];
+#pragma unroll
+        for (int t = 0; t < M - 1; ++t) {
+            int64_t v = 0;
+            if (src >= 0) {
+                if (ENT)
+                    v = (int64_t)((uint64_t)(int64_t)cc.p[t][src] +
+                                  ((uint64_t)(int64_t)cp.p[t][src] << l));
+                else
+                    v = in.p[t][src];
+            }
+            a[t] = segment_ops<int64_t>(v, seg, i);
+        }
+        recover_one<M>(a, oa, l);
+#pragma unroll
+        for (int t = 0; t < M; ++t) out.p[t][i] = oa[t];
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_extract_s(PtrsCI64 in, PtrsI64 out, int64_t n, int l)
 {
@@ -391,6 +429,28 @@ void launch_entangle(int M, int l, int64_t n, const PtrsI32 &c, const PtrsI64 &e
 void launch_entangle_inplace(int M, int l, int64_t n, const PtrsI64 &x, hipStream_t s)
 {
     NE_DISPATCH_M(M, entangle_inplace_m, l, n, x, s);
+}
+
+namespace {
+template <int M>
+void segment_extract_m(int l, int64_t n, bool entangle, const PtrsCI64 &in, const PtrsI32 &cc,
+                       const PtrsI32 &cp, const Segment &seg, const PtrsI64 &out, uint32_t *err,
+                       hipStream_t s)
+{
+    if (entangle)
+        hipLaunchKernelGGL((k_segment_extract<M, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, in,
+                           cc, cp, seg, out, n, l, err);
+    else
+        hipLaunchKernelGGL((k_segment_extract<M, false>), dim3(grid_for(n)), dim3(kBlock), 0, s,
+                           in, cc, cp, seg, out, n, l, err);
+}
+}  // namespace
+
+void launch_segment_extract(int M, int l, int64_t n, bool entangle, const PtrsCI64 &in,
+                            const PtrsI32 &cc, const PtrsI32 &cp, const Segment &seg,
+                            const PtrsI64 &out, uint32_t *err, hipStream_t s)
+{
+    NE_DISPATCH_M(M, segment_extract_m, l, n, entangle, in, cc, cp, seg, out, err, s);
 }
 
 void launch_entangle_operand(int l, int64_t n, const int32_t *g, int64_t *g_ent, hipStream_t s)

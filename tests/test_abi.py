@@ -357,6 +357,37 @@ def test_series_argument_checks():
     assert L.ne_chain_check(3, 10, 100, None, 1, ctypes.byref(no), None) == -1
 
 
+def test_series_run_workspace_and_checks():
+    """ne_chain_run: nothing for a series that is one run of element-wise
+    operations (one pass); the entangled inputs too when the series starts
+    with another operation; the intermediates otherwise. Bad arguments are
+    refused before the device is touched."""
+    n = 1000
+    up = lambda x: (x + 255) // 256 * 256
+    run = _series(("perm", n, 0, 0), ("add", n, 0, 8), ("scale", 0, 3, 0))  # one run
+    assert ne.chain_run_workspace_size(3, n, run) == 0
+    two = _series(("add", n, 0, 8), ("scale", 0, 3, 0), ("perm", n, 0, 0))  # a permutation leads
+    assert ne.chain_run_workspace_size(3, n, two) == 2 * 3 * up(8 * n)
+    conv = _series(("conv", 64, 0, 10))
+    assert ne.chain_run_workspace_size(3, n, conv) == 2 * 3 * up(8 * n)
+    mixed = _series(("add", n, 0, 8), ("scale", 0, 3, 0), ("conv", 64, 0, 10),
+                    ("perm", n + 63, 0, 0), ("add", n + 63, 0, 8))
+    assert ne.chain_run_workspace_size(5, n, mixed) == 2 * 5 * up(8 * (n + 63))
+    lead = _series(("conv", 64, 0, 10), ("perm", n + 63, 0, 0))
+    assert ne.chain_run_workspace_size(4, n, lead) == 2 * 4 * up(8 * (n + 63))
+    L = ne.load()
+    c = ne._ptr_array([FAKE + 64 * m for m in range(3)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 64 * m for m in range(3)])
+    arr = ne._chain_c(conv)
+    ws = ne.chain_run_workspace_size(3, n, conv)
+    assert L.ne_chain_run(3, n, c, arr, 1, -1, out, n + 63, None, 0, None) == -1     # no workspace
+    assert L.ne_chain_run(3, n, c, arr, 1, -1, out, n + 63, FAKE, ws - 1, None) == -1
+    assert L.ne_chain_run(3, n, c, arr, 1, -1, out, n + 62, FAKE, ws, None) == -1    # wrong n_out
+    assert L.ne_chain_run(3, n, c, arr, 1, 3, out, n + 63, FAKE, ws, None) == -3     # lost index
+    assert L.ne_chain_run(2, n, c, arr, 1, -1, out, n + 63, FAKE, ws, None) == -1    # M < 3
+    assert L.ne_chain_run(3, n, c, arr, 1, -1, out, n + 63, FAKE + 8, ws, None) == -1
+
+
 def test_series_workspace_size():
     """Two buffers of M streams of the longest intermediate (256-byte
     rounded); nothing for a single operation. ne_chain_apply refuses a

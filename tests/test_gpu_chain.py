@@ -121,3 +121,63 @@ def test_series_benchmark_size():
     ops = wl.chain_series(wl.rng(wl.SEED_BASE + 7), n, wl.CHAIN_RECIPE, bits=10, K=64)
     dhat, _ = run_series(c, ops, 1, 10, 10)
     assert np.array_equal(dhat, oracle.chain(c, ops))
+
+
+# ------------------------------------------------ the whole method in one call
+
+def run_whole(c, ops, lost, bits):
+    """ne_chain_run: int32 streams in, recovered outputs out."""
+    M, n = c.shape
+    l = ne.params(M)[0]
+    dops = device_ops(ops, l, bits)
+    no = n
+    for o in dops:
+        no = ne.n_out(o.op, no, o.n_operand)
+    cd = [dev32(r) for r in c]
+    dhat = [torch.full((max(no, 1),), POISON, dtype=torch.int64, device=DEV)[:no]
+            for _ in range(M)]
+    ne.chain_run(cd, dops, dhat, lost)
+    torch.cuda.synchronize()
+    return np.stack([t.cpu().numpy() for t in dhat])
+
+
+WHOLE = SERIES + [("scale", "add", "sub"), ("perm",), ("perm", "mul"), ("conv", "scale", "perm"),
+                  ("add", "conv")]
+
+
+@pytest.mark.parametrize("recipe", WHOLE)
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_series_in_one_call_recovers_plain_result(recipe, M):
+    """ne_chain_run: entanglement folded into a leading element-wise run,
+    recovery into a trailing one (one pass for a series that is one such
+    run), separate passes otherwise; every recipe against the oracle, with
+    and without a lost stream, ragged lengths."""
+    n = 3001
+    c = wl.uniform_i32(wl.rng(310 + M), -32, 32, (M, n))
+    ops = wl.chain_series(wl.rng(410 + M), n, recipe, bits=6, K=37)
+    want = oracle.chain(c, ops)
+    for lost in (-1, 0, M - 1):
+        assert np.array_equal(run_whole(c, ops, lost, 6), want), (recipe, M, lost)
+
+
+@pytest.mark.parametrize("recipe,n", [(("conv", "scale"), 0), (("scale",), 1), (("perm",), 1),
+                                      (("conv",), 5), (("add", "perm"), 2)])
+def test_series_in_one_call_edge_cases(recipe, n):
+    """Empty and one- or two-sample streams, one-operation series (no
+    workspace), a permutation that follows a fused run."""
+    M = 4
+    c = wl.uniform_i32(wl.rng(520 + n), -100, 100, (M, n))
+    ops = wl.chain_series(wl.rng(620 + n), n, recipe, bits=8, K=3)
+    want = oracle.chain(c, ops)
+    for lost in (-1, 2):
+        assert np.array_equal(run_whole(c, ops, lost, 8), want), (recipe, n, lost)
+
+
+def test_series_in_one_call_benchmark_size():
+    """The benchmark's series at its size through ne_chain_run, one stream
+    lost, compared in full."""
+    M, n = 3, 1 << 22
+    c = wl.uniform_i32(wl.rng(wl.SEED_BASE + 6), -512, 512, (M, n))
+    ops = wl.chain_series(wl.rng(wl.SEED_BASE + 7), n, wl.CHAIN_RECIPE, bits=10, K=64)
+    got = run_whole(c, ops, 1, 10)
+    assert np.array_equal(got, oracle.chain(c, ops))
