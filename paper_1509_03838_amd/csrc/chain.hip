@@ -202,6 +202,57 @@ __global__ __launch_bounds__(256) void k_segment(In x, Out y, int64_t n, Segment
     if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
 }
 
+// A run led by a permutation whose input rows hold the R streams' words of
+// each position (Segment::rows = R): every lane gathers all R words of its
+// source position from one row, so a random position costs one fetch of R
+// words rather than R fetches of one.
+template <int R>
+__global__ __launch_bounds__(256) void k_segment_rows(const int64_t *x, PtrsI64 y, int64_t n,
+                                                      Segment seg, uint32_t *err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        int64_t src = i;
+        if (seg.perm) {
+            src = seg.p[i];
+            if (src < 0 || src >= n) {
+                bad = true;
+                src = -1;
+            }
+        }
+        int64_t v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[t] = src >= 0 ? x[src * R + t] : 0;
+        segment_ops_all<int64_t, R>(v, seg, i);
+#pragma unroll
+        for (int t = 0; t < R; ++t) y.p[t][i] = v[t];
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
+// Streams a convolution may interleave into rows for the gather after it.
+constexpr int kMaxRows = 8;
+
+void launch_segment_rows(int count, int64_t n, const int64_t *x, const PtrsI64 &y,
+                         const Segment &seg, hipStream_t s)
+{
+    int64_t g = (n + 255) / 256;
+    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
+    const dim3 grid((unsigned)g), block(256);
+    uint32_t *err = device_flag_word();
+    switch (count) {
+    case 1: hipLaunchKernelGGL(k_segment_rows<1>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 2: hipLaunchKernelGGL(k_segment_rows<2>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 3: hipLaunchKernelGGL(k_segment_rows<3>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 4: hipLaunchKernelGGL(k_segment_rows<4>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 5: hipLaunchKernelGGL(k_segment_rows<5>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 6: hipLaunchKernelGGL(k_segment_rows<6>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 7: hipLaunchKernelGGL(k_segment_rows<7>, grid, block, 0, s, x, y, n, seg, err); break;
+    default: hipLaunchKernelGGL(k_segment_rows<8>, grid, block, 0, s, x, y, n, seg, err); break;
+    }
+}
+
 // The first run of a series with the entanglement on load: stream y's words
 // are c_m + 2^l c_{m-1} (cc.p[y], cp.p[y]) from the int32 inputs.
 __global__ __launch_bounds__(256) void k_segment_entangle(PtrsI32 cc, PtrsI32 cp, PtrsI64 y,
@@ -233,6 +284,12 @@ template <typename W, typename In, typename Out>
 void launch_segment(int count, int64_t n, const In &x, const Out &y, const Segment &seg,
                     hipStream_t s)
 {
+    if constexpr (std::is_same<W, int64_t>::value) {
+        if (seg.rows > 0) {
+            launch_segment_rows(count, n, x.p[0], y, seg, s);
+            return;
+        }
+    }
     int64_t g = (n + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     hipLaunchKernelGGL((k_segment<W, In, Out>), dim3((unsigned)g, count), dim3(256), 0, s, x, y, n,
@@ -241,10 +298,24 @@ void launch_segment(int count, int64_t n, const In &x, const Out &y, const Segme
 
 // Word-width traits of the series' execution: the stream tables and the
 // launch of one operation.
+inline bool conv_kind(int32_t op)
+{
+    return op == NE_OP_CONV || op == NE_OP_CIRC || op == NE_OP_XCORR;
+}
+
 struct Words64 {
     using W = int64_t;
     using In = PtrsCI64;
     using Out = PtrsI64;
+    static constexpr bool kRows = true;  // convolutions can write rows
+    static ne_status conv_rows(const ne_chain_op &o, int count, int64_t n, const In &cur,
+                               int64_t *rows, hipStream_t s)
+    {
+        const int kind = o.op == NE_OP_CIRC ? kConvCircular
+                                            : (o.op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
+        launch_conv_i64_rows(count, n, cur, (const int32_t *)o.operand, o.n_operand, rows, s, kind);
+        return launch_status();
+    }
     static ne_status launch(const ne_chain_op &o, int count, int64_t n, const In &cur,
                             const Out &dst, int64_t m, hipStream_t s)
     {
@@ -288,6 +359,12 @@ struct Words32 {
     using W = int32_t;
     using In = PtrsI32;
     using Out = PtrsW32;
+    static constexpr bool kRows = false;
+    static ne_status conv_rows(const ne_chain_op &, int, int64_t, const In &, int32_t *,
+                               hipStream_t)
+    {
+        return NE_EUNSUP;
+    }
     static ne_status launch(const ne_chain_op &o, int count, int64_t n, const In &cur,
                             const Out &dst, int64_t m, hipStream_t s)
     {
@@ -331,11 +408,20 @@ int split_stages(const ne_chain_op *ops, int32_t n_ops, int64_t n_in, Stage *out
     return ns;
 }
 
-Segment make_segment(const ne_chain_op *ops, const Stage &g)
+// Stage k, a convolution whose output a permutation-led run gathers next,
+// writes that output as rows of its `count` streams (kMaxRows at most).
+bool rows_after(const ne_chain_op *ops, const Stage *st, int ns, int k, int count)
+{
+    return k + 1 < ns && !st[k].seg && conv_kind(ops[st[k].i].op) && st[k + 1].seg &&
+           ops[st[k + 1].i].op == NE_OP_PERM && count <= kMaxRows;
+}
+
+Segment make_segment(const ne_chain_op *ops, const Stage &g, int rows = 0)
 {
     Segment seg{};
     seg.perm = ops[g.i].op == NE_OP_PERM;
     seg.p = seg.perm ? (const int32_t *)ops[g.i].operand : nullptr;
+    seg.rows = rows;
     for (int32_t k = g.i + seg.perm; k < g.j; ++k) {
         SegmentOp &so = seg.ops[seg.nops++];
         so.op = ops[k].op;
@@ -392,11 +478,15 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
     }
     hipStream_t s = (hipStream_t)stream;
     unsigned char *ws = (unsigned char *)workspace;
-    // Stage k writes workspace buffer (k & 1), the last one delta.
+    // Stage k writes workspace buffer (k & 1), the last one delta; a
+    // convolution before a permutation-led run writes rows there (the
+    // buffer's M planes hold count rows of the longest stage).
     Stage stages[kMaxChainOps];
     const int ns = split_stages(ops, n_ops, n_in, stages);
+    int rows_in = 0;  // > 0: the current input is in rows of that many words
     for (int k = 0; k < ns; ++k) {
         const Stage &g = stages[k];
+        const bool to_rows = T::kRows && rows_after(ops, stages, ns, k, count);
         typename T::Out dst{};
         if (k == ns - 1) {
             dst = fin;
@@ -406,11 +496,14 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
         }
         if (g.n_out > 0) {
             if (g.seg)
-                st = T::segment(make_segment(ops, g), count, g.n_in, cur, dst, s);
+                st = T::segment(make_segment(ops, g, rows_in), count, g.n_in, cur, dst, s);
+            else if (to_rows)
+                st = T::conv_rows(ops[g.i], count, g.n_in, cur, dst.p[0], s);
             else
                 st = T::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
             if (st != NE_OK) return st;
         }
+        rows_in = to_rows ? count : 0;
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
     }
     return NE_OK;
@@ -499,28 +592,33 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
                            n_in, Segment{}, l, err);
         for (int t = 0; t < count; ++t) cur.p[t] = e.p[t];
     }
+    int rows_in = 0;  // > 0: the current input is in rows of that many words
     for (int k = 0; k < ns; ++k) {
         const Stage &g = stages[k];
         const bool first = k == 0, last = k == ns - 1;
         if (last && g.seg) {
             // the last run with the recovery (and, as the only stage, the
             // entanglement) in the same pass
-            launch_segment_extract(M, l, g.n_in, first, cur, cc, cp, make_segment(ops, g), out,
-                                   err, s);
+            launch_segment_extract(M, l, g.n_in, first, cur, cc, cp, make_segment(ops, g, rows_in),
+                                   out, err, s);
             return launch_status();
         }
+        const bool to_rows = rows_after(ops, stages, ns, k, count);
         PtrsI64 dst = last ? out : buffer(k & 1);
         if (g.n_out > 0) {
             if (first && g.seg)
                 hipLaunchKernelGGL(k_segment_entangle, dim3(grid(g.n_in), count), dim3(256), 0, s,
                                    cc, cp, dst, g.n_in, make_segment(ops, g), l, err);
             else if (g.seg)
-                launch_segment<int64_t>(count, g.n_in, cur, dst, make_segment(ops, g), s);
+                launch_segment<int64_t>(count, g.n_in, cur, dst, make_segment(ops, g, rows_in), s);
+            else if (to_rows)
+                Words64::conv_rows(ops[g.i], count, g.n_in, cur, dst.p[0], s);
             else
                 Words64::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
             st = launch_status();
             if (st != NE_OK) return st;
         }
+        rows_in = to_rows ? count : 0;
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
     }
     // the last stage wrote the computed streams' words into dhat: recover in place

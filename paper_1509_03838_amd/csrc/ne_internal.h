@@ -57,6 +57,12 @@ struct Segment {
     int32_t nops;
     int32_t perm;          // 1: gather at p[i] first
     const int32_t *p;
+    // 0: stream t's input words are the plane in.p[t]; > 0: they are
+    // interleaved in rows of that many words (stream t of position i at
+    // in.p[0][i * rows + t]), so that a gather fetches every stream's word of
+    // one position from one place
+    int32_t rows;
+    int32_t pad_;
     SegmentOp ops[kMaxSegmentOps];
 };
 
@@ -79,6 +85,33 @@ __device__ __forceinline__ W segment_ops(W v0, const Segment &seg, int64_t i)
     return (W)v;
 }
 
+// The same run on the words of R streams at one position: every operand
+// word is read once for all of them.
+template <typename W, int R>
+__device__ __forceinline__ void segment_ops_all(W (&v)[R], const Segment &seg, int64_t i)
+{
+    using U = typename std::make_unsigned<W>::type;
+    for (int k = 0; k < seg.nops; ++k) {
+        const SegmentOp &o = seg.ops[k];
+        if (o.op == NE_OP_SCALE) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t] = (W)((U)v[t] * (U)o.s);
+            continue;
+        }
+        const U g = o.op == NE_OP_MUL ? (U)(W)((const int32_t *)o.g)[i] : (U)((const W *)o.g)[i];
+        if (o.op == NE_OP_ADD) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t] = (W)((U)v[t] + g);
+        } else if (o.op == NE_OP_SUB) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t] = (W)((U)v[t] - g);
+        } else {
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t] = (W)((U)v[t] * g);
+        }
+    }
+}
+
 // ------------------------------------------------------------- launchers
 // All launchers assume validated arguments (the C-ABI layer checks them).
 
@@ -97,7 +130,8 @@ void launch_extract(int M, int l, int64_t n, const PtrsCI64 &in, const PtrsI64 &
 // Recovery fused into the last run of a series: slot t (t < M - 1) takes the
 // words of stream r+1+t -- in.p[t], or, with entangle, entangled on load from
 // the int32 streams cc.p[t] + 2^l cp.p[t] -- applies the run, and the M
-// outputs are recovered and written as launch_extract writes them. A
+// outputs are recovered and written as launch_extract writes them; with
+// seg.rows > 0 (no entangle) slot t's words are in.p[0][i * seg.rows + t]. A
 // permutation index outside [0, n) reads nothing (the word is 0) and raises
 // NE_FLAG_PERM_INDEX in err.
 void launch_segment_extract(int M, int l, int64_t n, bool entangle, const PtrsCI64 &in,
@@ -118,6 +152,10 @@ void launch_inner_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g,
 constexpr int kConvLinear = 0, kConvCircular = 1, kConvXcorr = 2;
 void launch_conv_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
                      const PtrsI64 &y, hipStream_t s, int kind = kConvLinear);
+// The same, writing the `count` outputs of each position as one row:
+// stream t's output i goes to rows[i * count + t].
+void launch_conv_i64_rows(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, int64_t K,
+                          int64_t *rows, hipStream_t s, int kind = kConvLinear);
 void launch_sub_i64(int count, int64_t n, const PtrsCI64 &x, const int64_t *g, const PtrsI64 &y,
                     hipStream_t s);
 void launch_mul_i64(int count, int64_t n, const PtrsCI64 &x, const int32_t *g, const PtrsI64 &y,

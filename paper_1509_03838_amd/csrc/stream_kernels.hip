@@ -190,19 +190,27 @@ __global__ __launch_bounds__(kBlock) void k_segment_extract(PtrsCI64 in, PtrsI32
                 src = -1;
             }
         }
+        // every stream's word first (independent loads in flight together),
+        // then the run on all of them
         int64_t a[M - 1], oa[M];
 #pragma unroll
-        for (int t = 0; t < M - 1; ++t) {
-            int64_t v = 0;
-            if (src >= 0) {
-                if (ENT)
-                    v = (int64_t)((uint64_t)(int64_t)cc.p[t][src] +
-                                  ((uint64_t)(int64_t)cp.p[t][src] << l));
-                else
-                    v = in.p[t][src];
+        for (int t = 0; t < M - 1; ++t) a[t] = 0;
+        if (src >= 0) {
+            if (ENT) {
+#pragma unroll
+                for (int t = 0; t < M - 1; ++t)
+                    a[t] = (int64_t)((uint64_t)(int64_t)cc.p[t][src] +
+                                     ((uint64_t)(int64_t)cp.p[t][src] << l));
+            } else if (seg.rows > 0) {
+                const int64_t *row = in.p[0] + src * seg.rows;
+#pragma unroll
+                for (int t = 0; t < M - 1; ++t) a[t] = row[t];
+            } else {
+#pragma unroll
+                for (int t = 0; t < M - 1; ++t) a[t] = in.p[t][src];
             }
-            a[t] = segment_ops<int64_t>(v, seg, i);
         }
+        segment_ops_all<int64_t, M - 1>(a, seg, i);
         recover_one<M>(a, oa, l);
 #pragma unroll
         for (int t = 0; t < M; ++t) out.p[t][i] = oa[t];

@@ -15,7 +15,9 @@ POISON = -0x5A5A5A5A5A5A5A5A
 
 SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
           ("perm", "add", "conv", "inner"), ("add",), ("inner", "conv", "add"),
-          ("sub", "mul", "circ", "xcorr"), ("outer", "sub", "perm")]
+          ("sub", "mul", "circ", "xcorr"), ("outer", "sub", "perm"),
+          # a convolution before a permutation-led run writes interleaved rows
+          ("conv", "perm", "conv", "perm", "add"), ("circ", "perm", "scale"), ("xcorr", "perm")]
 
 
 def dev32(a):
@@ -181,3 +183,18 @@ def test_series_in_one_call_benchmark_size():
     ops = wl.chain_series(wl.rng(wl.SEED_BASE + 7), n, wl.CHAIN_RECIPE, bits=10, K=64)
     got = run_whole(c, ops, 1, 10)
     assert np.array_equal(got, oracle.chain(c, ops))
+
+
+@pytest.mark.parametrize("M", [8, 9])
+def test_series_rows_at_the_row_limit(M):
+    """Rows hold at most 8 streams: M = 8 gathers from rows with and without a
+    lost stream; M = 9 gathers from planes with all 9 streams computed and
+    from rows once one is lost (8 computed), through both calls."""
+    n = 2001
+    c = wl.uniform_i32(wl.rng(800 + M), -8, 8, (M, n))
+    ops = wl.chain_series(wl.rng(810 + M), n, ("conv", "perm", "add"), bits=4, K=9)
+    want = oracle.chain(c, ops)
+    for lost in (-1, 0, M - 1):
+        dhat, _ = run_series(c, ops, lost, 4, 4)
+        assert np.array_equal(dhat, want), (M, lost)
+        assert np.array_equal(run_whole(c, ops, lost, 4), want), (M, lost)
