@@ -63,6 +63,9 @@ def parse():
                    help="untimed launches of every mode for this long before timing")
     p.add_argument("--single-launch", action="store_true",
                    help="the timed mode runs as one persistent launch (ne_tuning.single_launch)")
+    p.add_argument("--by-category", action="store_true",
+                   help="also time every (operation, M) category of the batch alone and the "
+                        "widening copy of the batch's bytes (per-category roofline)")
     p.add_argument("--no-serving", action="store_true",
                    help="batched line: skip the short serving run")
     p.add_argument("--budget-mib", type=int, default=2048, help="serving: HBM budget")
@@ -330,8 +333,11 @@ def main():
         if "entangled_single_launch" in results:
             line["baselines"]["single_launch_pct_vs_per_variant_launches"] = pct(
                 "entangled_single_launch", main_mode)
-    if args.config == "batched" and not args.only:
+    if (args.config == "batched" and not args.only) or args.by_category:
         line["roofline"]["hbm_ceiling"] = hbm_ceiling(torch, ne, stream, stats, args, achieved)
+    if args.by_category:
+        line["categories"] = by_category(torch, ne, np, args, groups, c_dev, k_dev, out, in_bits,
+                                         main_mode, stream, tuner)
     if roof["bound"] == "mfma" and not args.only:
         line["roofline"]["mfma_ceiling"] = mfma_ceiling(torch, ne, stream, mfma_tops)
 
@@ -341,6 +347,35 @@ def main():
     if args.config == "batched" and not args.only and not args.no_serving:
         line["serving"] = serving_summary(args, wl)
     print(json.dumps(line), flush=True)
+
+
+def by_category(torch, ne, np, args, groups, c_dev, k_dev, out, in_bits, mode, stream, tuner):
+    """Every (operation, M) category of the batch alone, as its own captured
+    plan timed like the whole batch (median of the rounds): its time,
+    algorithmic bytes (inputs and operands read once, outputs written once)
+    and rate against the HBM peak."""
+    cats = {}
+    for i, g in enumerate(groups):
+        cats.setdefault((g.op, g.M), []).append(i)
+    rows = []
+    for (op, M), idx in sorted(cats.items()):
+        specs = [ne.GroupSpec(groups[i].op, c_dev[i], k_dev[i], out[i], groups[i].scalar, -1,
+                              in_bits) for i in idx]
+        if tuner is not None:
+            tuner.tune(specs, mode)
+        plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps)
+        plan.capture(stream)
+        ms = float(np.median([time_captured(torch, plan, stream, args.steps,
+                                            args.warmup if r == 0 else 0)[0]
+                              for r in range(args.rounds)]))
+        st = plan.stats()
+        plan.close()
+        b = st["in_bytes"] + st["out_bytes"]
+        gbps = b / (ms * 1e-3) / 1e9
+        rows.append({"op": op, "M": M, "groups": len(idx), "ms": round(ms, 4), "alg_bytes": b,
+                     "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBS, 4),
+                     "launches": st["launches"]})
+    return rows
 
 
 def name_of(key):
