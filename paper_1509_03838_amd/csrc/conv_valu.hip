@@ -16,12 +16,17 @@
 // disjoint words of the same rows (a block that looped over the streams
 // measured 2% slower).
 //
-// int64 x int32 products modulo 2^64 without a 64x64 multiply: with
-// x = xh 2^32 + xl (xl unsigned) and g = gu - 2^32 [g < 0] (gu = g mod 2^32),
-//     x g = xl gu + 2^32 (xh gu - xl [g < 0])          (mod 2^64),
-// so each tap costs one 32x32->64 multiply-add into a 64-bit accumulator
-// and one 32-bit multiply-add into a second accumulator that only needs to
-// be right modulo 2^32; the two are combined once per output.
+// int64 x int32 products modulo 2^64 without a 64x64 multiply: the window
+// word x is staged as x = xh 2^32 + xs with xs its low half read as a
+// signed int32 (xh then carries xs's borrow: xh = (x >> 32) + [xs < 0],
+// modulo 2^32), so that
+//     x g = xs g + 2^32 (xh g mod 2^32)          (mod 2^64)
+// with xs g an exact signed 32x32->64 product. Each tap costs one signed
+// 32x32->64 multiply-add into a 64-bit accumulator and one 32-bit
+// multiply-add into a second accumulator that only needs to be right
+// modulo 2^32; the two are combined once per output. (With an unsigned low
+// half the product needs a correction for negative taps, two more vector
+// operations per tap and output.)
 #include "ne_internal.h"
 
 namespace ne {
@@ -67,7 +72,7 @@ __device__ __forceinline__ int32_t tap(const int32_t *g, int64_t j, int64_t K, i
 
 // One stream's tile of kTile outputs (t0 onwards) into out[t * stride].
 __device__ __forceinline__ void conv_i64_tile(const ConvArgsI64 &a, const int64_t *x, int64_t *out,
-                                              int64_t stride, uint32_t *sxl, uint32_t *sxh,
+                                              int64_t stride, int32_t *sxl, uint32_t *sxh,
                                               int32_t *sg)
 {
     const int tid = threadIdx.x;
@@ -87,22 +92,25 @@ __device__ __forceinline__ void conv_i64_tile(const ConvArgsI64 &a, const int64_
         for (int w = tid; w < wlen; w += kBlock) {
             const int64_t idx = window_index(wbase + w, a.n, a.kind);
             const uint64_t v = idx >= 0 ? (uint64_t)x[idx] : 0;
-            sxl[w] = (uint32_t)v;
-            sxh[w] = (uint32_t)(v >> 32);
+            const uint32_t l32 = (uint32_t)v;
+            sxl[w] = (int32_t)l32;
+            sxh[w] = (uint32_t)(v >> 32) + (l32 >> 31);
         }
         for (int j = tid; j < kc; j += kBlock) sg[j] = tap(a.g, j0 + j, a.K, a.kind);
         __syncthreads();
+        // four taps per pass: their window words are read from LDS together
+        // (8% faster than one tap per pass)
+#pragma unroll 4
         for (int j = 0; j < kc; ++j) {
             const int32_t gj = sg[j];
             const uint32_t gu = (uint32_t)gj;
-            const uint32_t gs = (uint32_t)(gj >> 31);
             const int wb = tid + kc - 1 - j;
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const uint32_t xl = sxl[wb + q * kBlock];
+                const int32_t xs = sxl[wb + q * kBlock];
                 const uint32_t xh = sxh[wb + q * kBlock];
-                lo[q] += (uint64_t)xl * gu;
-                hi[q] += xh * gu - (xl & gs);
+                lo[q] += (uint64_t)((int64_t)xs * (int64_t)gj);
+                hi[q] += xh * gu;
             }
         }
     }
@@ -115,7 +123,7 @@ __device__ __forceinline__ void conv_i64_tile(const ConvArgsI64 &a, const int64_
 
 __global__ __launch_bounds__(kBlock) void k_conv_i64(ConvArgsI64 a)
 {
-    __shared__ uint32_t sxl[kTile + kKC];
+    __shared__ int32_t sxl[kTile + kKC];
     __shared__ uint32_t sxh[kTile + kKC];
     __shared__ int32_t sg[kKC];
     if (a.rows == 0)
