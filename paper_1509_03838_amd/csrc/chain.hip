@@ -253,33 +253,6 @@ void launch_segment_rows(int count, int64_t n, const int64_t *x, const PtrsI64 &
     }
 }
 
-// The first run of a series with the entanglement on load: stream y's words
-// are c_m + 2^l c_{m-1} (cc.p[y], cp.p[y]) from the int32 inputs.
-__global__ __launch_bounds__(256) void k_segment_entangle(PtrsI32 cc, PtrsI32 cp, PtrsI64 y,
-                                                          int64_t n, Segment seg, int l,
-                                                          uint32_t *err)
-{
-    const int32_t *xc = cc.p[blockIdx.y], *xp = cp.p[blockIdx.y];
-    int64_t *ys = y.p[blockIdx.y];
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256) {
-        int64_t src = i;
-        if (seg.perm) {
-            src = seg.p[i];
-            if (src < 0 || src >= n) {
-                bad = true;
-                src = -1;
-            }
-        }
-        const int64_t v = src < 0 ? 0
-                                  : (int64_t)((uint64_t)(int64_t)xc[src] +
-                                              ((uint64_t)(int64_t)xp[src] << l));
-        ys[i] = segment_ops<int64_t>(v, seg, i);
-    }
-    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
-}
-
 template <typename W, typename In, typename Out>
 void launch_segment(int count, int64_t n, const In &x, const Out &y, const Segment &seg,
                     hipStream_t s)
@@ -562,13 +535,11 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
     const int ns = split_stages(ops, n_ops, n_in, stages);
     const int r = lost >= 0 ? lost : 0;
     const int count = lost >= 0 ? M - 1 : M;  // computed streams
-    PtrsI32 cc{}, cp{};
+    PtrsI32 cr{};  // the int32 streams from r on: slot t entangles cr[t + 1] with cr[t]
     PtrsI64 out{};
     for (int t = 0; t < M; ++t) {
-        const int m = (r + 1 + t) % M;
-        cc.p[t] = c[m];
-        cp.p[t] = c[(m + M - 1) % M];
-        out.p[t] = dhat[m];
+        cr.p[t] = c[(r + t) % M];
+        out.p[t] = dhat[(r + 1 + t) % M];
     }
     hipStream_t s = (hipStream_t)stream;
     uint32_t *err = device_flag_word();
@@ -579,17 +550,12 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
         for (int t = 0; t < count; ++t) p.p[t] = (int64_t *)(ws + ((size_t)b * M + t) * plane);
         return p;
     };
-    auto grid = [](int64_t n) {
-        const int64_t g = (n + 255) / 256;
-        return (unsigned)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
-    };
     PtrsCI64 cur{};
     if (!stages[0].seg) {
         // a first stage that cannot entangle on load: the entangled words
         // first, into buffer 1 (stage 0 writes buffer 0)
         const PtrsI64 e = buffer(1);
-        hipLaunchKernelGGL(k_segment_entangle, dim3(grid(n_in), count), dim3(256), 0, s, cc, cp, e,
-                           n_in, Segment{}, l, err);
+        launch_segment_entangle(M, l, n_in, count, cr, Segment{}, e, err, s);
         for (int t = 0; t < count; ++t) cur.p[t] = e.p[t];
     }
     int rows_in = 0;  // > 0: the current input is in rows of that many words
@@ -599,16 +565,15 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
         if (last && g.seg) {
             // the last run with the recovery (and, as the only stage, the
             // entanglement) in the same pass
-            launch_segment_extract(M, l, g.n_in, first, cur, cc, cp, make_segment(ops, g, rows_in),
-                                   out, err, s);
+            launch_segment_extract(M, l, g.n_in, first, cur, cr, make_segment(ops, g, rows_in), out,
+                                   err, s);
             return launch_status();
         }
         const bool to_rows = rows_after(ops, stages, ns, k, count);
         PtrsI64 dst = last ? out : buffer(k & 1);
         if (g.n_out > 0) {
             if (first && g.seg)
-                hipLaunchKernelGGL(k_segment_entangle, dim3(grid(g.n_in), count), dim3(256), 0, s,
-                                   cc, cp, dst, g.n_in, make_segment(ops, g), l, err);
+                launch_segment_entangle(M, l, g.n_in, count, cr, make_segment(ops, g), dst, err, s);
             else if (g.seg)
                 launch_segment<int64_t>(count, g.n_in, cur, dst, make_segment(ops, g, rows_in), s);
             else if (to_rows)

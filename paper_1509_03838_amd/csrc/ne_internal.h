@@ -129,14 +129,21 @@ void launch_extract(int M, int l, int64_t n, const PtrsCI64 &in, const PtrsI64 &
                     hipStream_t s);
 // Recovery fused into the last run of a series: slot t (t < M - 1) takes the
 // words of stream r+1+t -- in.p[t], or, with entangle, entangled on load from
-// the int32 streams cc.p[t] + 2^l cp.p[t] -- applies the run, and the M
-// outputs are recovered and written as launch_extract writes them; with
-// seg.rows > 0 (no entangle) slot t's words are in.p[0][i * seg.rows + t]. A
-// permutation index outside [0, n) reads nothing (the word is 0) and raises
-// NE_FLAG_PERM_INDEX in err.
+// the int32 streams (c.p[u] is stream r + u mod M: slot t's word is
+// c.p[t + 1] + 2^l c.p[t]) -- applies the run, and the M outputs are
+// recovered and written as launch_extract writes them; with seg.rows > 0 (no
+// entangle) slot t's words are in.p[0][i * seg.rows + t]. A permutation index
+// outside [0, n) reads nothing (the word is 0) and raises NE_FLAG_PERM_INDEX
+// in err.
 void launch_segment_extract(int M, int l, int64_t n, bool entangle, const PtrsCI64 &in,
-                            const PtrsI32 &cc, const PtrsI32 &cp, const Segment &seg,
-                            const PtrsI64 &out, uint32_t *err, hipStream_t s);
+                            const PtrsI32 &c, const Segment &seg, const PtrsI64 &out,
+                            uint32_t *err, hipStream_t s);
+// The first run of a series with the entanglement on load: slots 0..count-1
+// (count = M, or M - 1 with a lost stream) entangled from the int32 streams
+// as above, each stream's sample read once per position, the run applied,
+// slot t's words written to y.p[t]. Permutation indices as above.
+void launch_segment_entangle(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                             const Segment &seg, const PtrsI64 &y, uint32_t *err, hipStream_t s);
 
 // Element-wise LSB operations on `count` int64 streams (already compacted to
 // the active ones).

@@ -172,12 +172,60 @@ __global__ __launch_bounds__(kBlock) void k_extract_v2(PtrsCI64 in, PtrsI64 out,
     }
 }
 
+// Slots 0..R-1 of a series' entangled words at source position src, from
+// the int32 streams c.p[u] = stream r + u (mod M): slot t is stream r+1+t,
+// c_{r+1+t} + 2^l c_{r+t}. Every stream's sample is read once, all loads
+// in flight together; src < 0 gives zeros.
+template <int M, int R>
+__device__ __forceinline__ void entangle_slots(const PtrsI32 &c, int64_t src, int l,
+                                               int64_t (&e)[R])
+{
+    int64_t v[M];
+#pragma unroll
+    for (int u = 0; u < M; ++u) v[u] = 0;
+    if (src >= 0) {
+#pragma unroll
+        for (int u = 0; u < M; ++u) v[u] = c.p[u][src];
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t)
+        e[t] = (int64_t)((uint64_t)v[(t + 1) % M] + ((uint64_t)v[t] << l));
+}
+
+// A series' first run of element-wise operations with the entanglement on
+// load (see launch_segment_entangle).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_segment_entangle(PtrsI32 c, Segment seg, PtrsI64 y,
+                                                             int count, int64_t n, int l,
+                                                             uint32_t *err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        int64_t src = i;
+        if (seg.perm) {
+            src = seg.p[i];
+            if (src < 0 || src >= n) {
+                bad = true;
+                src = -1;
+            }
+        }
+        int64_t e[M];
+        entangle_slots<M, M>(c, src, l, e);
+        segment_ops_all<int64_t, M>(e, seg, i);
+#pragma unroll
+        for (int t = 0; t < M; ++t)
+            if (t < count) y.p[t][i] = e[t];
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
 // Recovery fused into a series' last run of element-wise operations (see
 // launch_segment_extract).
 template <int M, bool ENT>
-__global__ __launch_bounds__(kBlock) void k_segment_extract(PtrsCI64 in, PtrsI32 cc, PtrsI32 cp,
-                                                            Segment seg, PtrsI64 out, int64_t n,
-                                                            int l, uint32_t *err)
+__global__ __launch_bounds__(kBlock) void k_segment_extract(PtrsCI64 in, PtrsI32 c, Segment seg,
+                                                            PtrsI64 out, int64_t n, int l,
+                                                            uint32_t *err)
 {
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -195,13 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_segment_extract(PtrsCI64 in, PtrsI32
         int64_t a[M - 1], oa[M];
 #pragma unroll
         for (int t = 0; t < M - 1; ++t) a[t] = 0;
-        if (src >= 0) {
-            if (ENT) {
-#pragma unroll
-                for (int t = 0; t < M - 1; ++t)
-                    a[t] = (int64_t)((uint64_t)(int64_t)cc.p[t][src] +
-                                     ((uint64_t)(int64_t)cp.p[t][src] << l));
-            } else if (seg.rows > 0) {
+        if (ENT) {
+            entangle_slots<M, M - 1>(c, src, l, a);
+        } else if (src >= 0) {
+            if (seg.rows > 0) {
                 const int64_t *row = in.p[0] + src * seg.rows;
 #pragma unroll
                 for (int t = 0; t < M - 1; ++t) a[t] = row[t];
@@ -441,24 +486,37 @@ void launch_entangle_inplace(int M, int l, int64_t n, const PtrsI64 &x, hipStrea
 
 namespace {
 template <int M>
-void segment_extract_m(int l, int64_t n, bool entangle, const PtrsCI64 &in, const PtrsI32 &cc,
-                       const PtrsI32 &cp, const Segment &seg, const PtrsI64 &out, uint32_t *err,
-                       hipStream_t s)
+void segment_extract_m(int l, int64_t n, bool entangle, const PtrsCI64 &in, const PtrsI32 &c,
+                       const Segment &seg, const PtrsI64 &out, uint32_t *err, hipStream_t s)
 {
     if (entangle)
         hipLaunchKernelGGL((k_segment_extract<M, true>), dim3(grid_for(n)), dim3(kBlock), 0, s, in,
-                           cc, cp, seg, out, n, l, err);
+                           c, seg, out, n, l, err);
     else
         hipLaunchKernelGGL((k_segment_extract<M, false>), dim3(grid_for(n)), dim3(kBlock), 0, s,
-                           in, cc, cp, seg, out, n, l, err);
+                           in, c, seg, out, n, l, err);
+}
+
+template <int M>
+void segment_entangle_m(int l, int64_t n, int count, const PtrsI32 &c, const Segment &seg,
+                        const PtrsI64 &y, uint32_t *err, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_segment_entangle<M>, dim3(grid_for(n)), dim3(kBlock), 0, s, c, seg, y,
+                       count, n, l, err);
 }
 }  // namespace
 
 void launch_segment_extract(int M, int l, int64_t n, bool entangle, const PtrsCI64 &in,
-                            const PtrsI32 &cc, const PtrsI32 &cp, const Segment &seg,
-                            const PtrsI64 &out, uint32_t *err, hipStream_t s)
+                            const PtrsI32 &c, const Segment &seg, const PtrsI64 &out,
+                            uint32_t *err, hipStream_t s)
 {
-    NE_DISPATCH_M(M, segment_extract_m, l, n, entangle, in, cc, cp, seg, out, err, s);
+    NE_DISPATCH_M(M, segment_extract_m, l, n, entangle, in, c, seg, out, err, s);
+}
+
+void launch_segment_entangle(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                             const Segment &seg, const PtrsI64 &y, uint32_t *err, hipStream_t s)
+{
+    NE_DISPATCH_M(M, segment_entangle_m, l, n, count, c, seg, y, err, s);
 }
 
 void launch_entangle_operand(int l, int64_t n, const int32_t *g, int64_t *g_ent, hipStream_t s)
