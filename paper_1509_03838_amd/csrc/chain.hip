@@ -241,7 +241,7 @@ void launch_segment_rows(int count, int64_t n, const int64_t *x, const PtrsI64 &
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     const dim3 grid((unsigned)g), block(256);
     uint32_t *err = device_flag_word();
-    switch (count) {
+    switch (count) {  // 1..kMaxRows: rows_after admits no more
     case 1: hipLaunchKernelGGL(k_segment_rows<1>, grid, block, 0, s, x, y, n, seg, err); break;
     case 2: hipLaunchKernelGGL(k_segment_rows<2>, grid, block, 0, s, x, y, n, seg, err); break;
     case 3: hipLaunchKernelGGL(k_segment_rows<3>, grid, block, 0, s, x, y, n, seg, err); break;
