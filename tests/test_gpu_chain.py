@@ -198,3 +198,22 @@ def test_series_rows_at_the_row_limit(M):
         dhat, _ = run_series(c, ops, lost, 4, 4)
         assert np.array_equal(dhat, want), (M, lost)
         assert np.array_equal(run_whole(c, ops, lost, 4), want), (M, lost)
+
+
+@pytest.mark.parametrize("M", [16, 32])
+@pytest.mark.parametrize("recipe", [("add", "scale"), ("conv", "perm", "add"),
+                                    ("scale", "conv", "add", "perm")])
+def test_series_many_streams(M, recipe):
+    """Groups of 16 and 32 streams (l = 4 and 2): the one-pass series (its
+    entanglement and recovery in one kernel), a permutation after a
+    convolution gathering from planes (past the 8-stream row limit), a
+    permutation leading the last run; through both calls, with and without a
+    lost stream."""
+    n = 1001
+    c = wl.uniform_i32(wl.rng(950 + M), -8, 8, (M, n))
+    ops = wl.chain_series(wl.rng(900 + M), n, recipe, bits=4, K=5)
+    want = oracle.chain(c, ops)
+    for lost in (-1, 0, M - 1):
+        dhat, _ = run_series(c, ops, lost, 4, 4)
+        assert np.array_equal(dhat, want), (M, recipe, lost)
+        assert np.array_equal(run_whole(c, ops, lost, 4), want), (M, recipe, lost)
