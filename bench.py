@@ -934,7 +934,10 @@ def w32_line(args, wl):
     executor with int32 outputs (one captured launch); baselines: the same
     with 64-bit words, the plain fused convolution with int32 outputs, and
     the per-step pipeline (entangle -> conv -> extract) in 32- and 64-bit
-    words against the plain per-step convolution."""
+    words against the plain per-step convolution; and a series in these
+    words (add -> conv -> perm -> add, worst case 2^19 + 2^7) through
+    ne_chain_run32 against its three separate calls."""
+    import numpy as np
     import torch
     from paper_1509_03838_amd import ne
 
@@ -1005,6 +1008,42 @@ def w32_line(args, wl):
     t_fplain32, okp = fused("plain", 32)
     if not (same and ok64 and ok32 and okp):
         raise SystemExit("w32: the 32-bit, 64-bit, fused and plain results differ")
+
+    # a series in 32-bit words: one call against three
+    sops = wl.chain_series(wl.rng(wl.SEED_BASE + 12), n, ("add", "conv", "perm", "add"), bits=8,
+                           K=K)
+    chain = []
+    for op, gv, sc in sops:
+        dg = torch.from_numpy(np.ascontiguousarray(gv)).to(dev)
+        if op == "add":
+            ge = torch.empty_like(dg)
+            ne.entangle_operand32(dg, ge, l32)
+            dg = ge
+        chain.append(ne.ChainOp(op, dg, sc, operand_bits=8))
+    torch.cuda.synchronize()
+    sno, _ = ne.chain_check(M, 8, n, chain, w=32)
+    s_one = [torch.empty(sno, dtype=torch.int32, device=dev) for _ in range(M)]
+    s_three = [torch.empty(sno, dtype=torch.int32, device=dev) for _ in range(M)]
+    s_delta = [torch.empty(sno, dtype=torch.int32, device=dev) for _ in range(M)]
+    ws_run = torch.empty(ne.chain_run_workspace_size(M, n, chain, w=32) + 256, dtype=torch.uint8,
+                         device=dev)
+    ws_run = ws_run[(-ws_run.data_ptr()) % 256:]
+    ws_apply = torch.empty(ne.chain_workspace_size(M, n, chain, w=32) + 256, dtype=torch.uint8,
+                           device=dev)
+    ws_apply = ws_apply[(-ws_apply.data_ptr()) % 256:]
+
+    def series_one():
+        ne.chain_run(cd, chain, s_one, lost, workspace=ws_run, stream=stream, w=32)
+
+    def series_three():
+        ne.entangle32(cd, e32, l32, stream=stream)
+        ne.chain_apply(e32, chain, s_delta, mask=mask, workspace=ws_apply, stream=stream, w=32)
+        ne.extract_recover32([s_delta[0], None, s_delta[2]], lost, s_three, l32, stream=stream)
+
+    t_series1 = timed(series_one)
+    t_series3 = timed(series_three)
+    if not all(torch.equal(a, b) for a, b in zip(s_one, s_three)):
+        raise SystemExit("w32: the series' one-call and three-call results differ")
     # algorithmic HBM bytes of the per-step launches (two streams computed)
     def nbytes(word):
         return (M * n * (4 + word) + (M - 1) * (n + no) * word + K * 4 +
@@ -1032,7 +1071,11 @@ def w32_line(args, wl):
                       "per_step_alg_bytes": {"w32": b32, "w64": b64},
                       "per_step_hbm_GBps_w32": round(b32 / (t32 * 1e-3) / 1e9, 1),
                       "speedup_w32_vs_w64": {"fused": round(t_fused64 / t_fused32, 3),
-                                             "per_step": round(t64 / t32, 3)}},
+                                             "per_step": round(t64 / t32, 3)},
+                      "series_w32": {"recipe": "add -> conv (16 taps) -> perm -> add, "
+                                               "8-bit operands, stream 1 lost",
+                                     "ms_per_step": {"ne_chain_run32": round(t_series1, 4),
+                                                     "three_calls": round(t_series3, 4)}}},
     }
     print(json.dumps(line), flush=True)
 

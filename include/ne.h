@@ -466,8 +466,11 @@ ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *
  * [3, NE_MAX_M32]); ne_chain_workspace_size32 counts int32 intermediates;
  * ne_chain_apply32 runs the series on int32 streams modulo 2^32 with the
  * operations of ne_lsb_apply32 (every operand int32; an added or
- * subtracted vector entangled by ne_entangle_operand32). Arguments and
- * errors otherwise as the 64-bit calls.
+ * subtracted vector entangled by ne_entangle_operand32). ne_chain_run32
+ * (+ ne_chain_run_workspace_size32) is ne_chain_run in these words: int32
+ * samples in, int32 recovered outputs out (|d| <= D of ne_params(M, 32)),
+ * l of ne_params(M, 32), the same passes (convolutions never write rows in
+ * this width). Arguments and errors otherwise as the 64-bit calls.
  */
 ne_status ne_chain_check32(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
                            int32_t n_ops, int64_t *n_out, int64_t *bound);
@@ -477,6 +480,11 @@ ne_status ne_chain_apply32(int32_t M, int64_t n_in, const int32_t *const *eps,
                            const ne_chain_op *ops, int32_t n_ops, int32_t *const *delta,
                            int64_t n_out, uint32_t stream_mask, void *workspace,
                            size_t workspace_bytes, ne_stream stream);
+ne_status ne_chain_run_workspace_size32(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                        int32_t n_ops, size_t *bytes);
+ne_status ne_chain_run32(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
+                         int32_t n_ops, int32_t lost, int32_t *const *dhat, int64_t n_out,
+                         void *workspace, size_t workspace_bytes, ne_stream stream);
 
 /* ------------------------------------------------------------------------
  * Entangled integer matrix product: the multiplication operator of eq. (2)

@@ -281,6 +281,23 @@ struct Words64 {
     using In = PtrsCI64;
     using Out = PtrsI64;
     static constexpr bool kRows = true;  // convolutions can write rows
+    static constexpr int kWidth = 64;
+    static constexpr int kGroupMax = kMaxM;
+    static void seg_entangle(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                             const Segment &seg, const Out &y, uint32_t *err, hipStream_t s)
+    {
+        launch_segment_entangle(M, l, n, count, c, seg, y, err, s);
+    }
+    static void seg_extract(int M, int l, int64_t n, bool entangle, const In &in,
+                            const PtrsI32 &c, const Segment &seg, const Out &out, uint32_t *err,
+                            hipStream_t s)
+    {
+        launch_segment_extract(M, l, n, entangle, in, c, seg, out, err, s);
+    }
+    static void extract(int M, int l, int64_t n, const In &in, const Out &out, hipStream_t s)
+    {
+        launch_extract(M, l, n, in, out, s);
+    }
     static ne_status conv_rows(const ne_chain_op &o, int count, int64_t n, const In &cur,
                                int64_t *rows, hipStream_t s)
     {
@@ -333,6 +350,23 @@ struct Words32 {
     using In = PtrsI32;
     using Out = PtrsW32;
     static constexpr bool kRows = false;
+    static constexpr int kWidth = 32;
+    static constexpr int kGroupMax = NE_MAX_M32;
+    static void seg_entangle(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                             const Segment &seg, const Out &y, uint32_t *err, hipStream_t s)
+    {
+        launch_segment_entangle32(M, l, n, count, c, seg, y, err, s);
+    }
+    static void seg_extract(int M, int l, int64_t n, bool entangle, const In &in,
+                            const PtrsI32 &c, const Segment &seg, const Out &out, uint32_t *err,
+                            hipStream_t s)
+    {
+        launch_segment_extract32(M, l, n, entangle, in, c, seg, out, err, s);
+    }
+    static void extract(int M, int l, int64_t n, const In &in, const Out &out, hipStream_t s)
+    {
+        launch_extract32(M, l, n, in, out, s);
+    }
     static ne_status conv_rows(const ne_chain_op &, int, int64_t, const In &, int32_t *,
                                hipStream_t)
     {
@@ -484,12 +518,13 @@ ne_status apply_w(int32_t M, int64_t n_in, const typename T::W *const *eps,
 
 // ------------------------------------------------ the whole method on a series
 
-// Workspace of ne_chain_run: two buffers of M planes, each as long as the
-// longest intermediate -- every stage's output but the last, and the
-// entangled inputs when the first stage cannot entangle them on load -- or
-// nothing when the series is one run of element-wise operations.
+// Workspace of ne_chain_run: two buffers of M planes of words of `word`
+// bytes, each as long as the longest intermediate -- every stage's output
+// but the last, and the entangled inputs when the first stage cannot
+// entangle them on load -- or nothing when the series is one run of
+// element-wise operations.
 ne_status run_workspace(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t n_ops,
-                        size_t *bytes)
+                        size_t word, size_t *bytes)
 {
     int64_t longest = 0;
     const ne_status st = walk(n_in, ops, n_ops, nullptr, &longest);
@@ -498,18 +533,21 @@ ne_status run_workspace(int32_t M, int64_t n_in, const ne_chain_op *ops, int32_t
     const int ns = split_stages(ops, n_ops, n_in, stages);
     if (!stages[0].seg) longest = std::max(longest, n_in);
     const bool need = ns > 1 || !stages[0].seg;
-    *bytes = need ? 2 * (size_t)M * align_up((size_t)longest * sizeof(int64_t)) : 0;
+    *bytes = need ? 2 * (size_t)M * align_up((size_t)longest * word) : 0;
     return NE_OK;
 }
 
-// Entangle, run the series on every computed stream, extract and recover.
-// Computed streams in slot order: slot t is stream (r + 1 + t) mod M, the
-// order recovery reads (slot M - 1, stream r, only when nothing was lost).
+// Entangle, run the series on every computed stream, extract and recover,
+// in words of T's width. Computed streams in slot order: slot t is stream
+// (r + 1 + t) mod M, the order recovery reads (slot M - 1, stream r, only
+// when nothing was lost).
+template <typename T>
 ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
-                    int32_t n_ops, int32_t lost, int64_t *const *dhat, int64_t n_out,
+                    int32_t n_ops, int32_t lost, typename T::W *const *dhat, int64_t n_out,
                     void *workspace, size_t workspace_bytes, ne_stream stream)
 {
-    if (M < 3 || M > kMaxM || !c || !dhat) return NE_EINVAL;
+    using W = typename T::W;
+    if (M < 3 || M > T::kGroupMax || !c || !dhat) return NE_EINVAL;
     if (lost < -1 || lost >= M) return NE_EFAILIDX;
     int64_t want = 0;
     ne_status st = walk(n_in, ops, n_ops, &want, nullptr);
@@ -523,9 +561,9 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
     for (int m = 0; m < M; ++m)
         if ((!c[m] && n_in > 0) || (!dhat[m] && n_out > 0)) return NE_EINVAL;
     int32_t l = 0;
-    if (ne_params(M, 64, &l, nullptr, nullptr) != NE_OK) return NE_ERANGE;
+    if (ne_params(M, T::kWidth, &l, nullptr, nullptr) != NE_OK) return NE_ERANGE;
     size_t need = 0;
-    st = run_workspace(M, n_in, ops, n_ops, &need);
+    st = run_workspace(M, n_in, ops, n_ops, sizeof(W), &need);
     if (st != NE_OK) return st;
     if (need > 0 && (!workspace || workspace_bytes < need || (uintptr_t)workspace % kWsAlign))
         return NE_EINVAL;
@@ -536,7 +574,7 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
     const int r = lost >= 0 ? lost : 0;
     const int count = lost >= 0 ? M - 1 : M;  // computed streams
     PtrsI32 cr{};  // the int32 streams from r on: slot t entangles cr[t + 1] with cr[t]
-    PtrsI64 out{};
+    typename T::Out out{};
     for (int t = 0; t < M; ++t) {
         cr.p[t] = c[(r + t) % M];
         out.p[t] = dhat[(r + 1 + t) % M];
@@ -546,16 +584,16 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
     const size_t plane = need / (2 * (size_t)M);
     unsigned char *ws = (unsigned char *)workspace;
     auto buffer = [&](int b) {
-        PtrsI64 p{};
-        for (int t = 0; t < count; ++t) p.p[t] = (int64_t *)(ws + ((size_t)b * M + t) * plane);
+        typename T::Out p{};
+        for (int t = 0; t < count; ++t) p.p[t] = (W *)(ws + ((size_t)b * M + t) * plane);
         return p;
     };
-    PtrsCI64 cur{};
+    typename T::In cur{};
     if (!stages[0].seg) {
         // a first stage that cannot entangle on load: the entangled words
         // first, into buffer 1 (stage 0 writes buffer 0)
-        const PtrsI64 e = buffer(1);
-        launch_segment_entangle(M, l, n_in, count, cr, Segment{}, e, err, s);
+        const typename T::Out e = buffer(1);
+        T::seg_entangle(M, l, n_in, count, cr, Segment{}, e, err, s);
         for (int t = 0; t < count; ++t) cur.p[t] = e.p[t];
     }
     int rows_in = 0;  // > 0: the current input is in rows of that many words
@@ -565,21 +603,21 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
         if (last && g.seg) {
             // the last run with the recovery (and, as the only stage, the
             // entanglement) in the same pass
-            launch_segment_extract(M, l, g.n_in, first, cur, cr, make_segment(ops, g, rows_in), out,
-                                   err, s);
+            T::seg_extract(M, l, g.n_in, first, cur, cr, make_segment(ops, g, rows_in), out, err,
+                           s);
             return launch_status();
         }
-        const bool to_rows = rows_after(ops, stages, ns, k, count);
-        PtrsI64 dst = last ? out : buffer(k & 1);
+        const bool to_rows = T::kRows && rows_after(ops, stages, ns, k, count);
+        typename T::Out dst = last ? out : buffer(k & 1);
         if (g.n_out > 0) {
             if (first && g.seg)
-                launch_segment_entangle(M, l, g.n_in, count, cr, make_segment(ops, g), dst, err, s);
+                T::seg_entangle(M, l, g.n_in, count, cr, make_segment(ops, g), dst, err, s);
             else if (g.seg)
-                launch_segment<int64_t>(count, g.n_in, cur, dst, make_segment(ops, g, rows_in), s);
+                launch_segment<W>(count, g.n_in, cur, dst, make_segment(ops, g, rows_in), s);
             else if (to_rows)
-                Words64::conv_rows(ops[g.i], count, g.n_in, cur, dst.p[0], s);
+                T::conv_rows(ops[g.i], count, g.n_in, cur, dst.p[0], s);
             else
-                Words64::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
+                T::launch(ops[g.i], count, g.n_in, cur, dst, g.n_out, s);
             st = launch_status();
             if (st != NE_OK) return st;
         }
@@ -587,9 +625,9 @@ ne_status chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_c
         for (int t = 0; t < count; ++t) cur.p[t] = dst.p[t];
     }
     // the last stage wrote the computed streams' words into dhat: recover in place
-    PtrsCI64 in{};
+    typename T::In in{};
     for (int t = 0; t < M - 1; ++t) in.p[t] = out.p[t];
-    launch_extract(M, l, n_out, in, out, s);
+    T::extract(M, l, n_out, in, out, s);
     return launch_status();
 }
 
@@ -622,15 +660,15 @@ ne_status ne_chain_run_workspace_size(int32_t M, int64_t n_in, const ne_chain_op
                                       int32_t n_ops, size_t *bytes)
 {
     if (M < 3 || M > kMaxM || !bytes) return NE_EINVAL;
-    return run_workspace(M, n_in, ops, n_ops, bytes);
+    return run_workspace(M, n_in, ops, n_ops, sizeof(int64_t), bytes);
 }
 
 ne_status ne_chain_run(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
                        int32_t n_ops, int32_t lost, int64_t *const *dhat, int64_t n_out,
                        void *workspace, size_t workspace_bytes, ne_stream stream)
 {
-    return chain_run(M, n_in, c, ops, n_ops, lost, dhat, n_out, workspace, workspace_bytes,
-                     stream);
+    return chain_run<Words64>(M, n_in, c, ops, n_ops, lost, dhat, n_out, workspace,
+                              workspace_bytes, stream);
 }
 
 ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *eps,
@@ -660,6 +698,21 @@ ne_status ne_chain_apply32(int32_t M, int64_t n_in, const int32_t *const *eps,
 {
     return apply_w<Words32>(M, n_in, eps, ops, n_ops, delta, n_out, stream_mask, workspace,
                             workspace_bytes, stream);
+}
+
+ne_status ne_chain_run_workspace_size32(int32_t M, int64_t n_in, const ne_chain_op *ops,
+                                        int32_t n_ops, size_t *bytes)
+{
+    if (M < 3 || M > NE_MAX_M32 || !bytes) return NE_EINVAL;
+    return run_workspace(M, n_in, ops, n_ops, sizeof(int32_t), bytes);
+}
+
+ne_status ne_chain_run32(int32_t M, int64_t n_in, const int32_t *const *c, const ne_chain_op *ops,
+                         int32_t n_ops, int32_t lost, int32_t *const *dhat, int64_t n_out,
+                         void *workspace, size_t workspace_bytes, ne_stream stream)
+{
+    return chain_run<Words32>(M, n_in, c, ops, n_ops, lost, dhat, n_out, workspace,
+                              workspace_bytes, stream);
 }
 
 

@@ -194,6 +194,18 @@ void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const in
                  int64_t n_operand, int64_t scalar, const PtrsW32 &y, int64_t n_out,
                  hipStream_t s);
 
+// The series in one call in 32-bit words: as launch_segment_entangle and
+// launch_segment_extract (no rows), words and outputs int32 modulo 2^32,
+// M in [3, NE_MAX_M32]; launch_extract32 recovers in place as
+// ne_extract_recover32 does (in: the M - 1 slots from r + 1 on).
+void launch_segment_entangle32(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                               const Segment &seg, const PtrsW32 &y, uint32_t *err, hipStream_t s);
+void launch_segment_extract32(int M, int l, int64_t n, bool entangle, const PtrsI32 &in,
+                              const PtrsI32 &c, const Segment &seg, const PtrsW32 &out,
+                              uint32_t *err, hipStream_t s);
+void launch_extract32(int M, int l, int64_t n, const PtrsI32 &in, const PtrsW32 &out,
+                      hipStream_t s);
+
 // Checksum method.
 void launch_checksum(int M, int64_t n, const PtrsI32 &c, int64_t *rsum, hipStream_t s);
 void launch_checksum_recover(int count, int64_t n, const PtrsCI64 &d, const int64_t *e,

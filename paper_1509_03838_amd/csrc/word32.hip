@@ -391,7 +391,124 @@ void map32(int count, int64_t n, const PtrsI32 &x, const int32_t *g, const PtrsW
                            dim3(kBlock), 0, s, x, g, y, n, sv);
 }
 
+// ------------------------------------------ series in one call (w = 32)
+
+// Slots 0..R-1 of a series' 32-bit entangled words at source position src
+// from the int32 streams c.p[u] = stream r + u (mod M): slot t is
+// c_{r+1+t} + 2^l c_{r+t} (mod 2^32), each stream read once; src < 0 gives
+// zeros.
+template <int M, int R>
+__device__ __forceinline__ void entangle_slots32(const PtrsI32 &c, int64_t src, int l,
+                                                 int32_t (&e)[R])
+{
+    int32_t v[M];
+#pragma unroll
+    for (int u = 0; u < M; ++u) v[u] = 0;
+    if (src >= 0) {
+#pragma unroll
+        for (int u = 0; u < M; ++u) v[u] = c.p[u][src];
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) e[t] = ent32(v[(t + 1) % M], v[t], l);
+}
+
+__device__ __forceinline__ int64_t gather_source(const Segment &seg, int64_t i, int64_t n,
+                                                 bool &bad)
+{
+    if (!seg.perm) return i;
+    const int64_t src = seg.p[i];
+    if (src < 0 || src >= n) {
+        bad = true;
+        return -1;
+    }
+    return src;
+}
+
+// A series' first run of element-wise operations with the entanglement on
+// load (see launch_segment_entangle32).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_segment_entangle32(PtrsI32 c, Segment seg, PtrsW32 y,
+                                                               int count, int64_t n, int l,
+                                                               uint32_t *err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        int32_t e[M];
+        entangle_slots32<M, M>(c, gather_source(seg, i, n, bad), l, e);
+        segment_ops_all<int32_t, M>(e, seg, i);
+#pragma unroll
+        for (int t = 0; t < M; ++t)
+            if (t < count) y.p[t][i] = e[t];
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
+// A series' last run of element-wise operations with the recovery (see
+// launch_segment_extract32).
+template <int M, bool ENT>
+__global__ __launch_bounds__(kBlock) void k_segment_extract32(PtrsI32 in, PtrsI32 c, Segment seg,
+                                                              PtrsW32 out, int64_t n, int l,
+                                                              uint32_t *err)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t src = gather_source(seg, i, n, bad);
+        int32_t a[M - 1], o[M];
+        if (ENT) {
+            entangle_slots32<M, M - 1>(c, src, l, a);
+        } else {
+#pragma unroll
+            for (int t = 0; t < M - 1; ++t) a[t] = src >= 0 ? in.p[t][src] : 0;
+        }
+        segment_ops_all<int32_t, M - 1>(a, seg, i);
+        recover32<M>(a, o, l);
+#pragma unroll
+        for (int t = 0; t < M; ++t) out.p[t][i] = o[t];
+    }
+    if (bad && err) atomicOr(err, NE_FLAG_PERM_INDEX);
+}
+
+template <int M>
+void segment_entangle32_m(int l, int64_t n, int count, const PtrsI32 &c, const Segment &seg,
+                          const PtrsW32 &y, uint32_t *err, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_segment_entangle32<M>, dim3(grid_for(n)), dim3(kBlock), 0, s, c, seg, y,
+                       count, n, l, err);
+}
+
+template <int M>
+void segment_extract32_m(int l, int64_t n, bool entangle, const PtrsI32 &in, const PtrsI32 &c,
+                         const Segment &seg, const PtrsW32 &out, uint32_t *err, hipStream_t s)
+{
+    if (entangle)
+        hipLaunchKernelGGL((k_segment_extract32<M, true>), dim3(grid_for(n)), dim3(kBlock), 0, s,
+                           in, c, seg, out, n, l, err);
+    else
+        hipLaunchKernelGGL((k_segment_extract32<M, false>), dim3(grid_for(n)), dim3(kBlock), 0, s,
+                           in, c, seg, out, n, l, err);
+}
+
 }  // namespace
+
+void launch_segment_entangle32(int M, int l, int64_t n, int count, const PtrsI32 &c,
+                               const Segment &seg, const PtrsW32 &y, uint32_t *err, hipStream_t s)
+{
+    NE_DISPATCH_M32(M, segment_entangle32_m, l, n, count, c, seg, y, err, s);
+}
+
+void launch_segment_extract32(int M, int l, int64_t n, bool entangle, const PtrsI32 &in,
+                              const PtrsI32 &c, const Segment &seg, const PtrsW32 &out,
+                              uint32_t *err, hipStream_t s)
+{
+    NE_DISPATCH_M32(M, segment_extract32_m, l, n, entangle, in, c, seg, out, err, s);
+}
+
+void launch_extract32(int M, int l, int64_t n, const PtrsI32 &in, const PtrsW32 &out, hipStream_t s)
+{
+    NE_DISPATCH_M32(M, extract32_m, l, n, in, out, s);
+}
 
 void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const int32_t *operand,
                  int64_t n_operand, int64_t scalar, const PtrsW32 &y, int64_t n_out,

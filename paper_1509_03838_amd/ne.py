@@ -34,7 +34,7 @@ EXPORTS = ("ne_strerror", "ne_last_hip_error", "ne_version", "ne_params", "ne_en
            "ne_extract_recover32", "ne_chain_check32", "ne_chain_workspace_size32",
            "ne_chain_apply32", "ne_device_flags", "ne_chain_apply_noalloc", "ne_stream_widen",
            "ne_mfma_i8_peak", "ne_wait_streams", "ne_stream_delay", "ne_chain_run_workspace_size",
-           "ne_chain_run")
+           "ne_chain_run", "ne_chain_run_workspace_size32", "ne_chain_run32")
 
 FUSED_MAX_M = 8
 MODES = {"entangled": 0, "plain": 1, "plain_same": 2, "checksum": 3, "checksum_same": 4}
@@ -125,6 +125,10 @@ def load() -> ctypes.CDLL:
                                                ctypes.POINTER(ctypes.c_size_t)]),
         "ne_chain_run": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _i32, _P, _i64,
                                 _P, ctypes.c_size_t, _P]),
+        "ne_chain_run_workspace_size32": (_i32, [_i32, _i64, ctypes.POINTER(ChainOpC), _i32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+        "ne_chain_run32": (_i32, [_i32, _i64, _P, ctypes.POINTER(ChainOpC), _i32, _i32, _P, _i64,
+                                  _P, ctypes.c_size_t, _P]),
         "ne_stream_widen": (_i32, [_P, _i64, _P, _P]),
         "ne_wait_streams": (_i32, [_i32, _P, _i64, ctypes.POINTER(_i32)]),
         "ne_stream_delay": (_i32, [_i64, _P]),
@@ -641,24 +645,24 @@ def chain_apply(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence, mask: in
                                    ws_bytes, _stream(stream)))
 
 
-def chain_run_workspace_size(M: int, n_in: int, ops: Sequence[ChainOp]) -> int:
+def chain_run_workspace_size(M: int, n_in: int, ops: Sequence[ChainOp], w: int = 64) -> int:
     sz = ctypes.c_size_t()
-    _check("ne_chain_run_workspace_size",
-           load().ne_chain_run_workspace_size(M, n_in, _chain_c(ops), len(ops), ctypes.byref(sz)))
+    fn = "ne_chain_run_workspace_size32" if w == 32 else "ne_chain_run_workspace_size"
+    _check(fn, getattr(load(), fn)(M, n_in, _chain_c(ops), len(ops), ctypes.byref(sz)))
     return sz.value
 
 
 def chain_run(c: Sequence, ops: Sequence[ChainOp], dhat: Sequence, lost: int = -1,
-              workspace=None, stream=None):
+              workspace=None, stream=None, w: int = 64):
     """The whole method on a series: entangle the int32 streams c, run the
     series on every stream but `lost`, recover all outputs into dhat (int64,
-    one per stream); entanglement and recovery fused into the first and last
-    runs of element-wise operations where the series allows (ne_chain_run).
-    workspace: a uint8 device tensor of chain_run_workspace_size bytes
-    (allocated here if None)."""
+    or int32 with w = 32; one per stream); entanglement and recovery fused
+    into the first and last runs of element-wise operations where the series
+    allows (ne_chain_run, ne_chain_run32). workspace: a uint8 device tensor
+    of chain_run_workspace_size bytes (allocated here if None)."""
     import torch
     _dtype(c, torch.int32, "c")
-    _dtype(dhat, torch.int64, "dhat")
+    _dtype(dhat, torch.int32 if w == 32 else torch.int64, "dhat")
     M = len(c)
     if len(dhat) != M:
         raise ValueError("c and dhat differ in length")
@@ -669,15 +673,16 @@ def chain_run(c: Sequence, ops: Sequence[ChainOp], dhat: Sequence, lost: int = -
     for o in ops:
         n = n_out(o.op, n, o.n_operand)
     _lengths("dhat", dhat, n, exact=False)
-    ws_bytes = chain_run_workspace_size(M, n_in, ops)
+    ws_bytes = chain_run_workspace_size(M, n_in, ops, w)
     if workspace is not None and workspace.numel() < ws_bytes:
         raise ValueError(f"workspace holds {workspace.numel()} bytes, the series needs {ws_bytes}")
     if workspace is None and ws_bytes:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
         workspace = workspace[(-workspace.data_ptr()) % 256:]
-    _check("ne_chain_run", load().ne_chain_run(M, n_in, _ptr_array(c), _chain_c(ops), len(ops),
-                                               int(lost), _ptr_array(dhat), n, _ptr(workspace),
-                                               ws_bytes, _stream(stream)))
+    fn = "ne_chain_run32" if w == 32 else "ne_chain_run"
+    _check(fn, getattr(load(), fn)(M, n_in, _ptr_array(c), _chain_c(ops), len(ops), int(lost),
+                                   _ptr_array(dhat), n, _ptr(workspace), ws_bytes,
+                                   _stream(stream)))
 
 
 def chain_apply_noalloc(eps: Sequence, ops: Sequence[ChainOp], delta: Sequence,

@@ -388,6 +388,34 @@ def test_series_run_workspace_and_checks():
     assert L.ne_chain_run(3, n, c, arr, 1, -1, out, n + 63, FAKE + 8, ws, None) == -1
 
 
+def test_series_run32_workspace_and_checks():
+    """ne_chain_run32: the same passes in int32 words (planes of 4-byte
+    words), groups of up to NE_MAX_M32 = 17 streams; bad arguments refused
+    before the device is touched."""
+    n = 1000
+    up = lambda x: (x + 255) // 256 * 256
+    run = _series(("perm", n, 0, 0), ("add", n, 0, 4), ("scale", 0, 3, 0))
+    assert ne.chain_run_workspace_size(3, n, run, w=32) == 0
+    mixed = _series(("add", n, 0, 4), ("scale", 0, 3, 0), ("conv", 16, 0, 4),
+                    ("perm", n + 15, 0, 0), ("add", n + 15, 0, 4))
+    assert ne.chain_run_workspace_size(5, n, mixed, w=32) == 2 * 5 * up(4 * (n + 15))
+    assert ne.chain_run_workspace_size(17, n, mixed, w=32) == 2 * 17 * up(4 * (n + 15))
+    with pytest.raises(ne.NeError) as e:
+        ne.chain_run_workspace_size(18, n, mixed, w=32)
+    assert e.value.status == -1
+    L = ne.load()
+    c = ne._ptr_array([FAKE + 64 * m for m in range(3)])
+    out = ne._ptr_array([FAKE + (1 << 20) + 64 * m for m in range(3)])
+    conv = _series(("conv", 16, 0, 4))
+    arr = ne._chain_c(conv)
+    ws = ne.chain_run_workspace_size(3, n, conv, w=32)
+    assert ws == 2 * 3 * up(4 * (n + 15))
+    assert L.ne_chain_run32(3, n, c, arr, 1, -1, out, n + 15, None, 0, None) == -1    # no workspace
+    assert L.ne_chain_run32(3, n, c, arr, 1, -1, out, n + 14, FAKE, ws, None) == -1   # wrong n_out
+    assert L.ne_chain_run32(3, n, c, arr, 1, 3, out, n + 15, FAKE, ws, None) == -3    # lost index
+    assert L.ne_chain_run32(18, n, c, arr, 1, -1, out, n + 15, FAKE, ws, None) == -1  # M > 17
+
+
 def test_series_workspace_size():
     """Two buffers of M streams of the longest intermediate (256-byte
     rounded); nothing for a single operation. ne_chain_apply refuses a

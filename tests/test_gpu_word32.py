@@ -341,11 +341,9 @@ SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale")
           ("outer", "sub", "perm")]
 
 
-def series32(c, ops, lost, bits):
-    """entangle32 -> the series on every stream but `lost` (ne_chain_apply32)
-    -> extract32; returns (recovered outputs, last-stage words)."""
-    M, n = c.shape
-    l = ne.params(M, 32)[0]
+def device_ops32(ops, l, bits):
+    """ChainOps with int32 device operands; an added or subtracted vector
+    entangled with itself in 32-bit words."""
     dops = []
     for op, g, s in ops:
         if op == "scale":
@@ -357,6 +355,15 @@ def series32(c, ops, lost, bits):
             ne.entangle_operand32(dg, ge, l)
             dg = ge
         dops.append(ne.ChainOp(op, dg, s, operand_bits=bits))
+    return dops
+
+
+def series32(c, ops, lost, bits):
+    """entangle32 -> the series on every stream but `lost` (ne_chain_apply32)
+    -> extract32; returns (recovered outputs, last-stage words)."""
+    M, n = c.shape
+    l = ne.params(M, 32)[0]
+    dops = device_ops32(ops, l, bits)
     no, _ = ne.chain_check(M, bits, n, dops, w=32)
     cd = [dev32(r) for r in c]
     eps = empty32(M, n)
@@ -387,3 +394,32 @@ def test_word32_series_matches_oracle(recipe, M):
         assert np.array_equal(dhat, want), (recipe, M, lost)
         live = [m for m in range(M) if m != lost]
         assert np.array_equal(delta[live], last[live]), (recipe, M, lost)
+
+
+WHOLE32 = SERIES + [("scale", "add", "sub"), ("perm",), ("perm", "mul"), ("conv", "scale", "perm"),
+                    ("add", "conv")]
+
+
+@pytest.mark.parametrize("recipe", WHOLE32)
+@pytest.mark.parametrize("M", [3, 5, 8, 17])
+def test_word32_series_in_one_call(recipe, M):
+    """ne_chain_run32: int32 samples in, recovered int32 outputs out, the
+    entanglement and recovery folded into the series' first and last runs of
+    element-wise operations (one pass for a single run); every recipe against
+    the oracle and the three-call path, with and without a lost stream, up to
+    the widest group of 32-bit words (M = 17)."""
+    n = 3001
+    rng = wl.rng(9950 + M + len(recipe))
+    c = wl.uniform_i32(rng, -2, 2, (M, n))
+    ops = wl.chain_series(rng, n, recipe, bits=2, K=9)
+    want = oracle.chain(c, ops)
+    l = ne.params(M, 32)[0]
+    dops = device_ops32(ops, l, 2)
+    no, _ = ne.chain_check(M, 2, n, dops, w=32)
+    cd = [dev32(r) for r in c]
+    for lost in (-1, 0, M - 1):
+        dhat = empty32(M, no, fill=POISON)
+        ne.chain_run(cd, dops, dhat, lost, w=32)
+        assert np.array_equal(host(dhat), want), (recipe, M, lost)
+        three, _ = series32(c, ops, lost, 2)
+        assert np.array_equal(three, want), (recipe, M, lost)
