@@ -469,8 +469,8 @@ ne_status ne_chain_apply_noalloc(int32_t M, int64_t n_in, const int64_t *const *
  * subtracted vector entangled by ne_entangle_operand32). ne_chain_run32
  * (+ ne_chain_run_workspace_size32) is ne_chain_run in these words: int32
  * samples in, int32 recovered outputs out (|d| <= D of ne_params(M, 32)),
- * l of ne_params(M, 32), the same passes (convolutions never write rows in
- * this width). Arguments and errors otherwise as the 64-bit calls.
+ * l of ne_params(M, 32), the same passes. Arguments and errors otherwise
+ * as the 64-bit calls.
  */
 ne_status ne_chain_check32(int32_t M, int32_t in_bits, int64_t n_in, const ne_chain_op *ops,
                            int32_t n_ops, int64_t *n_out, int64_t *bound);

@@ -206,9 +206,9 @@ __global__ __launch_bounds__(256) void k_segment(In x, Out y, int64_t n, Segment
 // each position (Segment::rows = R): every lane gathers all R words of its
 // source position from one row, so a random position costs one fetch of R
 // words rather than R fetches of one.
-template <int R>
-__global__ __launch_bounds__(256) void k_segment_rows(const int64_t *x, PtrsI64 y, int64_t n,
-                                                      Segment seg, uint32_t *err)
+template <typename W, typename Out, int R>
+__global__ __launch_bounds__(256) void k_segment_rows(const W *x, Out y, int64_t n, Segment seg,
+                                                      uint32_t *err)
 {
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
@@ -221,10 +221,10 @@ __global__ __launch_bounds__(256) void k_segment_rows(const int64_t *x, PtrsI64 
                 src = -1;
             }
         }
-        int64_t v[R];
+        W v[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) v[t] = src >= 0 ? x[src * R + t] : 0;
-        segment_ops_all<int64_t, R>(v, seg, i);
+        segment_ops_all<W, R>(v, seg, i);
 #pragma unroll
         for (int t = 0; t < R; ++t) y.p[t][i] = v[t];
     }
@@ -234,34 +234,36 @@ __global__ __launch_bounds__(256) void k_segment_rows(const int64_t *x, PtrsI64 
 // Streams a convolution may interleave into rows for the gather after it.
 constexpr int kMaxRows = 8;
 
-void launch_segment_rows(int count, int64_t n, const int64_t *x, const PtrsI64 &y,
-                         const Segment &seg, hipStream_t s)
+template <typename W, typename Out>
+void launch_segment_rows(int count, int64_t n, const W *x, const Out &y, const Segment &seg,
+                         hipStream_t s)
 {
     int64_t g = (n + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
     const dim3 grid((unsigned)g), block(256);
     uint32_t *err = device_flag_word();
+#define NE_ROWS_CASE(R)                                                                   \
+    hipLaunchKernelGGL((k_segment_rows<W, Out, R>), grid, block, 0, s, x, y, n, seg, err)
     switch (count) {  // 1..kMaxRows: rows_after admits no more
-    case 1: hipLaunchKernelGGL(k_segment_rows<1>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 2: hipLaunchKernelGGL(k_segment_rows<2>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 3: hipLaunchKernelGGL(k_segment_rows<3>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 4: hipLaunchKernelGGL(k_segment_rows<4>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 5: hipLaunchKernelGGL(k_segment_rows<5>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 6: hipLaunchKernelGGL(k_segment_rows<6>, grid, block, 0, s, x, y, n, seg, err); break;
-    case 7: hipLaunchKernelGGL(k_segment_rows<7>, grid, block, 0, s, x, y, n, seg, err); break;
-    default: hipLaunchKernelGGL(k_segment_rows<8>, grid, block, 0, s, x, y, n, seg, err); break;
+    case 1: NE_ROWS_CASE(1); break;
+    case 2: NE_ROWS_CASE(2); break;
+    case 3: NE_ROWS_CASE(3); break;
+    case 4: NE_ROWS_CASE(4); break;
+    case 5: NE_ROWS_CASE(5); break;
+    case 6: NE_ROWS_CASE(6); break;
+    case 7: NE_ROWS_CASE(7); break;
+    default: NE_ROWS_CASE(8); break;
     }
+#undef NE_ROWS_CASE
 }
 
 template <typename W, typename In, typename Out>
 void launch_segment(int count, int64_t n, const In &x, const Out &y, const Segment &seg,
                     hipStream_t s)
 {
-    if constexpr (std::is_same<W, int64_t>::value) {
-        if (seg.rows > 0) {
-            launch_segment_rows(count, n, x.p[0], y, seg, s);
-            return;
-        }
+    if (seg.rows > 0) {
+        launch_segment_rows<W>(count, n, x.p[0], y, seg, s);
+        return;
     }
     int64_t g = (n + 255) / 256;
     g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
@@ -349,7 +351,7 @@ struct Words32 {
     using W = int32_t;
     using In = PtrsI32;
     using Out = PtrsW32;
-    static constexpr bool kRows = false;
+    static constexpr bool kRows = true;  // convolutions can write rows
     static constexpr int kWidth = 32;
     static constexpr int kGroupMax = NE_MAX_M32;
     static void seg_entangle(int M, int l, int64_t n, int count, const PtrsI32 &c,
@@ -367,10 +369,13 @@ struct Words32 {
     {
         launch_extract32(M, l, n, in, out, s);
     }
-    static ne_status conv_rows(const ne_chain_op &, int, int64_t, const In &, int32_t *,
-                               hipStream_t)
+    static ne_status conv_rows(const ne_chain_op &o, int count, int64_t n, const In &cur,
+                               int32_t *rows, hipStream_t s)
     {
-        return NE_EUNSUP;
+        const int64_t n_out = o.op == NE_OP_CIRC ? n : n + o.n_operand - 1;
+        launch_conv32_rows(o.op, count, n, cur, (const int32_t *)o.operand, o.n_operand, n_out,
+                           rows, s);
+        return launch_status();
     }
     static ne_status launch(const ne_chain_op &o, int count, int64_t n, const In &cur,
                             const Out &dst, int64_t m, hipStream_t s)

@@ -195,7 +195,7 @@ void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const in
                  hipStream_t s);
 
 // The series in one call in 32-bit words: as launch_segment_entangle and
-// launch_segment_extract (no rows), words and outputs int32 modulo 2^32,
+// launch_segment_extract, words and outputs int32 modulo 2^32,
 // M in [3, NE_MAX_M32]; launch_extract32 recovers in place as
 // ne_extract_recover32 does (in: the M - 1 slots from r + 1 on).
 void launch_segment_entangle32(int M, int l, int64_t n, int count, const PtrsI32 &c,
@@ -205,6 +205,11 @@ void launch_segment_extract32(int M, int l, int64_t n, bool entangle, const Ptrs
                               uint32_t *err, hipStream_t s);
 void launch_extract32(int M, int l, int64_t n, const PtrsI32 &in, const PtrsW32 &out,
                       hipStream_t s);
+// A convolution kind (NE_OP_CONV, NE_OP_CIRC, NE_OP_XCORR) in 32-bit words
+// writing rows: stream t's output i at rows[i * count + t].
+void launch_conv32_rows(int32_t op, int count, int64_t n_in, const PtrsI32 &x,
+                        const int32_t *operand, int64_t n_operand, int64_t n_out, int32_t *rows,
+                        hipStream_t s);
 
 // Checksum method.
 void launch_checksum(int M, int64_t n, const PtrsI32 &c, int64_t *rsum, hipStream_t s);

@@ -290,7 +290,9 @@ struct ConvArgs32 {
     PtrsW32 y;
     const int32_t *g;
     int64_t n, K, n_out;
-    int32_t kind, pad_;
+    int32_t kind;
+    int32_t rows;  // 0: stream blockIdx.y's outputs to plane y.p[blockIdx.y]; > 0: to rows of
+                   // that many words at y.p[0] (stream t's output i at [i * rows + t])
 };
 
 __global__ __launch_bounds__(kBlock) void k_conv32(ConvArgs32 a)
@@ -329,11 +331,12 @@ __global__ __launch_bounds__(kBlock) void k_conv32(ConvArgs32 a)
             for (int q = 0; q < kQ; ++q) acc[q] += (uint32_t)sx[wb + q * kBlock] * gj;
         }
     }
-    int32_t *y = a.y.p[blockIdx.y];
+    int32_t *y = a.rows ? a.y.p[0] + blockIdx.y : a.y.p[blockIdx.y];
+    const int64_t stride = a.rows ? a.rows : 1;
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
         const int64_t t = t0 + q * kBlock + tid;
-        if (t < a.n_out) y[t] = (int32_t)acc[q];
+        if (t < a.n_out) y[t * stride] = (int32_t)acc[q];
     }
 }
 
@@ -458,6 +461,9 @@ __global__ __launch_bounds__(kBlock) void k_segment_extract32(PtrsI32 in, PtrsI3
         int32_t a[M - 1], o[M];
         if (ENT) {
             entangle_slots32<M, M - 1>(c, src, l, a);
+        } else if (seg.rows > 0) {
+#pragma unroll
+            for (int t = 0; t < M - 1; ++t) a[t] = src >= 0 ? in.p[0][src * seg.rows + t] : 0;
         } else {
 #pragma unroll
             for (int t = 0; t < M - 1; ++t) a[t] = src >= 0 ? in.p[t][src] : 0;
@@ -508,6 +514,19 @@ void launch_segment_extract32(int M, int l, int64_t n, bool entangle, const Ptrs
 void launch_extract32(int M, int l, int64_t n, const PtrsI32 &in, const PtrsW32 &out, hipStream_t s)
 {
     NE_DISPATCH_M32(M, extract32_m, l, n, in, out, s);
+}
+
+void launch_conv32_rows(int32_t op, int count, int64_t n_in, const PtrsI32 &x,
+                        const int32_t *operand, int64_t n_operand, int64_t n_out, int32_t *rows,
+                        hipStream_t s)
+{
+    const int kind =
+        op == NE_OP_CIRC ? kConvCircular : (op == NE_OP_XCORR ? kConvXcorr : kConvLinear);
+    PtrsW32 y{};
+    y.p[0] = rows;
+    ConvArgs32 a{x, y, operand, n_in, n_operand, n_out, kind, count};
+    hipLaunchKernelGGL(k_conv32, dim3((unsigned)((n_out + kTile - 1) / kTile), count),
+                       dim3(kBlock), 0, s, a);
 }
 
 void launch_op32(int32_t op, int count, int64_t n_in, const PtrsI32 &x, const int32_t *operand,

@@ -338,7 +338,9 @@ def test_fused_word32_benchmark_size():
 
 SERIES = [wl.CHAIN_RECIPE, ("conv", "conv"), ("scale", "perm", "inner", "scale"),
           ("perm", "add", "conv", "inner"), ("sub", "mul", "circ", "xcorr"),
-          ("outer", "sub", "perm")]
+          ("outer", "sub", "perm"),
+          # a convolution before a permutation-led run writes interleaved rows
+          ("conv", "perm", "conv", "perm", "add"), ("circ", "perm", "scale"), ("xcorr", "perm")]
 
 
 def device_ops32(ops, l, bits):
