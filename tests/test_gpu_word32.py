@@ -425,3 +425,23 @@ def test_word32_series_in_one_call(recipe, M):
         assert np.array_equal(host(dhat), want), (recipe, M, lost)
         three, _ = series32(c, ops, lost, 2)
         assert np.array_equal(three, want), (recipe, M, lost)
+
+
+@pytest.mark.parametrize("recipe,n", [(("conv", "scale"), 0), (("scale",), 1), (("perm",), 1),
+                                      (("conv",), 5), (("add", "perm"), 2),
+                                      (("conv", "perm"), 3)])
+def test_word32_series_in_one_call_edge_cases(recipe, n):
+    """ne_chain_run32 on empty and one- to five-sample streams, one-operation
+    series (no workspace), rows after a tiny convolution."""
+    M = 4
+    c = wl.uniform_i32(wl.rng(9980 + n), -2, 2, (M, n))
+    ops = wl.chain_series(wl.rng(9990 + n), n, recipe, bits=2, K=3)
+    want = oracle.chain(c, ops)
+    l = ne.params(M, 32)[0]
+    dops = device_ops32(ops, l, 2)
+    no, _ = ne.chain_check(M, 2, n, dops, w=32)
+    cd = [dev32(r) for r in c]
+    for lost in (-1, 2):
+        dhat = empty32(M, no, fill=POISON)
+        ne.chain_run(cd, dops, dhat, lost, w=32)
+        assert np.array_equal(host(dhat), want), (recipe, n, lost)
