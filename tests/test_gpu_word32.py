@@ -445,3 +445,51 @@ def test_word32_series_in_one_call_edge_cases(recipe, n):
         dhat = empty32(M, no, fill=POISON)
         ne.chain_run(cd, dops, dhat, lost, w=32)
         assert np.array_equal(host(dhat), want), (recipe, n, lost)
+
+
+def _conv_mod32(x, g, kind):
+    """The convolution kinds modulo 2^32 by definition (uint64 products and
+    sums wrap modulo 2^64, a multiple of 2^32)."""
+    xu = x.astype(np.int64).astype(np.uint64)
+    gu = g.astype(np.int64).astype(np.uint64)
+    n, K = x.size, g.size
+    if kind == "xcorr":
+        gu = gu[::-1].copy()
+    if kind == "circ":
+        y = np.zeros(n, dtype=np.uint64)
+        for j in range(K):
+            y += gu[j] * np.roll(xu, j)
+    else:
+        y = np.zeros(n + K - 1, dtype=np.uint64)
+        for j in range(K):
+            y[j:j + n] += gu[j] * xu
+    return (y & np.uint64(0xFFFFFFFF)).astype(np.int64)
+
+
+@pytest.mark.parametrize("case", ["one_wide", "all_wide", "second_chunk", "narrow"])
+@pytest.mark.parametrize("kind", ["conv", "circ", "xcorr"])
+def test_word32_convolution_tap_width(case, kind):
+    """The 32-bit convolution kinds on arbitrary 32-bit words (the whole
+    int32 range) against their definition modulo 2^32: one wide tap among
+    narrow ones, all taps wide, a wide tap in the second 1024-tap chunk only,
+    taps at the edges of 24 signed bits."""
+    rng = wl.rng(9970 + len(case) + len(kind))
+    n = 3000
+    x = wl.uniform_i32(rng, -(1 << 31), 1 << 31, (2, n))
+    if case == "one_wide":
+        g = wl.uniform_i32(rng, -100, 100, 8)
+        g[3] = (1 << 24) + 3
+    elif case == "all_wide":
+        g = wl.uniform_i32(rng, 1 << 23, 1 << 30, 5) * np.int32(-1)
+    elif case == "second_chunk":
+        g = wl.uniform_i32(rng, -(1 << 23), 1 << 23, 1100)
+        g[1050] = -(1 << 23) - 1
+    else:
+        g = np.array([-(1 << 23), (1 << 23) - 1, -1, 0, 1], dtype=np.int32)
+    eps = [dev32(r) for r in x]
+    no = ne.n_out(kind, n, g.size)
+    out = empty32(2, no, fill=POISON)
+    ne.lsb_apply32(kind, eps, dev32(g), out)
+    got = host(out) & 0xFFFFFFFF
+    for m in range(2):
+        assert np.array_equal(got[m], _conv_mod32(x[m], g, kind)), (case, kind, m)
