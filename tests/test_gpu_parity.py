@@ -366,3 +366,48 @@ def test_mfma_i8_peak_runs_and_reports_its_work():
         assert (s[4 * blocks:] == -7).all()
     with pytest.raises(ne.NeError):
         ne.mfma_i8_peak(sink, blocks, 12, True)  # varied rounds come in sets of 8
+
+
+def _conv_mod64(x, g, kind):
+    """The convolution kinds modulo 2^64 by definition (uint64 products and
+    sums wrap modulo 2^64)."""
+    xu = x.astype(np.uint64)
+    gu = g.astype(np.int64).astype(np.uint64)
+    n, K = x.size, g.size
+    if kind == "xcorr":
+        gu = gu[::-1].copy()
+    if kind == "circ":
+        y = np.zeros(n, dtype=np.uint64)
+        for j in range(K):
+            y += gu[j] * np.roll(xu, j)
+    else:
+        y = np.zeros(n + K - 1, dtype=np.uint64)
+        for j in range(K):
+            y[j:j + n] += gu[j] * xu
+    return y.astype(np.int64)
+
+
+@pytest.mark.parametrize("kind", ["conv", "circ", "xcorr"])
+def test_word64_convolution_full_range(kind):
+    """The 64-bit vector-ALU convolution (each word's low half staged as a
+    signed int32, its borrow moved into the high half) on words over the
+    whole int64 range -- low halves of exactly 2^31 and 2^31 - 1, the words
+    -2^63 and 2^63 - 1 among them -- with taps at the int32 extremes, against
+    its definition modulo 2^64; more than one 1024-tap chunk."""
+    rng = wl.rng(9960 + len(kind))
+    n, K = 3000, 1100
+    x = rng.integers(-(1 << 63), (1 << 63) - 1, (2, n), dtype=np.int64, endpoint=True)
+    special = np.array([-(1 << 63), (1 << 63) - 1, 0x80000000, 0x7FFFFFFF, -0x80000000,
+                        -0x7FFFFFFF, 0xFFFFFFFF, -1, 0, 1, (1 << 32) | 0x80000000], dtype=np.int64)
+    x[:, :special.size] = special
+    x[:, n - special.size:] = special[::-1]
+    g = wl.uniform_i32(rng, -(1 << 31), 1 << 31, K)
+    g[:4] = [-(1 << 31), (1 << 31) - 1, -1, 1]
+    g[1030:1033] = [-(1 << 31), (1 << 31) - 1, -(1 << 31)]
+    eps = [torch.from_numpy(r.copy()).to(DEV) for r in x]
+    no = ne.n_out(kind, n, K)
+    out = [torch.full((no,), 0x5A5A, dtype=torch.int64, device=DEV) for _ in range(2)]
+    ne.lsb_apply(kind, eps, torch.from_numpy(g).to(DEV), out)
+    torch.cuda.synchronize()
+    for m in range(2):
+        assert np.array_equal(out[m].cpu().numpy(), _conv_mod64(x[m], g, kind)), (kind, m)
