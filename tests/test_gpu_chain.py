@@ -217,3 +217,30 @@ def test_series_many_streams(M, recipe):
         dhat, _ = run_series(c, ops, lost, 4, 4)
         assert np.array_equal(dhat, want), (M, recipe, lost)
         assert np.array_equal(run_whole(c, ops, lost, 4), want), (M, recipe, lost)
+
+
+@pytest.mark.parametrize("stream", [0, 2])
+def test_series_one_computed_stream(stream):
+    """ne_chain_apply with one stream in the mask: rows of one word between
+    a convolution and the permutation after it; the stream's last-stage
+    words equal the oracle's pipeline, the other outputs stay untouched."""
+    M, n = 3, 2001
+    c = wl.uniform_i32(wl.rng(840 + stream), -32, 32, (M, n))
+    ops = wl.chain_series(wl.rng(850 + stream), n, ("conv", "perm", "add"), bits=6, K=21)
+    _, last = oracle.chain_pipeline(c, ops, r=0)
+    l = ne.params(M)[0]
+    dops = device_ops(ops, l, 6)
+    no, _ = ne.chain_check(M, 6, n, dops)
+    cd = [dev32(r) for r in c]
+    eps = [torch.empty(n, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ne.entangle(cd, eps, l)
+    delta = [torch.full((no,), POISON, dtype=torch.int64, device=DEV) for _ in range(M)]
+    ws = torch.empty(ne.chain_workspace_size(M, n, dops) + 256, dtype=torch.uint8, device=DEV)
+    ws = ws[(-ws.data_ptr()) % 256:]
+    ne.chain_apply(eps, dops, delta, mask=1 << stream, workspace=ws)
+    torch.cuda.synchronize()
+    got = np.stack([t.cpu().numpy() for t in delta])
+    assert np.array_equal(got[stream], last[stream])
+    for m in range(M):
+        if m != stream:
+            assert (got[m] == POISON).all()
