@@ -187,7 +187,10 @@ def main():
         single = how == "single" or (args.single_launch and mode == main_mode)
         specs = [ne.GroupSpec(g.op, c_dev[i], k_dev[i], out[i], g.scalar, lost, in_bits)
                  for i, g in enumerate(groups)]
-        if tuner is not None:
+        # the tuner times per-variant launches; the single launch keeps the
+        # planner's strips (in a run whose tuner chose longer strips for many
+        # classes the single launch took 6.64 ms against 5.1 with the planner's)
+        if tuner is not None and not single:
             tuned.update(tuner.tune(specs, mode))
         plan = ne.Plan(specs, mode, conv_steps=args.conv_steps, stream_steps=args.stream_steps,
                        single_launch=single)
