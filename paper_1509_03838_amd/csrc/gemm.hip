@@ -46,27 +46,29 @@ __device__ __forceinline__ void store_nt(int64_t *p, int64_t v)
 }
 
 // Phase 2: slot blockIdx.z's product. The block stages each 64-deep chunk
-// of its 64 A rows and 64 B columns (all digit planes) in LDS once, by direct
+// of its 32 WR A rows and 64 B columns (all digit planes) in LDS once, by direct
 // HBM-to-LDS loads (no staging registers: 154 instead of 206 VGPRs for the
 // split-word variant) into two buffers, the next chunk's loads in flight
 // while this chunk's products run, one barrier per chunk (three buffers,
 // two chunks ahead, measured 5-8% slower: 72 KB of LDS admit 2 blocks per
 // CU, 48 KB admit 3); every wave reads its fragments
 // from there: every digit pair of 16 x 64 A and 64 x 16 B fragments goes
-// into the accumulator of its weight, each wave a 32 x 32 tile (2 x 2
-// matrix-core tiles). The entangled (or plain) int64 products
+// into the accumulator of its weight, each wave a 16 WR x 32 tile (WR x 2
+// matrix-core tiles; WR = 4 reads 20 fragments per 64 products where WR = 2
+// reads 12 per 32, and stages B once per 128 rows). The entangled (or plain) int64 products
 // y = sum_s 256^s acc_s (mod 2^64) go to the slot's output buffer.
 //
 // LDS rows are 64 bytes, unpadded (a direct load fills 1 KB contiguously):
 // row r keeps its 16-byte segment s at position s ^ swz(r), so that the
 // fragment reads of 16 consecutive rows fall on distinct bank groups.
 constexpr int kDigitRow = 64;                            // LDS bytes per staged row
-constexpr int kDigitPlane = kGemmSplitRows * kDigitRow;  // one digit plane of a chunk
+constexpr int kDigitPlane = kGemmSplitRows * kDigitRow;  // 64 rows of one digit plane of a chunk
 constexpr int kDigitBuffers = 2;  // loads run kDigitBuffers - 1 chunks ahead
 
-__host__ __device__ constexpr size_t digits_lds(int la, int lb)
+// LDS of one block: WR / 2 times 64 A rows and 64 B columns per plane.
+__host__ __device__ constexpr size_t digits_lds(int la, int lb, int wr)
 {
-    return (size_t)kDigitBuffers * (la + lb) * kDigitPlane;
+    return (size_t)kDigitBuffers * (la * (wr / 2) + lb) * kDigitPlane;
 }
 
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
@@ -74,54 +76,68 @@ __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 // FS > 0: the data planes hold split words (FS digits of the low field, then
 // FS of the high field, weights 256^a and 2^l 256^a): every pair accumulates
 // into its field's weight and y = lo-sum + 2^l hi-sum.
-template <int LA, int LB, int FS = 0>
-__global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, const DigitJob job,
+template <int LA, int LB, int FS = 0, int WR = 2>
+__global__ __launch_bounds__(fk::kBlock) __attribute__((amdgpu_waves_per_eu(WR / 2)))
+void k_gemm_digits(const GemmSplit w, const DigitJob job,
                                                             int64_t N, int64_t Q, int l)
 {
     static_assert(kGemmSplitRows == 64 && kGemmSplitCols == 64, "block tile");
     static_assert(FS == 0 || 2 * FS == LA, "split words");
+    static_assert(WR == 2 || WR == 4, "wave rows");
     constexpr int SL = FS + LB - 1;
     constexpr int S = FS ? 2 * SL : ((LA + LB - 1) < 8 ? (LA + LB - 1) : 8);
-    constexpr int NP = LA + LB;  // staged planes per chunk: A digits, then B digits
+    constexpr int H = WR / 2;                    // 64-row halves of the block's A rows
+    constexpr int APlane = H * kDigitPlane;      // one A digit plane of a chunk
+    constexpr int Buf = LA * APlane + LB * kDigitPlane;
+    constexpr int NL = LA * H + LB;              // direct loads per wave and chunk
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int fi = lane & 15, fh = lane >> 4;
     const int64_t Pp = w.Pp;
-    const int64_t R0 = (int64_t)blockIdx.y * kGemmSplitRows, C0 = (int64_t)blockIdx.x * kGemmSplitCols;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int64_t R0 = (int64_t)blockIdx.y * (64 * H), C0 = (int64_t)blockIdx.x * kGemmSplitCols;
+    const int wr = (wave >> 1) * 16 * WR, wc = (wave & 1) * 32;
     const size_t aplane = (size_t)w.Np * Pp, bplane = (size_t)w.Qp * Pp;
-    // Staging: wave v fills rows 16 v .. 16 v + 15 of every plane, one 1 KB
-    // direct load per plane; its lane i lands at LDS position i of that
-    // kilobyte (row 16 v + i / 4, position i % 4) and so fetches segment
-    // (i % 4) ^ swz(row) of that row.
+    // Staging: wave v fills rows 64 h + 16 v .. 64 h + 16 v + 15 of every
+    // plane, one 1 KB direct load per plane and half h; its lane i lands at
+    // LDS position i of that kilobyte (row 64 h + 16 v + i / 4, position
+    // i % 4) and so fetches segment (i % 4) ^ swz(row) of that row
+    // (swz(row) does not depend on h).
     const int sr = 16 * wave + (lane >> 2);
     const int sseg = 16 * ((lane & 3) ^ swz(sr));
     const unsigned char *ga = job.a[blockIdx.z] + (R0 + sr) * Pp + sseg;
     const unsigned char *gb = w.b + (C0 + sr) * Pp + sseg;
     typedef __attribute__((address_space(3))) void lds_t;
     auto issue = [&](int64_t c) {
-        unsigned char *buf = smem + (c % kDigitBuffers) * NP * kDigitPlane + wave * 1024;
+        unsigned char *buf = smem + (c % kDigitBuffers) * Buf + wave * 1024;
         const int64_t kc = c * kGemmK;
 #pragma unroll
         for (int a = 0; a < LA; ++a)
-            __builtin_amdgcn_global_load_lds((const void *)(ga + a * aplane + kc),
-                                             (lds_t *)(buf + a * kDigitPlane), 16, 0, 0);
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+                __builtin_amdgcn_global_load_lds(
+                    (const void *)(ga + a * aplane + (int64_t)h * 64 * Pp + kc),
+                    (lds_t *)(buf + a * APlane + h * kDigitPlane), 16, 0, 0);
 #pragma unroll
         for (int b = 0; b < LB; ++b)
             __builtin_amdgcn_global_load_lds((const void *)(gb + b * bplane + kc),
-                                             (lds_t *)(buf + (LA + b) * kDigitPlane), 16, 0, 0);
+                                             (lds_t *)(buf + LA * APlane + b * kDigitPlane), 16, 0,
+                                             0);
     };
     // this lane's fragment offsets within a plane (row * 64 + swizzled segment)
-    int aoff[2], boff[2];
+    int aoff[WR], boff[2];
+#pragma unroll
+    for (int t = 0; t < WR; ++t) {
+        const int ra = wr + 16 * t + fi;
+        aoff[t] = ra * kDigitRow + 16 * (fh ^ swz(ra));
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        const int ra = wr + 16 * t + fi, rb = wc + 16 * t + fi;
-        aoff[t] = ra * kDigitRow + 16 * (fh ^ swz(ra));
+        const int rb = wc + 16 * t + fi;
         boff[t] = rb * kDigitRow + 16 * (fh ^ swz(rb));
     }
-    fk::v4i acc[2][2][S];
+    fk::v4i acc[WR][2][S];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < WR; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -135,7 +151,7 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
         // this wave's loads of chunk c have landed (with D = 2 those of chunk
         // c + 1 may still be in flight: NP of them), then every wave's
         if (D == 2 && c + 1 < nc)
-            __builtin_amdgcn_s_waitcnt(0xF70 | NP);  // vmcnt(NP), other counters untouched
+            __builtin_amdgcn_s_waitcnt(0xF70 | NL);  // vmcnt(NL), other counters untouched
         else
             __builtin_amdgcn_s_waitcnt(0xF70);       // vmcnt(0)
         // Then the block barrier: every wave's chunk c is in LDS, and every
@@ -148,20 +164,21 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         if (c + D < nc) issue(c + D);
-        const unsigned char *cur = smem + (c % kDigitBuffers) * NP * kDigitPlane;
-        fk::v4i af[2][LA], bf[2][LB];
+        const unsigned char *cur = smem + (c % kDigitBuffers) * Buf;
+        fk::v4i af[WR][LA], bf[2][LB];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < WR; ++rt)
 #pragma unroll
             for (int a = 0; a < LA; ++a)
-                af[rt][a] = *reinterpret_cast<const fk::v4i *>(cur + a * kDigitPlane + aoff[rt]);
+                af[rt][a] = *reinterpret_cast<const fk::v4i *>(cur + a * APlane + aoff[rt]);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int b = 0; b < LB; ++b)
-                bf[ct][b] = *reinterpret_cast<const fk::v4i *>(cur + (LA + b) * kDigitPlane + boff[ct]);
+                bf[ct][b] = *reinterpret_cast<const fk::v4i *>(cur + LA * APlane + b * kDigitPlane +
+                                                               boff[ct]);
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < WR; ++rt)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
@@ -176,7 +193,7 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
     }
     int64_t *d = job.d[blockIdx.z];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < WR; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
             const int64_t col = C0 + wc + 16 * ct + fi;
@@ -207,13 +224,13 @@ __global__ __launch_bounds__(fk::kBlock) void k_gemm_digits(const GemmSplit w, c
 using DigitLaunch = void (*)(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N,
                              int64_t Q, int l, hipStream_t s);
 
-template <int LA, int LB, int FS = 0>
-void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q, int l,
-                   hipStream_t s)
+template <int LA, int LB, int FS, int WR>
+void launch_digits_wr(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q,
+                      int l, hipStream_t s)
 {
     void (*k)(const GemmSplit, const DigitJob, int64_t, int64_t, int) =
-        &k_gemm_digits<LA, LB, FS>;
-    constexpr size_t lds = digits_lds(LA, LB);
+        &k_gemm_digits<LA, LB, FS, WR>;
+    constexpr size_t lds = digits_lds(LA, LB, WR);
     if (lds > 64 * 1024) {
         // raised once per variant; should it fail, the launch below fails
         // too and the caller's hipGetLastError reports it
@@ -221,9 +238,21 @@ void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t 
             reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)e;
     }
-    const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / kGemmSplitRows),
+    const dim3 grid((unsigned)(w.Qp / kGemmSplitCols), (unsigned)(w.Np / (32 * WR)),
                     (unsigned)nslots);
     hipLaunchKernelGGL(k, grid, dim3(fk::kBlock), lds, s, w, job, N, Q, l);
+}
+
+// 128-row blocks (WR = 4) where the padded rows divide into them and two
+// blocks still fit one CU's 160 KB of LDS; 64-row blocks otherwise.
+template <int LA, int LB, int FS = 0>
+void launch_digits(const GemmSplit &w, const DigitJob &job, int nslots, int64_t N, int64_t Q, int l,
+                   hipStream_t s)
+{
+    if constexpr (2 * digits_lds(LA, LB, 4) <= 160 * 1024) {
+        if (w.Np % 128 == 0) return launch_digits_wr<LA, LB, FS, 4>(w, job, nslots, N, Q, l, s);
+    }
+    launch_digits_wr<LA, LB, FS, 2>(w, job, nslots, N, Q, l, s);
 }
 
 #define NE_DIGITS_ROW(LA) {&launch_digits<LA, 1>, &launch_digits<LA, 2>, &launch_digits<LA, 3>}

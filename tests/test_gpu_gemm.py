@@ -86,10 +86,35 @@ def test_gemm_every_variant(mode, m_lo, split):
 
 
 @pytest.mark.parametrize("split", SPLIT)
-def test_gemm_vector_loads_and_extremes(split):
+@pytest.mark.parametrize("mode,m_lo", MODES)
+def test_gemm_128_row_blocks(mode, m_lo, split):
+    """Padded rows a multiple of 128, where the two-phase product runs
+    128-row blocks: N = 250 (a ragged last block), every M and digit-count
+    variant, one lost block where the mode recovers it."""
+    ran = 0
+    for M in range(m_lo, 9):
+        for bits in (1, 7, 9, 12, 16):
+            c, g = draw(3000 + 17 * M + bits, M, 250, 131, 70, bits)
+            want = oracle.gemm(c, g)
+            lost = M - 1 if mode in ("entangled", "checksum") else -1
+            try:
+                got, flags = run(c, g, mode, lost, bits, split=split)
+            except ne.NeError as e:
+                assert e.status == -2, (mode, M, bits, e)  # only the range check may refuse
+                continue
+            assert flags == 0
+            assert np.array_equal(got, want), (mode, M, bits)
+            ran += 1
+    assert ran > 0
+
+
+@pytest.mark.parametrize("split", SPLIT)
+@pytest.mark.parametrize("N", [64, 256])
+def test_gemm_vector_loads_and_extremes(split, N):
     """P a multiple of 4 (16-byte row loads), values at both ends of the
-    declared 16-bit range, several chunks of the inner dimension."""
-    M, N, P, Q = 3, 64, 256, 64
+    declared 16-bit range, several chunks of the inner dimension; 64 and
+    256 rows (64- and 128-row blocks of the two-phase product)."""
+    M, P, Q = 3, 256, 64
     c = np.full((M, N, P), -(1 << 15), np.int32)
     c[1] = (1 << 15) - 1
     g = np.full((P, Q), -(1 << 15), np.int32)
